@@ -1,0 +1,234 @@
+"""Python front end of the FP64 CPU oracle (test infrastructure only).
+
+Only `tests/`, `__graft_entry__.smoke()` and the CPU-baseline leg of `bench.py` may
+import this module.  The library under `paper_2303_10672_amd/` never does.
+
+The demand and remaining-life tables are built here with scipy.stats, an
+implementation independent of the GPU library's own table code:
+
+* Scenario A gamma demand (Appendix A, demand equation): P(d) = F(d+1/2) - F(d-1/2)
+  for d < d_max with F(x <= 0) = 0, and P(d_max) = 1 - F(d_max - 1/2).  The paper's
+  "coefficient of variation" is read as sigma/mu, so shape = 1/cv^2, scale = mu*cv^2.
+* Poisson demand (Scenario B description; folded the same way as Scenario C):
+  P(d) = pmf(d) for d < d_max, P(d_max) = 1 - F(d_max - 1).
+* Negative binomial demand (Appendix C, demand equation): n target successes and
+  mean delta, p = n/(n+delta); P(d) = pmf(d) for d < d_max, P(d_max) = 1 - F(d_max-1).
+* Remaining life on arrival (Appendix C, age-on-arrival equations):
+  log(p_k(a)/p_1(a)) = c0_k + c1_k * a for k = 2..m, normalised to sum to one.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+from scipy import stats
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pvi_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_FAMILY = {"A": 0, "B": 1, "C": 2}
+
+
+def build(force=True):
+    """Compile the oracle's C library in place (gcc, OpenMP, plain -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                               _SRC, "-o", _LIB, "-lm"])
+    return _LIB
+
+
+class _OrMdp(ctypes.Structure):
+    _fields_ = [
+        ("family", ctypes.c_int32), ("m", ctypes.c_int32), ("L", ctypes.c_int32),
+        ("n_periods", ctypes.c_int32), ("a_max", ctypes.c_int32 * 2),
+        ("d_max", ctypes.c_int32 * 2), ("pmf0", ctypes.POINTER(ctypes.c_double)),
+        ("pmf1", ctypes.POINTER(ctypes.c_double)), ("rul_p", ctypes.POINTER(ctypes.c_double)),
+        ("rho", ctypes.c_double), ("c_var", ctypes.c_double * 2), ("c_fixed", ctypes.c_double),
+        ("c_hold", ctypes.c_double), ("c_short", ctypes.c_double), ("c_waste", ctypes.c_double),
+        ("c_rev", ctypes.c_double * 2), ("gamma", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        lib.or_num_states.restype = ctypes.c_int64
+        lib.or_num_states.argtypes = [P(_OrMdp)]
+        lib.or_num_actions.restype = ctypes.c_int32
+        lib.or_num_actions.argtypes = [P(_OrMdp)]
+        lib.or_decode.argtypes = [P(_OrMdp), ctypes.c_int64, P(ctypes.c_int32)]
+        lib.or_encode.restype = ctypes.c_int64
+        lib.or_encode.argtypes = [P(_OrMdp), P(ctypes.c_int32)]
+        lib.or_q_states.argtypes = [P(_OrMdp), P(ctypes.c_double), P(ctypes.c_int64),
+                                    ctypes.c_int64, P(ctypes.c_double)]
+        lib.or_sweep.argtypes = [P(_OrMdp), P(ctypes.c_double), P(ctypes.c_double),
+                                 P(ctypes.c_int32), P(ctypes.c_double)]
+        lib.or_solve.argtypes = [P(_OrMdp), ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                 P(ctypes.c_double), P(ctypes.c_int32), P(ctypes.c_double),
+                                 P(ctypes.c_double)]
+        lib.or_transition.argtypes = [P(_OrMdp), ctypes.c_int64, ctypes.c_int32,
+                                      P(ctypes.c_int32), P(ctypes.c_int64), P(ctypes.c_double)]
+        lib.or_arrival_prob.restype = ctypes.c_double
+        lib.or_arrival_prob.argtypes = [P(_OrMdp), ctypes.c_int32, P(ctypes.c_int32)]
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _lp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+# ---------------------------------------------------------------- tables
+
+def demand_pmf(spec, d_max, period=0):
+    """Truncated demand PMF over 0..d_max with the tail folded into d_max."""
+    kind = spec["kind"]
+    d = np.arange(d_max + 1, dtype=np.float64)
+    out = np.zeros(d_max + 1)
+    if kind == "poisson":
+        mu = spec["mean"][period]
+        out[:d_max] = stats.poisson.pmf(d[:d_max], mu)
+        out[d_max] = stats.poisson.sf(d_max - 1, mu)
+    elif kind == "gamma":
+        mu, cv = spec["mean"][period], spec["cv"][period]
+        shape, scale = 1.0 / cv ** 2, mu * cv ** 2
+
+        def F(x):
+            return np.where(x <= 0.0, 0.0, stats.gamma.cdf(np.maximum(x, 0.0), shape,
+                                                            scale=scale))
+        out[:d_max] = F(d[:d_max] + 0.5) - F(d[:d_max] - 0.5)
+        out[d_max] = stats.gamma.sf(d_max - 0.5, shape, scale=scale)
+    elif kind == "negbin":
+        n, mean = spec["n"][period], spec["mean"][period]
+        p = n / (n + mean)
+        out[:d_max] = stats.nbinom.pmf(d[:d_max], n, p)
+        out[d_max] = stats.nbinom.sf(d_max - 1, n, p)
+    elif kind == "none":
+        out[:] = 0.0
+        out[0] = 1.0
+    else:
+        raise ValueError(f"unknown demand kind {kind!r}")
+    return out
+
+
+def life_probabilities(sc):
+    """p_k(a) for a in 0..a_max, k = 1..m (column k-1)."""
+    m, a_max = sc["m"], sc["a_max"][0]
+    c0 = np.asarray(sc["rul_c0"], dtype=np.float64)
+    c1 = np.asarray(sc["rul_c1"], dtype=np.float64)
+    out = np.zeros((a_max + 1, m))
+    for a in range(a_max + 1):
+        logits = np.zeros(m)
+        logits[1:] = c0[1:m] + c1[1:m] * a
+        w = np.exp(logits - logits.max())
+        out[a] = w / w.sum()
+    return out
+
+
+class Oracle:
+    """One scenario, ready for oracle sweeps and solves."""
+
+    def __init__(self, sc):
+        self.sc = sc
+        self.lib = _load()
+        fam = sc["family"]
+        P = int(sc["n_periods"])
+        self.pmf0 = np.ascontiguousarray(np.stack(
+            [demand_pmf(sc["demand"][0], sc["d_max"][0], t) for t in range(P)]))
+        if fam == "B":
+            self.pmf1 = np.ascontiguousarray(demand_pmf(sc["demand"][1], sc["d_max"][1]))
+        else:
+            self.pmf1 = np.zeros(1)
+        if fam == "C":
+            self.rul = np.ascontiguousarray(life_probabilities(sc))
+        else:
+            self.rul = np.zeros(1)
+        c = sc["costs"]
+        self.s = _OrMdp()
+        self.s.family = _FAMILY[fam]
+        self.s.m, self.s.L, self.s.n_periods = sc["m"], sc["L"], P
+        self.s.a_max[0], self.s.a_max[1] = sc["a_max"]
+        self.s.d_max[0], self.s.d_max[1] = sc["d_max"]
+        self.s.pmf0, self.s.pmf1, self.s.rul_p = _dp(self.pmf0), _dp(self.pmf1), _dp(self.rul)
+        self.s.rho = sc["subst_rho"]
+        self.s.c_var[0], self.s.c_var[1] = c["var"]
+        self.s.c_fixed, self.s.c_hold = c["fixed"], c["hold"]
+        self.s.c_short, self.s.c_waste = c["short"], c["waste"]
+        self.s.c_rev[0], self.s.c_rev[1] = c["rev"]
+        self.s.gamma = sc["gamma"]
+        self.ref = ctypes.byref(self.s)
+        self.n_states = int(self.lib.or_num_states(self.ref))
+        self.n_actions = int(self.lib.or_num_actions(self.ref))
+        self.threshold = sc["eps"] * (1.0 - sc["gamma"]) / sc["gamma"]
+
+    # encoding --------------------------------------------------------------
+    def n_digits(self):
+        fam, m, L = self.sc["family"], self.sc["m"], self.sc["L"]
+        return {"A": m + L - 1, "B": 2 * (m - 1), "C": m}[fam]
+
+    def decode(self, idx):
+        out = np.zeros(self.n_digits(), dtype=np.int32)
+        self.lib.or_decode(self.ref, int(idx), _ip(out))
+        return out
+
+    def encode(self, digits):
+        d = np.ascontiguousarray(digits, dtype=np.int32)
+        return int(self.lib.or_encode(self.ref, _ip(d)))
+
+    # transitions -----------------------------------------------------------
+    def transition(self, s, a, omega):
+        om = np.ascontiguousarray(omega, dtype=np.int32)
+        sn = ctypes.c_int64()
+        r = ctypes.c_double()
+        self.lib.or_transition(self.ref, int(s), int(a), _ip(om), ctypes.byref(sn),
+                               ctypes.byref(r))
+        return int(sn.value), float(r.value)
+
+    def arrival_prob(self, a, y_desc):
+        y = np.ascontiguousarray(y_desc, dtype=np.int32)
+        return float(self.lib.or_arrival_prob(self.ref, int(a), _ip(y)))
+
+    # backups ---------------------------------------------------------------
+    def q_states(self, V, states):
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        st = np.ascontiguousarray(states, dtype=np.int64)
+        q = np.zeros((len(st), self.n_actions))
+        self.lib.or_q_states(self.ref, _dp(V), _lp(st), len(st), _dp(q))
+        return q
+
+    def sweep(self, V):
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        Vn = np.zeros(self.n_states)
+        pi = np.zeros(self.n_states, dtype=np.int32)
+        gap = np.zeros(self.n_states)
+        self.lib.or_sweep(self.ref, _dp(V), _dp(Vn), _ip(pi), _dp(gap))
+        return Vn, pi, gap
+
+    def solve(self, thr=None, max_sweeps=100000, fixed_sweeps=0, v0=None):
+        """Value iteration.  Returns dict(V, pi, gap, sweeps, span, dmax, dmin, converged)."""
+        thr = self.threshold if thr is None else float(thr)
+        V = np.zeros(self.n_states) if v0 is None else np.array(v0, dtype=np.float64)
+        pi = np.zeros(self.n_states, dtype=np.int32)
+        gap = np.zeros(self.n_states)
+        st = np.zeros(4)
+        rc = self.lib.or_solve(self.ref, thr, int(max_sweeps), int(fixed_sweeps), _dp(V),
+                               _ip(pi), _dp(gap), _dp(st))
+        return {"V": V, "pi": pi, "gap": gap, "sweeps": int(st[0]), "span": st[1],
+                "dmax": st[2], "dmin": st[3], "converged": rc == 0}

@@ -1,0 +1,441 @@
+/*
+ * Plain FP64 CPU value iteration for perishable-inventory MDPs: the ORACLE.
+ *
+ * Test infrastructure only.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load this file's library.  It shares no source with the
+ * GPU library and implements every step by its plain definition:
+ *
+ *   Q(s,a)   = sum over outcomes w of P(w|s,a) * (r_w + gamma * V(s'_w)),
+ *              where (s'_w, r_w) = T(s, a, w)         (deterministic-transition
+ *              form of the value-iteration update, Methods, "Value iteration")
+ *   V'(s)    = max_a Q(s,a),  pi(s) = lowest argmax_a Q(s,a)
+ *   stop     when max_s(V'-V) - min_s(V'-V) < eps*(1-gamma)/gamma
+ *
+ * Outcomes are enumerated one by one and summed left to right in outcome order;
+ * nothing is factorised, hoisted or reordered.
+ *
+ * Scenario A (Appendix A, FIFO equation and reward equation): state
+ *   [O_{L-1}, ..., O_1, X_m, ..., X_1], outcome = demand d.
+ * Scenario B (Appendix B, FIFO equation and reward equation, substitution as in
+ *   the Scenario B problem description): L = 0 here, state
+ *   [A_{m-1}..A_1, B_{m-1}..B_1], outcome = (dA, dB, k) where k ~ Binomial(uA, rho)
+ *   of product 0's unmet demand uA accept product 1, served from product 1's stock
+ *   left after its own demand, oldest first.
+ * Scenario C (Appendix C, state-transition and reward equations): state
+ *   [tau, X_{m-1}, ..., X_1], outcome = (d, y) with y a multinomial split of the
+ *   order over remaining lives m..1 and stock of each life capped at a_max.
+ *
+ * Demand PMFs (with their folded tails) and remaining-life probabilities are
+ * inputs; oracle.py builds them from the scenario parameters.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAXD 16 /* max digits in a state */
+
+typedef struct {
+    int32_t family;      /* 0 = A, 1 = B, 2 = C */
+    int32_t m, L, n_periods;
+    int32_t a_max[2], d_max[2];
+    const double* pmf0;  /* product 0 demand PMF, [n_periods][d_max[0]+1] */
+    const double* pmf1;  /* product 1 demand PMF (B), [d_max[1]+1] */
+    const double* rul_p; /* C: [a_max+1][m]; entry (a, k-1) = p_k(a), k = remaining life */
+    double rho;
+    double c_var[2], c_fixed, c_hold, c_short, c_waste, c_rev[2];
+    double gamma;
+} or_mdp;
+
+static double pos(double x) { return x > 0.0 ? x : 0.0; }
+static int ipos(int x) { return x > 0 ? x : 0; }
+
+/* ---------------------------------------------------------------- encoding */
+
+static int n_digits(const or_mdp* p) {
+    if (p->family == 0) return p->m + p->L - 1;
+    if (p->family == 1) return 2 * (p->m - 1);
+    return p->m; /* tau + (m-1) stock digits */
+}
+
+static void radices(const or_mdp* p, int* rad) {
+    int n = n_digits(p);
+    if (p->family == 0) {
+        for (int i = 0; i < n; ++i) rad[i] = p->a_max[0] + 1;
+    } else if (p->family == 1) {
+        for (int i = 0; i < p->m - 1; ++i) rad[i] = p->a_max[0] + 1;
+        for (int i = 0; i < p->m - 1; ++i) rad[p->m - 1 + i] = p->a_max[1] + 1;
+    } else {
+        rad[0] = p->n_periods;
+        for (int i = 1; i < n; ++i) rad[i] = p->a_max[0] + 1;
+    }
+}
+
+int64_t or_num_states(const or_mdp* p) {
+    int rad[OR_MAXD];
+    radices(p, rad);
+    int64_t n = 1;
+    for (int i = 0; i < n_digits(p); ++i) n *= rad[i];
+    return n;
+}
+
+int32_t or_num_actions(const or_mdp* p) {
+    if (p->family == 1) return (p->a_max[0] + 1) * (p->a_max[1] + 1);
+    return p->a_max[0] + 1;
+}
+
+/* digits in written order, most significant first */
+void or_decode(const or_mdp* p, int64_t idx, int32_t* dig) {
+    int rad[OR_MAXD];
+    radices(p, rad);
+    for (int i = n_digits(p) - 1; i >= 0; --i) {
+        dig[i] = (int32_t)(idx % rad[i]);
+        idx /= rad[i];
+    }
+}
+
+int64_t or_encode(const or_mdp* p, const int32_t* dig) {
+    int rad[OR_MAXD];
+    radices(p, rad);
+    int64_t idx = 0;
+    for (int i = 0; i < n_digits(p); ++i) idx = idx * rad[i] + dig[i];
+    return idx;
+}
+
+/* -------------------------------------------------------------- scenario A */
+/* One transition of Scenario A.  dig = [O_{L-1}..O_1, X_m..X_1]. */
+static void trans_a(const or_mdp* p, const int32_t* dig, int a, int d, int32_t* nd,
+                    double* r) {
+    int m = p->m, L = p->L;
+    int X[OR_MAXD + 1]; /* X[1..m] */
+    int O[OR_MAXD + 1]; /* O[1..L-1] */
+    for (int i = 1; i <= L - 1; ++i) O[i] = dig[(L - 1) - i];
+    for (int j = 1; j <= m; ++j) X[j] = dig[(L - 1) + (m - j)];
+    int Xtot = 0;
+    for (int j = 1; j <= m; ++j) Xtot += X[j];
+    int W = ipos(X[1] - d); /* units expiring at the end of the day */
+    int Xn[OR_MAXD + 1], On[OR_MAXD + 1];
+    int cum = 0;
+    for (int j = 1; j <= m - 1; ++j) {
+        cum += X[j];
+        Xn[j] = ipos(X[j + 1] - ipos(d - cum));
+    }
+    Xn[m] = (L >= 2) ? O[1] : a;
+    if (L >= 2) {
+        On[L - 1] = a;
+        for (int i = 1; i <= L - 2; ++i) On[i] = O[i + 1];
+    }
+    for (int i = 1; i <= L - 1; ++i) nd[(L - 1) - i] = On[i];
+    for (int j = 1; j <= m; ++j) nd[(L - 1) + (m - j)] = Xn[j];
+    *r = -p->c_var[0] * a - p->c_hold * pos((double)(Xtot - d - W)) -
+         p->c_short * pos((double)(d - Xtot)) - p->c_waste * W;
+}
+
+static double q_a(const or_mdp* p, const double* V, const int32_t* dig, int a) {
+    int32_t nd[OR_MAXD];
+    double q = 0.0;
+    for (int d = 0; d <= p->d_max[0]; ++d) {
+        double pr = p->pmf0[d];
+        if (pr == 0.0) continue;
+        double r;
+        trans_a(p, dig, a, d, nd, &r);
+        q += pr * (r + p->gamma * V[or_encode(p, nd)]);
+    }
+    return q;
+}
+
+/* -------------------------------------------------------------- scenario B */
+/* FIFO issue of demand e from stock o[1..m] (oldest first); returns units issued,
+ * writes leftovers into left[1..m]. */
+static int fifo_issue(const int* o, int m, int e, int* left) {
+    int issued = 0;
+    for (int j = 1; j <= m; ++j) {
+        int take = e < o[j] ? e : o[j];
+        left[j] = o[j] - take;
+        e -= take;
+        issued += take;
+    }
+    return issued;
+}
+
+static double binom_pmf(int k, int n, double rho) {
+    if (k < 0 || k > n) return 0.0;
+    /* n choose k by the product formula, then rho^k (1-rho)^(n-k) */
+    double c = 1.0;
+    for (int i = 1; i <= k; ++i) c = c * (double)(n - k + i) / (double)i;
+    return c * pow(rho, (double)k) * pow(1.0 - rho, (double)(n - k));
+}
+
+/* dig = [A_{m-1}..A_1, B_{m-1}..B_1]; action (aA, aB); outcome (dA, dB, k). */
+static void trans_b(const or_mdp* p, const int32_t* dig, int aA, int aB, int dA, int dB,
+                    int k, int32_t* nd, double* r) {
+    int m = p->m;
+    int oA[OR_MAXD + 1], oB[OR_MAXD + 1], lA[OR_MAXD + 1], lB[OR_MAXD + 1];
+    for (int j = 1; j <= m - 1; ++j) {
+        oA[j] = dig[(m - 1) - j];
+        oB[j] = dig[(m - 1) + (m - 1) - j];
+    }
+    oA[m] = aA; /* L = 0: today's order is on hand, with m days of life */
+    oB[m] = aB;
+    int hA = fifo_issue(oA, m, dA, lA);
+    int uA = dA - hA;
+    (void)uA;
+    int lB1[OR_MAXD + 1];
+    int hB_own = fifo_issue(oB, m, dB, lB1);
+    int hB_sub = fifo_issue(lB1, m, k, lB); /* substitutes take what is left, FIFO */
+    /* next state: units of life j+1 that were not issued now have life j;
+     * life-1 leftovers expire */
+    for (int j = 1; j <= m - 1; ++j) {
+        nd[(m - 1) - j] = lA[j + 1];
+        nd[(m - 1) + (m - 1) - j] = lB[j + 1];
+    }
+    *r = -(p->c_var[0] * aA + p->c_var[1] * aB) + p->c_rev[0] * hA +
+         p->c_rev[1] * (hB_own + hB_sub);
+}
+
+static double q_b(const or_mdp* p, const double* V, const int32_t* dig, int aA, int aB) {
+    int m = p->m;
+    int32_t nd[OR_MAXD];
+    int stockA = aA;
+    for (int j = 0; j < m - 1; ++j) stockA += dig[j];
+    double q = 0.0;
+    for (int dA = 0; dA <= p->d_max[0]; ++dA) {
+        double pA = p->pmf0[dA];
+        if (pA == 0.0) continue;
+        int uA = ipos(dA - stockA);
+        for (int dB = 0; dB <= p->d_max[1]; ++dB) {
+            double pB = p->pmf1[dB];
+            if (pB == 0.0) continue;
+            for (int k = 0; k <= uA; ++k) {
+                double pk = binom_pmf(k, uA, p->rho);
+                if (pk == 0.0) continue;
+                double r;
+                trans_b(p, dig, aA, aB, dA, dB, k, nd, &r);
+                q += pA * pB * pk * (r + p->gamma * V[or_encode(p, nd)]);
+            }
+        }
+    }
+    return q;
+}
+
+/* -------------------------------------------------------------- scenario C */
+/* dig = [tau, X_{m-1}..X_1]; y[1..m] arrivals by remaining life; demand d. */
+static void trans_c(const or_mdp* p, const int32_t* dig, int a, const int* y, int d,
+                    int32_t* nd, double* r) {
+    int m = p->m, cap = p->a_max[0];
+    int z[OR_MAXD + 1];
+    for (int j = 1; j <= m - 1; ++j) {
+        int x = dig[m - j];
+        z[j] = x + y[j] < cap ? x + y[j] : cap; /* excess rejected at delivery */
+    }
+    z[m] = y[m];
+    int tot = 0;
+    for (int j = 1; j <= m; ++j) tot += z[j];
+    int cum = 0;
+    int Xn[OR_MAXD + 1];
+    for (int j = 1; j <= m - 1; ++j) {
+        cum += z[j];
+        Xn[j] = ipos(z[j + 1] - ipos(d - cum));
+    }
+    nd[0] = (dig[0] + 1) % p->n_periods;
+    for (int j = 1; j <= m - 1; ++j) nd[m - j] = Xn[j];
+    *r = -(a > 0 ? p->c_fixed : 0.0) - p->c_hold * pos((double)(tot - d)) -
+         p->c_short * pos((double)(d - tot)) - p->c_waste * pos((double)(z[1] - d));
+}
+
+/* multinomial probability of y[1..m] given a and the life probabilities p_k(a) */
+static double multinom_pmf(const or_mdp* p, int a, const int* y) {
+    int m = p->m;
+    const double* pk = p->rul_p + (size_t)a * m;
+    double c = 1.0;
+    int placed = 0;
+    for (int k = 1; k <= m; ++k) {
+        /* choose y[k] of the remaining (a - placed) */
+        for (int i = 1; i <= y[k]; ++i) c = c * (double)(placed + i) / (double)i;
+        placed += y[k];
+        c *= pow(pk[k - 1], (double)y[k]);
+    }
+    return c;
+}
+
+typedef struct {
+    const or_mdp* p;
+    const double* V;
+    const int32_t* dig;
+    int a;
+    const double* pd;
+    double q;
+} c_acc;
+
+static void c_enum(c_acc* A, int* y, int k, int left) {
+    const or_mdp* p = A->p;
+    int m = p->m;
+    if (k == 1) {
+        y[1] = left;
+        double py = multinom_pmf(p, A->a, y);
+        if (py == 0.0) return;
+        int32_t nd[OR_MAXD];
+        for (int d = 0; d <= p->d_max[0]; ++d) {
+            double pr = A->pd[d];
+            if (pr == 0.0) continue;
+            double r;
+            trans_c(p, A->dig, A->a, y, d, nd, &r);
+            A->q += py * pr * (r + p->gamma * A->V[or_encode(p, nd)]);
+        }
+        return;
+    }
+    for (int v = left; v >= 0; --v) { /* y_m first, largest first */
+        y[k] = v;
+        c_enum(A, y, k - 1, left - v);
+    }
+    (void)m;
+}
+
+static double q_c(const or_mdp* p, const double* V, const int32_t* dig, int a) {
+    c_acc A;
+    A.p = p;
+    A.V = V;
+    A.dig = dig;
+    A.a = a;
+    A.pd = p->pmf0 + (size_t)dig[0] * (p->d_max[0] + 1);
+    A.q = 0.0;
+    int y[OR_MAXD + 1];
+    memset(y, 0, sizeof y);
+    c_enum(&A, y, p->m, a);
+    return A.q;
+}
+
+/* ------------------------------------------------------------------ backup */
+
+static double q_sa(const or_mdp* p, const double* V, const int32_t* dig, int a) {
+    if (p->family == 0) return q_a(p, V, dig, a);
+    if (p->family == 1) {
+        int nb = p->a_max[1] + 1;
+        return q_b(p, V, dig, a / nb, a % nb);
+    }
+    return q_c(p, V, dig, a);
+}
+
+/* Q(s, .) for a list of states: q_out[i*n_actions + a]. */
+int or_q_states(const or_mdp* p, const double* V, const int64_t* states, int64_t n,
+                double* q_out) {
+    int na = or_num_actions(p);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t dig[OR_MAXD];
+        or_decode(p, states[i], dig);
+        for (int a = 0; a < na; ++a) q_out[i * na + a] = q_sa(p, V, dig, a);
+    }
+    return 0;
+}
+
+/* max, lowest argmax and best-minus-second gap of one state's Q row */
+static void best_of(const double* q, int na, double* best, int32_t* arg, double* gap) {
+    double b = q[0], s = -INFINITY;
+    int32_t ia = 0;
+    for (int a = 1; a < na; ++a) {
+        if (q[a] > b) {
+            s = b;
+            b = q[a];
+            ia = a;
+        } else if (q[a] > s) {
+            s = q[a];
+        }
+    }
+    *best = b;
+    *arg = ia;
+    *gap = b - s;
+}
+
+/* One synchronous sweep V -> Vnew (pi, gap optional). */
+int or_sweep(const or_mdp* p, const double* V, double* Vnew, int32_t* pi, double* gap) {
+    int64_t ns = or_num_states(p);
+    int na = or_num_actions(p);
+#pragma omp parallel
+    {
+        double* q = (double*)malloc(sizeof(double) * na);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t s = 0; s < ns; ++s) {
+            int32_t dig[OR_MAXD];
+            or_decode(p, s, dig);
+            for (int a = 0; a < na; ++a) q[a] = q_sa(p, V, dig, a);
+            double b, g;
+            int32_t ia;
+            best_of(q, na, &b, &ia, &g);
+            Vnew[s] = b;
+            if (pi) pi[s] = ia;
+            if (gap) gap[s] = g;
+        }
+        free(q);
+    }
+    return 0;
+}
+
+/*
+ * Value iteration from V (in: V0, out: V_ret = the last V_new).  Stops when the
+ * span of V_new - V drops below thr, or after fixed_sweeps sweeps when that is
+ * positive (no early stop), or at max_sweeps (returns 1).  The policy comes from
+ * one more backup of V_ret.  out_stats = {sweeps, final span, max dV, min dV}.
+ */
+int or_solve(const or_mdp* p, double thr, int32_t max_sweeps, int32_t fixed_sweeps,
+             double* V, int32_t* pi, double* gap, double* out_stats) {
+    int64_t ns = or_num_states(p);
+    double* Vn = (double*)malloc(sizeof(double) * ns);
+    double* Vx = (double*)malloc(sizeof(double) * ns);
+    int sweeps = 0, rc = 1;
+    double span = INFINITY, dmax = 0.0, dmin = 0.0;
+    int limit = fixed_sweeps > 0 ? fixed_sweeps : max_sweeps;
+    while (sweeps < limit) {
+        or_sweep(p, V, Vn, NULL, NULL);
+        ++sweeps;
+        dmax = -INFINITY;
+        dmin = INFINITY;
+        for (int64_t s = 0; s < ns; ++s) {
+            double dv = Vn[s] - V[s];
+            if (dv > dmax) dmax = dv;
+            if (dv < dmin) dmin = dv;
+        }
+        span = dmax - dmin;
+        memcpy(V, Vn, sizeof(double) * ns);
+        if (fixed_sweeps <= 0 && span < thr) {
+            rc = 0;
+            break;
+        }
+    }
+    if (fixed_sweeps > 0) rc = 0;
+    or_sweep(p, V, Vx, pi, gap);
+    out_stats[0] = sweeps;
+    out_stats[1] = span;
+    out_stats[2] = dmax;
+    out_stats[3] = dmin;
+    free(Vn);
+    free(Vx);
+    return rc;
+}
+
+/* Single transitions, for tests of T against an independent unit-level model.
+ * omega: A {d}; B {dA, dB, k}; C {d, y_m, ..., y_1}. */
+int or_transition(const or_mdp* p, int64_t s, int32_t a, const int32_t* omega,
+                  int64_t* s_next, double* r) {
+    int32_t dig[OR_MAXD], nd[OR_MAXD];
+    or_decode(p, s, dig);
+    if (p->family == 0) {
+        trans_a(p, dig, a, omega[0], nd, r);
+    } else if (p->family == 1) {
+        int nb = p->a_max[1] + 1;
+        trans_b(p, dig, a / nb, a % nb, omega[0], omega[1], omega[2], nd, r);
+    } else {
+        int y[OR_MAXD + 1];
+        for (int k = 1; k <= p->m; ++k) y[k] = omega[1 + (p->m - k)];
+        trans_c(p, dig, a, y, omega[0], nd, r);
+    }
+    *s_next = or_encode(p, nd);
+    return 0;
+}
+
+/* Multinomial probability of an arrival profile (y_m..y_1) for order a (C). */
+double or_arrival_prob(const or_mdp* p, int32_t a, const int32_t* y_desc) {
+    int y[OR_MAXD + 1];
+    for (int k = 1; k <= p->m; ++k) y[k] = y_desc[p->m - k];
+    return multinom_pmf(p, a, y);
+}

@@ -1,0 +1,171 @@
+"""Scenario parameter dictionaries for perishable-inventory value iteration.
+
+Every dictionary has the same keys, whatever the family:
+
+  family      "A" (lead time, FIFO), "B" (two products, one-way substitution),
+              "C" (weekday demand, random remaining life on arrival)
+  m           maximum useful life
+  L           lead time (A: >= 1; B and C: 0, the order arrives before demand)
+  n_periods   demand periods (7 weekdays for C, else 1)
+  a_max       [product 0, product 1] maximum order quantity (product 1 only for B)
+  d_max       [product 0, product 1] demand truncation point (tail folded into d_max)
+  demand      per product: {"kind": "poisson", "mean": [...]},
+              {"kind": "gamma", "mean": [...], "cv": [...]} or
+              {"kind": "negbin", "mean": [...], "n": [...]}; one entry per period
+  rul_c0, rul_c1  C only: log(p_k(a)/p_1(a)) = c0[k] + c1[k]*a for k = 2..m
+              (lists of length m, entry 0 unused and zero)
+  subst_rho   B only: probability that a customer of product 0 left unserved
+              accepts product 1 instead
+  costs       var [2], fixed, hold, short, waste, rev [2]
+  gamma       discount factor
+  eps         tolerance; the span stopping threshold is eps*(1-gamma)/gamma
+
+The only randomness is `numpy.random.default_rng([config_id, request_id])`.
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+__all__ = [
+    "scenario_a", "scenario_b", "scenario_c", "config0", "config1", "config2",
+    "config3", "config_by_index", "serving_mix", "random_values", "sample_indices",
+]
+
+
+def _costs(var=(0.0, 0.0), fixed=0.0, hold=0.0, short=0.0, waste=0.0, rev=(0.0, 0.0)):
+    return {"var": [float(var[0]), float(var[1])], "fixed": float(fixed),
+            "hold": float(hold), "short": float(short), "waste": float(waste),
+            "rev": [float(rev[0]), float(rev[1])]}
+
+
+def scenario_a(m=2, L=1, a_max=10, d_max=20, demand=None, costs=None, gamma=0.99,
+               eps=1e-4):
+    """Scenario A (single product, lead time L >= 1, FIFO issuing)."""
+    if demand is None:
+        demand = {"kind": "poisson", "mean": [4.0]}
+    if costs is None:
+        costs = _costs(var=(3.0, 0.0), hold=1.0, short=5.0, waste=7.0)
+    return {"family": "A", "m": int(m), "L": int(L), "n_periods": 1,
+            "a_max": [int(a_max), 0], "d_max": [int(d_max), 0],
+            "demand": [copy.deepcopy(demand), {"kind": "none", "mean": [0.0]}],
+            "rul_c0": [0.0] * int(m), "rul_c1": [0.0] * int(m), "subst_rho": 0.0,
+            "costs": copy.deepcopy(costs), "gamma": float(gamma), "eps": float(eps)}
+
+
+def scenario_b(m=3, a_max=(14, 14), d_max=(20, 20), means=(5.0, 4.0), rho=0.5,
+               costs=None, gamma=0.99, eps=1e-4):
+    """Scenario B (two products, L=0, product 0's unmet demand may take product 1)."""
+    if costs is None:
+        costs = _costs(var=(0.5, 0.5), rev=(1.0, 1.0))
+    return {"family": "B", "m": int(m), "L": 0, "n_periods": 1,
+            "a_max": [int(a_max[0]), int(a_max[1])],
+            "d_max": [int(d_max[0]), int(d_max[1])],
+            "demand": [{"kind": "poisson", "mean": [float(means[0])]},
+                       {"kind": "poisson", "mean": [float(means[1])]}],
+            "rul_c0": [0.0] * int(m), "rul_c1": [0.0] * int(m), "subst_rho": float(rho),
+            "costs": copy.deepcopy(costs), "gamma": float(gamma), "eps": float(eps)}
+
+
+def scenario_c(m=3, a_max=4, d_max=8, n=None, means=None, c0=None, c1=None,
+               costs=None, gamma=0.99, eps=1e-4, n_periods=7):
+    """Scenario C (weekday negative-binomial demand, random remaining life, L=0)."""
+    if n is None:
+        n = [5.0] * n_periods
+    if means is None:
+        means = [4.0] * n_periods
+    if c0 is None:
+        c0 = [0.0] + [1.0] * (m - 1)
+    if c1 is None:
+        c1 = [0.0] * m
+    if costs is None:
+        costs = _costs(fixed=10.0, hold=1.0, short=20.0, waste=5.0)
+    return {"family": "C", "m": int(m), "L": 0, "n_periods": int(n_periods),
+            "a_max": [int(a_max), 0], "d_max": [int(d_max), 0],
+            "demand": [{"kind": "negbin", "mean": [float(x) for x in means],
+                        "n": [float(x) for x in n]}, {"kind": "none", "mean": [0.0]}],
+            "rul_c0": [float(x) for x in c0], "rul_c1": [float(x) for x in c1],
+            "subst_rho": 0.0, "costs": copy.deepcopy(costs), "gamma": float(gamma),
+            "eps": float(eps)}
+
+
+def _jitter(rng, x, frac=0.2):
+    return float(x) * float(1.0 + rng.uniform(-frac, frac))
+
+
+def config0():
+    """m=2, L=1, order <= 10, Poisson(4) folded at 20, costs 3/5/7/1, gamma 0.99."""
+    return scenario_a(m=2, L=1, a_max=10, d_max=20,
+                      demand={"kind": "poisson", "mean": [4.0]},
+                      costs=_costs(var=(3.0, 0.0), hold=1.0, short=5.0, waste=7.0))
+
+
+def config1(request_id=0):
+    """m=4, L=2, order <= 20, gamma demand (mean 4, CV 1.5) folded at 60, costs x(1+-20%)."""
+    rng = np.random.default_rng([1, request_id])
+    costs = _costs(var=(_jitter(rng, 3.0), 0.0), short=_jitter(rng, 5.0),
+                   waste=_jitter(rng, 7.0), hold=_jitter(rng, 1.0))
+    return scenario_a(m=4, L=2, a_max=20, d_max=60,
+                      demand={"kind": "gamma", "mean": [4.0], "cv": [1.5]}, costs=costs)
+
+
+def config2():
+    """Two products, m=3, L=0, orders <= 14 each, Poisson(5)/(4) folded at 20, rho 0.5."""
+    return scenario_b(m=3, a_max=(14, 14), d_max=(20, 20), means=(5.0, 4.0), rho=0.5)
+
+
+def config3(request_id=0, a_max=20):
+    """Weekday NB demand (n=5, mean ~ U(5,10)) folded at 40, m=5, L=0, RUL logits ~ U(0,3)."""
+    rng = np.random.default_rng([3, request_id])
+    means = [float(x) for x in rng.uniform(5.0, 10.0, size=7)]
+    c0 = [0.0] + [float(x) for x in rng.uniform(0.0, 3.0, size=4)]
+    return scenario_c(m=5, a_max=a_max, d_max=40, n=[5.0] * 7, means=means, c0=c0,
+                      c1=[0.0] * 5, gamma=0.99)
+
+
+def config_by_index(i):
+    return [config0, config1, config2, config3][i]()
+
+
+def serving_mix(n_requests=2000, rate_per_s=100.0, seed=4, large_fraction=0.05,
+                c_fraction=0.25):
+    """Seeded request stream: (arrival_time_s, scenario) pairs.
+
+    70% scenario-A instances of the small family (m in 2..3, costs x(1+-20%)),
+    25% scenario-C instances with order cap in 10..20, 5% large scenario-A instances
+    (the m=4, L=2, order <= 20 size).  Inter-arrival times are exponential.
+    """
+    rng = np.random.default_rng([4, seed])
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += float(rng.exponential(1.0 / rate_per_s))
+        u = float(rng.uniform())
+        if u < large_fraction:
+            sc = config1(request_id=1000 + i)
+        elif u < large_fraction + c_fraction:
+            sc = config3(request_id=1000 + i, a_max=int(rng.integers(10, 21)))
+        else:
+            m = int(rng.integers(2, 4))
+            costs = _costs(var=(_jitter(rng, 3.0), 0.0), short=_jitter(rng, 5.0),
+                           waste=_jitter(rng, 7.0), hold=_jitter(rng, 1.0))
+            sc = scenario_a(m=m, L=1, a_max=10, d_max=20,
+                            demand={"kind": "poisson", "mean": [4.0]}, costs=costs)
+        out.append((t, sc))
+    return out
+
+
+def random_values(n, seed=0, scale=100.0, offset=-1000.0):
+    """A seeded FP64 value-function guess of length n (for one-sweep parity)."""
+    rng = np.random.default_rng([99, seed])
+    return offset + scale * rng.standard_normal(int(n))
+
+
+def sample_indices(n, k, seed=0):
+    """k distinct sorted indices in [0, n), always including 0 and n-1."""
+    rng = np.random.default_rng([98, seed])
+    k = min(int(k), int(n))
+    idx = set(rng.choice(int(n), size=max(k - 2, 0), replace=False).tolist())
+    idx.update({0, int(n) - 1})
+    return np.array(sorted(idx), dtype=np.int64)
