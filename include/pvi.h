@@ -1,0 +1,220 @@
+/*
+ * pvi.h - value iteration for perishable-inventory MDPs on one MI355X (gfx950).
+ *
+ * The library computes, for every state s of a perishable-inventory MDP, the
+ * synchronous Bellman backup in its deterministic-transition form
+ *
+ *     V_{i+1}(s) = max_a  sum_w P(w|s,a) [ r_w + gamma V_i(s'_w) ],
+ *     (s'_w, r_w) = T(s, a, w)
+ *
+ * (Methods, "Value iteration": the deterministic-transition update and policy
+ * equations), stops when span(V_{i+1} - V_i) = max - min < eps (1-gamma)/gamma
+ * (the span rule of Appendix B, with the discount folded into the threshold),
+ * and extracts the greedy policy with one more backup of the returned V (the
+ * extraction step of the vmap value-iteration algorithm).  Ties go to the
+ * lowest action index.
+ *
+ * Three scenario families are supported:
+ *   PVI_FAMILY_LEADTIME    Scenario A (Appendix A): one product, lead time L >= 1,
+ *                          FIFO issuing.  State digits, most significant first:
+ *                          [O_{L-1}, ..., O_1, X_m, ..., X_1], radix a_max+1.
+ *                          Outcome: demand d in 0..d_max.
+ *   PVI_FAMILY_SUBST2      Scenario B (Appendix B): two products, L = 0 (today's
+ *                          order is on hand before demand), FIFO; unmet demand of
+ *                          product 0 accepts product 1 with probability subst_rho
+ *                          per customer (binomial), served from product 1 stock
+ *                          left after its own demand.  State digits
+ *                          [A_{m-1}..A_1, B_{m-1}..B_1]; action a = a0*(a_max[1]+1)+a1.
+ *                          Reward -c_var.a + c_rev.issued.
+ *   PVI_FAMILY_RUL_WEEKDAY Scenario C (Appendix C): weekday demand, L = 0, remaining
+ *                          life on arrival ~ Multinomial(a; p_m(a)..p_1(a)), stock
+ *                          of each life capped at a_max (excess refused at delivery).
+ *                          State digits [tau, X_{m-1}, ..., X_1].
+ *
+ * Conventions
+ *  - Every function returns pvi_status and never throws across the ABI.  On error
+ *    a thread-local message is available from pvi_last_error(); outputs are left
+ *    untouched unless stated.
+ *  - Host pointers are caller-owned.  Descriptors, tables and v0 are copied.
+ *  - A pvi_mdp owns its device buffers (tables, V, policy), which stay resident in
+ *    HBM from the first solve until mdp_destroy.
+ *  - Distinct pvi_mdp handles may be used from different threads.  One handle must
+ *    not be used by two threads at once.  Server calls are thread-safe.
+ *  - There is no CPU fallback: without a usable gfx950 device, solves return
+ *    PVI_E_DEVICE.
+ */
+#ifndef PVI_H
+#define PVI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PVI_OK = 0,
+    PVI_E_INVALID = 1,       /* bad argument or descriptor */
+    PVI_E_NOMEM = 2,         /* host or device allocation failed */
+    PVI_E_DEVICE = 3,        /* HIP runtime error or no device */
+    PVI_E_NOT_CONVERGED = 4, /* max_sweeps reached; V and policy still readable */
+    PVI_E_NOT_READY = 5,     /* ticket still running, or no solve yet */
+    PVI_E_CANCELLED = 6,     /* request cancelled or server shut down */
+    PVI_E_BUSY = 7           /* request does not fit the server's HBM budget */
+} pvi_status;
+
+typedef enum {
+    PVI_FAMILY_LEADTIME = 0,
+    PVI_FAMILY_SUBST2 = 1,
+    PVI_FAMILY_RUL_WEEKDAY = 2
+} pvi_family;
+
+typedef enum {
+    PVI_DEMAND_NONE = 0,    /* demand is always 0 */
+    PVI_DEMAND_POISSON = 1, /* mean */
+    PVI_DEMAND_GAMMA = 2,   /* mean, shape = coefficient of variation sigma/mu;
+                               P(d) = F(d+1/2) - F(d-1/2), F(x<=0) = 0 (Appendix A) */
+    PVI_DEMAND_NEGBIN = 3,  /* mean, shape = n target successes, p = n/(n+mean)
+                               (Appendix C, demand equation) */
+    PVI_DEMAND_TABLE = 4    /* explicit PMF rows in demand_table */
+} pvi_demand_kind;
+
+typedef enum {
+    PVI_FP64 = 0,      /* FP64 storage and FP64 accumulation in every sweep */
+    PVI_FP32 = 1,      /* FP32 centred storage (V = c + v, c FP64 per instance),
+                          compensated (Kahan) FP32 accumulation over outcomes;
+                          FP64 span check, then FP64 polish sweeps to the threshold */
+    PVI_FP32_WIDE = 2  /* FP32 centred storage, FP64 accumulation; FP64 check and
+                          polish as PVI_FP32 */
+} pvi_precision;
+
+#define PVI_MAX_PERIODS 7
+#define PVI_MAX_LIFE 8
+
+/* Parametric MDP descriptor.  Parameters not used by a family are ignored.
+ * Demand PMFs are truncated at d_max with the upper tail folded into d_max:
+ * P(d_max) = P(D >= d_max) (Poisson, negative binomial) or 1 - F(d_max - 1/2)
+ * (gamma). */
+typedef struct pvi_mdp_desc {
+    uint32_t struct_size;      /* sizeof(pvi_mdp_desc) */
+    int32_t family;            /* pvi_family */
+    int32_t m;                 /* maximum useful life, 1..PVI_MAX_LIFE */
+    int32_t lead_time;         /* A: >= 1; B and C: 0 */
+    int32_t n_periods;         /* C: 1..7 demand periods (weekdays); else 1 */
+    int32_t a_max[2];          /* max order per product; B uses both */
+    int32_t d_max[2];          /* demand truncation per product */
+    int32_t demand_kind[2];    /* pvi_demand_kind per product */
+    double demand_mean[2][PVI_MAX_PERIODS];
+    double demand_shape[2][PVI_MAX_PERIODS];
+    const double* demand_table[2]; /* TABLE: [n_periods][d_max+1], rows sum to 1 */
+    double rul_c0[PVI_MAX_LIFE];   /* C: log(p_k(a)/p_1(a)) = c0[k-1] + c1[k-1] a, k>=2 */
+    double rul_c1[PVI_MAX_LIFE];
+    double subst_rho;          /* B: per-customer substitution probability */
+    double c_var[2];           /* per-unit order cost */
+    double c_fixed;            /* C: fixed cost when a > 0 */
+    double c_hold, c_short, c_waste;
+    double c_rev[2];           /* B: revenue per unit issued */
+    double gamma;              /* discount factor, 0 < gamma < 1 */
+} pvi_mdp_desc;
+
+typedef struct pvi_solve_opts {
+    uint32_t struct_size;      /* sizeof(pvi_solve_opts) */
+    int32_t precision;         /* pvi_precision */
+    double eps;                /* stop when span(V_new - V) < eps (1-gamma)/gamma */
+    int32_t max_sweeps;        /* cap on sweeps (> 0) */
+    int32_t fixed_sweeps;      /* > 0: run exactly this many sweeps, no early stop */
+    const double* v0;          /* optional host [N_S] initial values; NULL = zeros */
+    void* stream;              /* optional hipStream_t; NULL = the handle's own */
+    int32_t check_every;       /* sweeps launched between host checks; 0 = default */
+    int32_t time_kernels;      /* 1: time every backup launch with HIP events */
+} pvi_solve_opts;
+
+typedef struct pvi_result {
+    int32_t status;            /* pvi_status of the solve */
+    int32_t sweeps_fp32;       /* sweeps run with FP32 storage */
+    int32_t sweeps_fp64;       /* sweeps run in FP64 (including polish) */
+    int32_t backup_launches;   /* backup kernel launches timed (time_kernels = 1) */
+    double final_span;         /* span of the last V_new - V */
+    double threshold;          /* eps (1-gamma)/gamma */
+    double dmax, dmin;         /* max and min of the last V_new - V */
+    double wall_ms;            /* host wall time of the solve */
+    double backup_ms;          /* summed backup kernel time (time_kernels = 1) */
+    int64_t logical_backups;   /* sum over sweeps of N_S * sum_a |Omega(s,a)| */
+    int64_t executed_terms;    /* multiply-adds the kernels actually ran */
+} pvi_result;
+
+typedef struct pvi_mdp pvi_mdp;
+typedef struct pvi_server pvi_server;
+
+/* Validate a descriptor and build its tables on the host (demand PMFs, expected
+ * one-day rewards, arrival and substitution probabilities).  No device memory is
+ * taken until the first solve.  Errors: PVI_E_INVALID (bad descriptor: sizes,
+ * probabilities, gamma, unsupported family/size combination), PVI_E_NOMEM. */
+pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out);
+
+/* Free host and device memory of a handle.  NULL is accepted. */
+pvi_status mdp_destroy(pvi_mdp* mdp);
+
+/* Number of states N_S and actions N_A; -1 for a NULL handle. */
+int64_t mdp_num_states(const pvi_mdp* mdp);
+int32_t mdp_num_actions(const pvi_mdp* mdp);
+/* Number of state digits (A: m+L-1, B: 2(m-1), C: m). */
+int32_t mdp_num_digits(const pvi_mdp* mdp);
+
+/* Mixed-radix state encoding, digits most significant first (see families). */
+pvi_status mdp_encode(const pvi_mdp* mdp, const int32_t* digits, int64_t* idx);
+pvi_status mdp_decode(const pvi_mdp* mdp, int64_t idx, int32_t* digits);
+
+/* The FP64 demand PMF the library built: out[d_max+1] for (product, period). */
+pvi_status mdp_demand_pmf(const pvi_mdp* mdp, int32_t product, int32_t period,
+                          double* out);
+
+/* C: remaining-life probabilities p_k(a), out[(a_max+1) * m], entry a*m + (k-1). */
+pvi_status mdp_life_probs(const pvi_mdp* mdp, double* out);
+
+/* Blocking solve (see the header comment for the stopping rule and policy).
+ * Precision PVI_FP32/PVI_FP32_WIDE run FP32 sweeps until the FP64 span reaches
+ * the FP32 floor, then FP64 sweeps until the threshold; the last FP64 backup also
+ * gives the policy and the best-minus-second Q gap.  With fixed_sweeps > 0
+ * exactly that many sweeps run (all in the chosen storage precision) and the
+ * policy comes from one FP64 backup of the result.  Returns PVI_E_NOT_CONVERGED
+ * after max_sweeps (results still readable).  res may be NULL. */
+pvi_status vi_solve(pvi_mdp* mdp, const pvi_solve_opts* opts, pvi_result* res);
+
+/* One backup of a caller-given FP64 V (host [N_S]) in the given precision:
+ * v_out[N_S] = T(V), policy[N_S] = argmax, q_gap[N_S] = best - second (FP64
+ * precision only; NULL allowed).  For parity checks of single sweeps. */
+pvi_status vi_backup(pvi_mdp* mdp, int32_t precision, const double* v_in, double* v_out,
+                     int32_t* policy, double* q_gap);
+
+/* Results of the last solve: policy[N_S] (and q_gap[N_S], nullable) and the FP64
+ * values V[N_S] (= c + v for FP32 storage).  PVI_E_NOT_READY before a solve. */
+pvi_status policy_get(const pvi_mdp* mdp, int32_t* policy, double* q_gap);
+pvi_status value_get(const pvi_mdp* mdp, double* v);
+/* Copy the policy into caller device memory (int32[N_S]) on `stream`. */
+pvi_status policy_get_device(const pvi_mdp* mdp, int32_t* d_policy, void* stream);
+
+/* Request server: solves of many MDPs of different sizes, admitted by free HBM
+ * within hbm_budget_bytes (0 = 80% of free device memory).  Small scenario-A
+ * instances are batched, up to small_batch per persistent launch.  Each ticket's
+ * results stay in its pvi_mdp handle, which the caller keeps alive until the
+ * ticket completes. */
+pvi_status pvi_server_create(int64_t hbm_budget_bytes, int32_t small_batch,
+                             pvi_server** out);
+pvi_status pvi_server_destroy(pvi_server* server);
+pvi_status vi_batch_submit(pvi_server* server, pvi_mdp* const* mdps,
+                           const pvi_solve_opts* opts, int32_t n, uint64_t* tickets_out);
+pvi_status vi_poll(pvi_server* server, uint64_t ticket, pvi_result* res);
+pvi_status vi_wait(pvi_server* server, uint64_t ticket, int64_t timeout_us,
+                   pvi_result* res);
+/* Latency statistics over completed tickets (milliseconds, submit to done). */
+pvi_status pvi_server_stats(pvi_server* server, double* p50_ms, double* p99_ms,
+                            int64_t* completed);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* pvi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PVI_H */

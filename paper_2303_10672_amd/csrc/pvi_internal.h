@@ -1,0 +1,81 @@
+// Internal definitions shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pvi.h"
+
+namespace pvi {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+pvi_status fail(pvi_status st, const std::string& msg);
+
+#define PVI_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return ::pvi::fail(PVI_E_DEVICE, std::string(#call) + ": " +           \
+                                                 hipGetErrorString(e_));           \
+    } while (0)
+
+// ------------------------------------------------------------------ device control
+// One per solve, in device memory.  Written only by the single-workgroup span
+// kernel and by the host between launches; read by every backup launch.
+struct Ctl {
+    double mu;        // FP32 storage: centre shift applied to the next sweep
+    double c;         // FP32 storage: FP64 offset of the current iterate, V = c + v
+    double dmax, dmin;  // max/min of V_new - V of the last sweep
+    double span;      // dmax - dmin
+    double best_span; // smallest span seen in the current phase
+    double thr;       // stopping threshold on the span (negative: never stop)
+    double floor32;   // FP32 phase ends when span <= max(thr, floor32 * max|v|)
+    double vabs;      // FP32 storage: max |v| of the last sweep
+    int32_t stop;     // 1 once the phase's stopping rule fired; later launches return
+    int32_t sweeps;   // sweeps completed in the current phase
+    int32_t stop_sweep;
+    int32_t stall;    // sweeps without a new best span (FP32 phase)
+    int32_t fp32_phase;
+    int32_t pad[3];
+};
+
+// ------------------------------------------------------------------ family A
+struct ADev {
+    const void* v_in;
+    void* v_out;
+    int32_t* pi;        // extraction only
+    double* gap;        // extraction only
+    double* partials;   // [tiles][4]: max dv, min dv, max v_out, min v_out
+    const double* r0;   // [R][xt]: expected one-day reward without the order cost
+    const double* pmf;  // [tab]: P(d), zero beyond d_max
+    const double* cdf;  // [tab]: P(D <= d), one beyond d_max
+    const double* tail; // [tab]: P(D >= d), zero beyond d_max
+    Ctl* ctl;
+    int64_t stride_a;   // R^(m+L-2): offset of next-state block of action a
+    int64_t stride_h;   // R^(m-1): block size, one block per in-transit vector
+    int32_t R, m, dmax, xt, tab;
+    int32_t nz;         // R^(m-2) tiles per in-transit vector (1 if m <= 2)
+    int32_t r2;         // R if m >= 2 else 1
+    int32_t tiles;      // nh * nz
+    int32_t pow_y[8];   // R^(i-1), weight of next-state digit i inside a block
+    double gamma, cvar;
+};
+
+struct Tables;  // host tables (tables.cpp)
+
+// launchers (kernels_a.hip)
+hipError_t launch_backup_a(const ADev& p, int storage_fp32, int acc_kahan, int extract,
+                           hipStream_t s);
+hipError_t launch_span(Ctl* ctl, const double* partials, int tiles, int storage_fp32,
+                       int fixed, double gamma, hipStream_t s);
+hipError_t launch_to_f64(const float* v32, double* v64, const Ctl* ctl, int64_t n,
+                         hipStream_t s);
+hipError_t launch_to_f32(const double* v64, float* v32, double c, int64_t n, hipStream_t s);
+hipError_t launch_fill(double* v, double value, int64_t n, hipStream_t s);
+
+}  // namespace pvi

@@ -1,0 +1,379 @@
+// Device memory, the sweep loop with its precision schedule, and result access.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "families.h"
+#include "mdp.h"
+
+namespace pvi {
+
+size_t device_bytes(const pvi_mdp* p) {
+    const size_t ns = (size_t)p->ns;
+    size_t b = ns * (2 * sizeof(double) + 2 * sizeof(float) + sizeof(int32_t) + sizeof(double));
+    b += family_extra_bytes(p);
+    b += 4 * sizeof(double) * (size_t)family_tiles(p) + sizeof(Ctl) + 4096;
+    return b;
+}
+
+void free_device(pvi_mdp* p) {
+    auto& d = p->dev;
+    if (!d.ready) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(d.device);
+    if (d.own) (void)hipStreamSynchronize(d.own);
+    void* bufs[] = {d.v64[0], d.v64[1], d.v32[0], d.v32[1], d.pi,  d.gap,
+                    d.partials, d.ctl, d.pmf,   d.cdf,   d.tail, d.r0};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    family_free(p);
+    if (d.h_ctl) (void)hipHostFree(d.h_ctl);
+    for (auto e : d.ev) (void)hipEventDestroy(e);
+    if (d.own) (void)hipStreamDestroy(d.own);
+    (void)hipSetDevice(prev);
+    d = pvi_mdp::Dev{};
+}
+
+template <class T>
+static hipError_t upload(T** dst, const std::vector<T>& src) {
+    hipError_t e = hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(src.size(), 1));
+    if (e != hipSuccess) return e;
+    if (src.empty()) return hipSuccess;
+    return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+static bool device_is_gfx950(int dev, std::string& name) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    name = prop.gcnArchName;
+    return name.rfind("gfx950", 0) == 0;
+}
+
+pvi_status ensure_device(pvi_mdp* p) {
+    auto& d = p->dev;
+    if (d.ready) {
+        int cur = -1;
+        PVI_HIP(hipGetDevice(&cur));
+        if (cur != d.device) PVI_HIP(hipSetDevice(d.device));
+        return PVI_OK;
+    }
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0)
+        return fail(PVI_E_DEVICE, "no HIP device available (this library has no CPU path)");
+    int dev = 0;
+    PVI_HIP(hipGetDevice(&dev));
+    std::string arch;
+    if (!device_is_gfx950(dev, arch))
+        return fail(PVI_E_DEVICE, "device architecture " + arch + " is not gfx950");
+    d.device = dev;
+    const size_t ns = (size_t)p->ns;
+    auto alloc = [&](void** ptr, size_t bytes) -> bool {
+        return hipMalloc(ptr, std::max<size_t>(bytes, 16)) == hipSuccess;
+    };
+    bool ok = alloc((void**)&d.v64[0], ns * 8) && alloc((void**)&d.v64[1], ns * 8) &&
+              alloc((void**)&d.v32[0], ns * 4) && alloc((void**)&d.v32[1], ns * 4) &&
+              alloc((void**)&d.pi, ns * 4) && alloc((void**)&d.gap, ns * 8);
+    d.tiles = family_tiles(p);
+    ok = ok && alloc((void**)&d.partials, 4 * sizeof(double) * (size_t)d.tiles) &&
+         alloc((void**)&d.ctl, sizeof(Ctl));
+    if (ok && p->family == PVI_FAMILY_LEADTIME) {
+        ok = upload(&d.pmf, p->a_pmf) == hipSuccess && upload(&d.cdf, p->a_cdf) == hipSuccess &&
+             upload(&d.tail, p->a_tail) == hipSuccess && upload(&d.r0, p->a_r0) == hipSuccess;
+    }
+    d.ready = true;  // so free_device releases whatever was taken
+    if (!ok) {
+        free_device(p);
+        return fail(PVI_E_NOMEM, "device allocation failed");
+    }
+    pvi_status st = family_init(p);
+    if (st != PVI_OK) {
+        free_device(p);
+        return st;
+    }
+    if (hipHostMalloc((void**)&d.h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        free_device(p);
+        return fail(PVI_E_NOMEM, "pinned host allocation failed");
+    }
+    if (hipStreamCreateWithFlags(&d.own, hipStreamNonBlocking) != hipSuccess) {
+        free_device(p);
+        return fail(PVI_E_DEVICE, "stream creation failed");
+    }
+    d.bytes = device_bytes(p);
+    return PVI_OK;
+}
+
+namespace {
+
+struct Phase {
+    bool fp32 = false;
+    int kahan = 0;
+    int fixed = 0;       // > 0: exactly this many sweeps, no stopping rule
+    int max_sweeps = 0;
+    int k0 = 4;          // sweeps in the first batch
+    int kmax = 64;       // cap on sweeps per batch
+    bool time = false;
+};
+
+struct PhaseOut {
+    int sweeps = 0;
+    double backup_ms = 0.0;
+    int timed = 0;
+    bool stopped = false;
+};
+
+pvi_status init_ctl(pvi_mdp* p, hipStream_t s, double thr, double c0) {
+    Ctl h{};
+    h.mu = 0.0;
+    h.c = c0;
+    h.best_span = INFINITY;
+    h.thr = thr;
+    h.floor32 = 4.0 * std::ldexp(1.0, -23);
+    *p->dev.h_ctl = h;
+    PVI_HIP(hipMemcpyAsync(p->dev.ctl, p->dev.h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    return PVI_OK;
+}
+
+pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) {
+    auto& d = p->dev;
+    int launched = 0, k = ph.k0;
+    double prev_span = -1.0;
+    int prev_sweeps = 0;
+    const int limit = ph.fixed > 0 ? ph.fixed : ph.max_sweeps;
+    if (ph.time && (int)d.ev.size() < 2 * ph.kmax) {
+        for (int i = (int)d.ev.size(); i < 2 * ph.kmax; ++i) {
+            hipEvent_t e;
+            PVI_HIP(hipEventCreate(&e));
+            d.ev.push_back(e);
+        }
+    }
+    while (launched < limit) {
+        const int n = std::min(k, limit - launched);
+        const int before = d.h_ctl->sweeps;
+        for (int i = 0; i < n; ++i) {
+            const void* vin = ph.fp32 ? (const void*)d.v32[launched & 1] : d.v64[launched & 1];
+            void* vout = ph.fp32 ? (void*)d.v32[(launched + 1) & 1] : d.v64[(launched + 1) & 1];
+            if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i], s));
+            PVI_HIP(family_backup(p, ph.fp32, ph.kahan, 0, vin, vout, s));
+            if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i + 1], s));
+            PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, ph.fp32 ? 1 : 0, ph.fixed > 0,
+                                p->d.gamma, s));
+            ++launched;
+        }
+        PVI_HIP(hipMemcpyAsync(d.h_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        PVI_HIP(hipStreamSynchronize(s));
+        const Ctl& h = *d.h_ctl;
+        if (ph.time) {
+            const int real = std::min(n, h.sweeps - before);  // launches that did work
+            for (int i = 0; i < real; ++i) {
+                float ms = 0.f;
+                PVI_HIP(hipEventElapsedTime(&ms, d.ev[2 * i], d.ev[2 * i + 1]));
+                out.backup_ms += ms;
+                ++out.timed;
+            }
+        }
+        if (h.stop) {
+            out.stopped = true;
+            break;
+        }
+        // size the next batch from the observed contraction of the span
+        if (ph.fixed > 0) {
+            k = std::min(ph.kmax, 2 * k);
+        } else if (prev_span > 0.0 && h.span > 0.0 && h.span < prev_span &&
+                   h.sweeps > prev_sweeps) {
+            const double rate = std::pow(h.span / prev_span, 1.0 / (h.sweeps - prev_sweeps));
+            double target = h.thr;
+            if (ph.fp32) target = std::max(target, h.floor32 * h.vabs);
+            const double need = rate < 1.0 ? std::log(target / h.span) / std::log(rate) : ph.kmax;
+            k = (int)std::min<double>(ph.kmax, std::max(1.0, std::ceil(need)));
+        } else {
+            k = std::min(ph.kmax, 2 * k);
+        }
+        prev_span = h.span;
+        prev_sweeps = h.sweeps;
+    }
+    out.sweeps = d.h_ctl->sweeps;
+    return PVI_OK;
+}
+
+double midrange(const double* v, int64_t n) {
+    if (!v || n == 0) return 0.0;
+    double lo = v[0], hi = v[0];
+    for (int64_t i = 1; i < n; ++i) {
+        lo = std::min(lo, v[i]);
+        hi = std::max(hi, v[i]);
+    }
+    return 0.5 * (lo + hi);
+}
+
+}  // namespace
+}  // namespace pvi
+
+using namespace pvi;
+
+extern "C" {
+
+pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* o, pvi_result* res) {
+    if (!p || !o) return fail(PVI_E_INVALID, "vi_solve: NULL argument");
+    if (o->struct_size < sizeof(pvi_solve_opts))
+        return fail(PVI_E_INVALID, "vi_solve: struct_size too small");
+    if (o->precision < PVI_FP64 || o->precision > PVI_FP32_WIDE)
+        return fail(PVI_E_INVALID, "vi_solve: bad precision");
+    if (!(o->eps > 0.0)) return fail(PVI_E_INVALID, "vi_solve: eps must be > 0");
+    if (o->max_sweeps <= 0 && o->fixed_sweeps <= 0)
+        return fail(PVI_E_INVALID, "vi_solve: max_sweeps must be > 0");
+    if (o->fixed_sweeps < 0) return fail(PVI_E_INVALID, "vi_solve: fixed_sweeps < 0");
+    if (!family_supported(p)) return fail(PVI_E_INVALID, "vi_solve: " + family_support_msg(p));
+    std::lock_guard<std::mutex> lock(p->mu);
+    const auto t0 = std::chrono::steady_clock::now();
+    pvi_status st = ensure_device(p);
+    if (st != PVI_OK) return st;
+    auto& d = p->dev;
+    hipStream_t s = o->stream ? (hipStream_t)o->stream : d.own;
+    const double g = p->d.gamma;
+    const double thr = o->eps * (1.0 - g) / g;
+    const int max_sweeps = o->max_sweeps > 0 ? o->max_sweeps : o->fixed_sweeps;
+    const int kmax = o->check_every > 0 ? o->check_every : 64;
+    p->have_result = 0;
+
+    // initial values
+    double c0 = 0.0;
+    if (o->v0) {
+        PVI_HIP(hipMemcpyAsync(d.v64[0], o->v0, sizeof(double) * p->ns, hipMemcpyHostToDevice, s));
+        c0 = midrange(o->v0, p->ns);
+    } else {
+        PVI_HIP(launch_fill(d.v64[0], 0.0, p->ns, s));
+    }
+    PhaseOut o32, o64;
+    const bool fp32 = o->precision != PVI_FP64;
+    const int kahan = o->precision == PVI_FP32 ? 1 : 0;
+    if (fp32) {
+        PVI_HIP(launch_to_f32(d.v64[0], d.v32[0], c0, p->ns, s));
+        if ((st = init_ctl(p, s, thr, c0)) != PVI_OK) return st;
+        Phase ph;
+        ph.fp32 = true;
+        ph.kahan = kahan;
+        ph.fixed = o->fixed_sweeps;
+        ph.max_sweeps = max_sweeps;
+        ph.kmax = kmax;
+        ph.time = o->time_kernels != 0;
+        if ((st = run_phase(p, ph, s, o32)) != PVI_OK) return st;
+        PVI_HIP(launch_to_f64(d.v32[o32.sweeps & 1], d.v64[0], d.ctl, p->ns, s));
+    }
+    const bool fp64_phase = !fp32 || o->fixed_sweeps <= 0;
+    if (fp64_phase) {
+        if ((st = init_ctl(p, s, thr, 0.0)) != PVI_OK) return st;
+        Phase ph;
+        ph.fixed = fp32 ? 0 : o->fixed_sweeps;
+        ph.max_sweeps = max_sweeps;
+        ph.kmax = kmax;
+        ph.k0 = fp32 ? 1 : 4;
+        ph.time = o->time_kernels != 0;
+        if ((st = run_phase(p, ph, s, o64)) != PVI_OK) return st;
+        p->ret_buf = o64.sweeps & 1;
+    } else {
+        p->ret_buf = 0;
+    }
+    // policy and Q gap from one more FP64 backup of the returned V
+    PVI_HIP(family_backup(p, 0, 0, 1, d.v64[p->ret_buf], nullptr, s));
+    PVI_HIP(hipStreamSynchronize(s));
+    p->have_result = 1;
+    const bool converged = o->fixed_sweeps > 0 || o64.stopped;
+    if (res) {
+        std::memset(res, 0, sizeof(*res));
+        const Ctl& h = *d.h_ctl;
+        res->status = converged ? PVI_OK : PVI_E_NOT_CONVERGED;
+        res->sweeps_fp32 = o32.sweeps;
+        res->sweeps_fp64 = fp64_phase ? o64.sweeps : 0;
+        res->backup_launches = o32.timed + o64.timed;
+        res->final_span = h.span;
+        res->threshold = thr;
+        res->dmax = h.dmax;
+        res->dmin = h.dmin;
+        res->backup_ms = o32.backup_ms + o64.backup_ms;
+        const int64_t sweeps = res->sweeps_fp32 + res->sweeps_fp64 + 1;
+        res->logical_backups = p->logical_per_sweep * sweeps;
+        res->executed_terms = p->executed_per_sweep * sweeps;
+        res->wall_ms = std::chrono::duration<double, std::milli>(
+                           std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!converged) return fail(PVI_E_NOT_CONVERGED, "vi_solve: max_sweeps reached");
+    return PVI_OK;
+}
+
+pvi_status vi_backup(pvi_mdp* p, int32_t precision, const double* v_in, double* v_out,
+                     int32_t* policy, double* q_gap) {
+    if (!p || !v_in) return fail(PVI_E_INVALID, "vi_backup: NULL argument");
+    if (precision < PVI_FP64 || precision > PVI_FP32_WIDE)
+        return fail(PVI_E_INVALID, "vi_backup: bad precision");
+    if (!family_supported(p)) return fail(PVI_E_INVALID, "vi_backup: " + family_support_msg(p));
+    std::lock_guard<std::mutex> lock(p->mu);
+    pvi_status st = ensure_device(p);
+    if (st != PVI_OK) return st;
+    auto& d = p->dev;
+    hipStream_t s = d.own;
+    p->have_result = 0;
+    PVI_HIP(hipMemcpyAsync(d.v64[0], v_in, sizeof(double) * p->ns, hipMemcpyHostToDevice, s));
+    if (precision == PVI_FP64) {
+        if ((st = init_ctl(p, s, -1.0, 0.0)) != PVI_OK) return st;
+        PVI_HIP(family_backup(p, 0, 0, 0, d.v64[0], d.v64[1], s));
+        PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, 0, 1, p->d.gamma, s));
+    } else {
+        const double c0 = midrange(v_in, p->ns);
+        PVI_HIP(launch_to_f32(d.v64[0], d.v32[0], c0, p->ns, s));
+        if ((st = init_ctl(p, s, -1.0, c0)) != PVI_OK) return st;
+        PVI_HIP(family_backup(p, 1, precision == PVI_FP32, 0, d.v32[0], d.v32[1], s));
+        PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, 1, 1, p->d.gamma, s));
+        PVI_HIP(launch_to_f64(d.v32[1], d.v64[1], d.ctl, p->ns, s));
+    }
+    PVI_HIP(family_backup(p, 0, 0, 1, d.v64[0], nullptr, s));
+    if (v_out)
+        PVI_HIP(hipMemcpyAsync(v_out, d.v64[1], sizeof(double) * p->ns, hipMemcpyDeviceToHost, s));
+    if (policy)
+        PVI_HIP(hipMemcpyAsync(policy, d.pi, sizeof(int32_t) * p->ns, hipMemcpyDeviceToHost, s));
+    if (q_gap)
+        PVI_HIP(hipMemcpyAsync(q_gap, d.gap, sizeof(double) * p->ns, hipMemcpyDeviceToHost, s));
+    PVI_HIP(hipStreamSynchronize(s));
+    return PVI_OK;
+}
+
+pvi_status policy_get(const pvi_mdp* cp, int32_t* policy, double* q_gap) {
+    pvi_mdp* p = const_cast<pvi_mdp*>(cp);
+    if (!p || !policy) return fail(PVI_E_INVALID, "policy_get: NULL argument");
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (!p->have_result) return fail(PVI_E_NOT_READY, "policy_get: no solve has completed");
+    PVI_HIP(hipSetDevice(p->dev.device));
+    PVI_HIP(hipMemcpy(policy, p->dev.pi, sizeof(int32_t) * p->ns, hipMemcpyDeviceToHost));
+    if (q_gap) PVI_HIP(hipMemcpy(q_gap, p->dev.gap, sizeof(double) * p->ns, hipMemcpyDeviceToHost));
+    return PVI_OK;
+}
+
+pvi_status value_get(const pvi_mdp* cp, double* v) {
+    pvi_mdp* p = const_cast<pvi_mdp*>(cp);
+    if (!p || !v) return fail(PVI_E_INVALID, "value_get: NULL argument");
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (!p->have_result) return fail(PVI_E_NOT_READY, "value_get: no solve has completed");
+    PVI_HIP(hipSetDevice(p->dev.device));
+    PVI_HIP(hipMemcpy(v, p->dev.v64[p->ret_buf], sizeof(double) * p->ns, hipMemcpyDeviceToHost));
+    return PVI_OK;
+}
+
+pvi_status policy_get_device(const pvi_mdp* cp, int32_t* d_policy, void* stream) {
+    pvi_mdp* p = const_cast<pvi_mdp*>(cp);
+    if (!p || !d_policy) return fail(PVI_E_INVALID, "policy_get_device: NULL argument");
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (!p->have_result) return fail(PVI_E_NOT_READY, "policy_get_device: no solve yet");
+    PVI_HIP(hipSetDevice(p->dev.device));
+    hipStream_t s = stream ? (hipStream_t)stream : p->dev.own;
+    PVI_HIP(hipMemcpyAsync(d_policy, p->dev.pi, sizeof(int32_t) * p->ns,
+                           hipMemcpyDeviceToDevice, s));
+    if (!stream) PVI_HIP(hipStreamSynchronize(s));
+    return PVI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,303 @@
+"""ctypes binding of libpvi.so (include/pvi.h), with the C ABI's names.
+
+The binding only marshals arguments: scenario dictionaries become pvi_mdp_desc
+structs and numpy arrays become pointers.  Every step of value iteration runs in
+the library's HIP kernels.  There is no fallback: if libpvi.so is missing,
+`load()` raises, and on a machine without a gfx950 device the solves return
+PVI_E_DEVICE, which is raised here as PviError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpvi.so")
+
+PVI_OK, PVI_E_INVALID, PVI_E_NOMEM, PVI_E_DEVICE = 0, 1, 2, 3
+PVI_E_NOT_CONVERGED, PVI_E_NOT_READY, PVI_E_CANCELLED, PVI_E_BUSY = 4, 5, 6, 7
+STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGED",
+                5: "NOT_READY", 6: "CANCELLED", 7: "BUSY"}
+FAMILY = {"A": 0, "B": 1, "C": 2}
+DEMAND = {"none": 0, "poisson": 1, "gamma": 2, "negbin": 3, "table": 4}
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_wide": 2}
+MAX_PERIODS, MAX_LIFE = 7, 8
+
+
+class PviError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("family", ctypes.c_int32), ("m", ctypes.c_int32),
+        ("lead_time", ctypes.c_int32), ("n_periods", ctypes.c_int32),
+        ("a_max", ctypes.c_int32 * 2), ("d_max", ctypes.c_int32 * 2),
+        ("demand_kind", ctypes.c_int32 * 2),
+        ("demand_mean", (ctypes.c_double * MAX_PERIODS) * 2),
+        ("demand_shape", (ctypes.c_double * MAX_PERIODS) * 2),
+        ("demand_table", ctypes.POINTER(ctypes.c_double) * 2),
+        ("rul_c0", ctypes.c_double * MAX_LIFE), ("rul_c1", ctypes.c_double * MAX_LIFE),
+        ("subst_rho", ctypes.c_double), ("c_var", ctypes.c_double * 2),
+        ("c_fixed", ctypes.c_double), ("c_hold", ctypes.c_double),
+        ("c_short", ctypes.c_double), ("c_waste", ctypes.c_double),
+        ("c_rev", ctypes.c_double * 2), ("gamma", ctypes.c_double),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
+        ("fixed_sweeps", ctypes.c_int32), ("v0", ctypes.POINTER(ctypes.c_double)),
+        ("stream", ctypes.c_void_p), ("check_every", ctypes.c_int32),
+        ("time_kernels", ctypes.c_int32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("sweeps_fp32", ctypes.c_int32),
+        ("sweeps_fp64", ctypes.c_int32), ("backup_launches", ctypes.c_int32),
+        ("final_span", ctypes.c_double), ("threshold", ctypes.c_double),
+        ("dmax", ctypes.c_double), ("dmin", ctypes.c_double), ("wall_ms", ctypes.c_double),
+        ("backup_ms", ctypes.c_double), ("logical_backups", ctypes.c_int64),
+        ("executed_terms", ctypes.c_int64),
+    ]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_P = ctypes.POINTER
+
+
+def load():
+    """Load libpvi.so (built by paper_2303_10672_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2303_10672_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, _P(ctypes.c_double)
+    sig = {
+        "mdp_create": (i32, [_P(Desc), _P(vp)]),
+        "mdp_destroy": (i32, [vp]),
+        "mdp_num_states": (i64, [vp]),
+        "mdp_num_actions": (i32, [vp]),
+        "mdp_num_digits": (i32, [vp]),
+        "mdp_encode": (i32, [vp, _P(i32), _P(i64)]),
+        "mdp_decode": (i32, [vp, i64, _P(i32)]),
+        "mdp_demand_pmf": (i32, [vp, i32, i32, dp]),
+        "mdp_life_probs": (i32, [vp, dp]),
+        "vi_solve": (i32, [vp, _P(Opts), _P(Result)]),
+        "vi_backup": (i32, [vp, i32, dp, dp, _P(i32), dp]),
+        "policy_get": (i32, [vp, _P(i32), dp]),
+        "value_get": (i32, [vp, dp]),
+        "policy_get_device": (i32, [vp, vp, vp]),
+        "pvi_server_create": (i32, [i64, i32, _P(vp)]),
+        "pvi_server_destroy": (i32, [vp]),
+        "vi_batch_submit": (i32, [vp, _P(vp), _P(Opts), i32, _P(ctypes.c_uint64)]),
+        "vi_poll": (i32, [vp, ctypes.c_uint64, _P(Result)]),
+        "vi_wait": (i32, [vp, ctypes.c_uint64, i64, _P(Result)]),
+        "pvi_server_stats": (i32, [vp, dp, dp, _P(i64)]),
+        "pvi_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        if not hasattr(lib, name):
+            continue
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st, what):
+    if st != PVI_OK:
+        msg = _lib.pvi_last_error().decode(errors="replace")
+        raise PviError(st, f"{what}: {msg}")
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_P(ctypes.c_double)) if a is not None else None
+
+
+def _iptr(a):
+    return a.ctypes.data_as(_P(ctypes.c_int32)) if a is not None else None
+
+
+def make_desc(sc):
+    """Marshal a scenario dictionary (see workloads.scenarios) into pvi_mdp_desc."""
+    d = Desc()
+    d.struct_size = ctypes.sizeof(Desc)
+    d.family = FAMILY[sc["family"]]
+    d.m, d.lead_time = sc["m"], sc["L"]
+    d.n_periods = sc["n_periods"]
+    d.a_max[0], d.a_max[1] = sc["a_max"]
+    d.d_max[0], d.d_max[1] = sc["d_max"]
+    keep = []
+    for k in range(2):
+        spec = sc["demand"][k]
+        d.demand_kind[k] = DEMAND[spec["kind"]]
+        means = spec.get("mean", [0.0])
+        shape = spec.get("cv", spec.get("n", [0.0]))
+        for t in range(MAX_PERIODS):
+            d.demand_mean[k][t] = means[t] if t < len(means) else means[0]
+            d.demand_shape[k][t] = shape[t] if t < len(shape) else shape[0]
+        if spec["kind"] == "table":
+            tab = np.ascontiguousarray(spec["table"], dtype=np.float64)
+            keep.append(tab)
+            d.demand_table[k] = _dptr(tab)
+    for i in range(min(len(sc["rul_c0"]), MAX_LIFE)):
+        d.rul_c0[i] = sc["rul_c0"][i]
+        d.rul_c1[i] = sc["rul_c1"][i]
+    d.subst_rho = sc["subst_rho"]
+    c = sc["costs"]
+    d.c_var[0], d.c_var[1] = c["var"]
+    d.c_fixed, d.c_hold, d.c_short, d.c_waste = c["fixed"], c["hold"], c["short"], c["waste"]
+    d.c_rev[0], d.c_rev[1] = c["rev"]
+    d.gamma = sc["gamma"]
+    return d, keep
+
+
+class Mdp:
+    """Owning wrapper of a pvi_mdp handle."""
+
+    def __init__(self, handle, sc):
+        self.handle = handle
+        self.sc = sc
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.mdp_destroy(h)
+
+    @property
+    def n_states(self):
+        return int(_lib.mdp_num_states(self.handle))
+
+    @property
+    def n_actions(self):
+        return int(_lib.mdp_num_actions(self.handle))
+
+
+def mdp_create(sc):
+    lib = load()
+    d, keep = make_desc(sc)
+    h = ctypes.c_void_p()
+    _check(lib.mdp_create(ctypes.byref(d), ctypes.byref(h)), "mdp_create")
+    del keep
+    return Mdp(h, sc)
+
+
+def mdp_destroy(m):
+    h, m.handle = m.handle, None
+    if h:
+        _check(_lib.mdp_destroy(h), "mdp_destroy")
+
+
+def mdp_num_states(m):
+    return m.n_states
+
+
+def mdp_num_actions(m):
+    return m.n_actions
+
+
+def mdp_num_digits(m):
+    return int(_lib.mdp_num_digits(m.handle))
+
+
+def mdp_encode(m, digits):
+    dg = np.ascontiguousarray(digits, dtype=np.int32)
+    out = ctypes.c_int64()
+    _check(_lib.mdp_encode(m.handle, _iptr(dg), ctypes.byref(out)), "mdp_encode")
+    return int(out.value)
+
+
+def mdp_decode(m, idx):
+    out = np.zeros(mdp_num_digits(m), dtype=np.int32)
+    _check(_lib.mdp_decode(m.handle, int(idx), _iptr(out)), "mdp_decode")
+    return out
+
+
+def mdp_demand_pmf(m, product=0, period=0):
+    out = np.zeros(m.sc["d_max"][product] + 1)
+    _check(_lib.mdp_demand_pmf(m.handle, product, period, _dptr(out)), "mdp_demand_pmf")
+    return out
+
+
+def mdp_life_probs(m):
+    out = np.zeros((m.sc["a_max"][0] + 1) * m.sc["m"])
+    _check(_lib.mdp_life_probs(m.handle, _dptr(out)), "mdp_life_probs")
+    return out.reshape(m.sc["a_max"][0] + 1, m.sc["m"])
+
+
+def make_opts(precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0, v0=None,
+              stream=None, check_every=0, time_kernels=False, sc=None):
+    o = Opts()
+    o.struct_size = ctypes.sizeof(Opts)
+    o.precision = PRECISION[precision]
+    o.eps = float(eps if eps is not None else (sc["eps"] if sc else 1e-4))
+    o.max_sweeps = int(max_sweeps)
+    o.fixed_sweeps = int(fixed_sweeps)
+    o.v0 = _dptr(v0)
+    o.stream = stream
+    o.check_every = int(check_every)
+    o.time_kernels = 1 if time_kernels else 0
+    return o
+
+
+def vi_solve(m, precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0, v0=None,
+             stream=None, check_every=0, time_kernels=False, allow_not_converged=False):
+    """Blocking solve; returns the pvi_result fields as a dict."""
+    v0a = None if v0 is None else np.ascontiguousarray(v0, dtype=np.float64)
+    o = make_opts(precision, eps, max_sweeps, fixed_sweeps, v0a, stream, check_every,
+                  time_kernels, m.sc)
+    r = Result()
+    st = _lib.vi_solve(m.handle, ctypes.byref(o), ctypes.byref(r))
+    if not (allow_not_converged and st == PVI_E_NOT_CONVERGED):
+        _check(st, "vi_solve")
+    return r.to_dict()
+
+
+def vi_backup(m, v_in, precision="fp64"):
+    """One backup of V: returns (T(V), argmax policy, FP64 Q gap)."""
+    v = np.ascontiguousarray(v_in, dtype=np.float64)
+    n = m.n_states
+    out = np.zeros(n)
+    pol = np.zeros(n, dtype=np.int32)
+    gap = np.zeros(n)
+    _check(_lib.vi_backup(m.handle, PRECISION[precision], _dptr(v), _dptr(out), _iptr(pol),
+                          _dptr(gap)), "vi_backup")
+    return out, pol, gap
+
+
+def policy_get(m):
+    n = m.n_states
+    pol = np.zeros(n, dtype=np.int32)
+    gap = np.zeros(n)
+    _check(_lib.policy_get(m.handle, _iptr(pol), _dptr(gap)), "policy_get")
+    return pol, gap
+
+
+def value_get(m):
+    v = np.zeros(m.n_states)
+    _check(_lib.value_get(m.handle, _dptr(v)), "value_get")
+    return v
+
+
+def policy_get_device(m, d_policy_ptr, stream=None):
+    _check(_lib.policy_get_device(m.handle, ctypes.c_void_p(d_policy_ptr), stream),
+           "policy_get_device")
+
+
+def last_error():
+    return load().pvi_last_error().decode(errors="replace")

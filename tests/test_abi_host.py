@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI (no GPU): exports, validation, encoding, tables."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.oracle import Oracle, life_probabilities
+from paper_2303_10672_amd import pvi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "pvi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    lib = ctypes.CDLL(pvi.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_sizes_match_header_layout():
+    # pvi_mdp_desc: 5 int32 + 3x2 int32 + 2x7x2 doubles + 2 ptrs + 16 doubles + ...
+    assert ctypes.sizeof(pvi.Desc) % 8 == 0
+    assert ctypes.sizeof(pvi.Opts) == 48
+    assert ctypes.sizeof(pvi.Result) == 80
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_counts_encoding_and_pmfs_match_oracle(cfg):
+    sc = W.config_by_index(cfg)
+    m = pvi.mdp_create(sc)
+    o = Oracle(sc)
+    assert m.n_states == o.n_states and m.n_actions == o.n_actions
+    for s in W.sample_indices(o.n_states, 200, seed=cfg):
+        dg = pvi.mdp_decode(m, s)
+        assert np.array_equal(dg, o.decode(s))
+        assert pvi.mdp_encode(m, dg) == s
+    for t in range(sc["n_periods"]):
+        assert np.allclose(pvi.mdp_demand_pmf(m, 0, t), o.pmf0[t], rtol=1e-12, atol=1e-15)
+    if sc["family"] == "B":
+        assert np.allclose(pvi.mdp_demand_pmf(m, 1, 0), o.pmf1, rtol=1e-12, atol=1e-15)
+    if sc["family"] == "C":
+        assert np.allclose(pvi.mdp_life_probs(m), life_probabilities(sc), rtol=1e-13)
+
+
+def test_gamma_pmf_small_shape_matches_oracle():
+    for cv in (0.3, 0.5, 1.0, 1.5, 3.0):
+        sc = W.scenario_a(m=2, L=1, a_max=5, d_max=100,
+                          demand={"kind": "gamma", "mean": [4.0], "cv": [cv]})
+        m = pvi.mdp_create(sc)
+        assert np.allclose(pvi.mdp_demand_pmf(m), Oracle(sc).pmf0[0], rtol=1e-11, atol=1e-15)
+
+
+def _bad(**kw):
+    sc = W.config0()
+    sc.update(kw)
+    return sc
+
+
+@pytest.mark.parametrize("sc,msg", [
+    (_bad(gamma=1.0), "gamma"),
+    (_bad(gamma=0.0), "gamma"),
+    (_bad(m=0), "m out of range"),
+    (_bad(m=9), "m out of range"),
+    (_bad(L=0), "L >= 1"),
+    (_bad(a_max=[32, 0]), "a_max"),
+    (_bad(d_max=[-1, 0]), "d_max"),
+    (_bad(n_periods=3), "n_periods"),
+    (W.scenario_c(m=1), "m >= 2"),
+    (dict(W.scenario_b(), L=1), "L = 0"),
+    (dict(W.scenario_b(), subst_rho=1.5), "subst_rho"),
+])
+def test_invalid_descriptors_are_rejected(sc, msg):
+    with pytest.raises(pvi.PviError) as e:
+        pvi.mdp_create(sc)
+    assert e.value.status == pvi.PVI_E_INVALID
+    assert msg in str(e.value)
+
+
+def test_bad_demand_table_rejected():
+    sc = W.config0()
+    sc["demand"][0] = {"kind": "table", "table": [0.5] * 21}
+    with pytest.raises(pvi.PviError):
+        pvi.mdp_create(sc)
+    sc["demand"][0] = {"kind": "table", "table": [1.0] + [0.0] * 20}
+    m = pvi.mdp_create(sc)
+    assert pvi.mdp_demand_pmf(m)[0] == 1.0
+
+
+def test_encode_rejects_out_of_range_digits():
+    m = pvi.mdp_create(W.config0())
+    with pytest.raises(pvi.PviError):
+        pvi.mdp_encode(m, [11, 0])
+    with pytest.raises(pvi.PviError):
+        pvi.mdp_decode(m, 121)
+
+
+def test_results_not_ready_before_a_solve():
+    m = pvi.mdp_create(W.config0())
+    with pytest.raises(pvi.PviError) as e:
+        pvi.policy_get(m)
+    assert e.value.status == pvi.PVI_E_NOT_READY
+
+
+def test_no_device_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    m = pvi.mdp_create(W.config0())
+    with pytest.raises(pvi.PviError) as e:
+        pvi.vi_solve(m)
+    assert e.value.status == pvi.PVI_E_DEVICE
