@@ -133,12 +133,13 @@ typedef struct pvi_result {
     int32_t status;            /* pvi_status of the solve */
     int32_t sweeps_fp32;       /* sweeps run with FP32 storage */
     int32_t sweeps_fp64;       /* sweeps run in FP64 (including polish) */
-    int32_t backup_launches;   /* backup kernel launches timed (time_kernels = 1) */
+    int32_t backup_launches[2];/* backup launches timed (time_kernels = 1); [0] FP64
+                                  storage sweeps, [1] FP32 storage sweeps */
     double final_span;         /* span of the last V_new - V */
     double threshold;          /* eps (1-gamma)/gamma */
     double dmax, dmin;         /* max and min of the last V_new - V */
     double wall_ms;            /* host wall time of the solve */
-    double backup_ms;          /* summed backup kernel time (time_kernels = 1) */
+    double backup_ms[2];       /* summed backup kernel time of those launches */
     int64_t logical_backups;   /* sum over sweeps of N_S * sum_a |Omega(s,a)| */
     int64_t executed_terms;    /* multiply-adds the kernels actually ran */
 } pvi_result;

@@ -1,0 +1,48 @@
+// Device helpers shared by the kernel files (header-only, no relocatable code).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pvi {
+
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of tiles so the V blocks a range touches stay in one L2.
+    const int q = nb >> 3, r = nb & 7, x = bid & 7, l = bid >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide reduction of 4 values (max, min, max, min); result valid in thread 0.
+__device__ inline void block_reduce4(double& a, double& b, double& c, double& d, double* red) {
+    a = wave_max(a);
+    b = wave_min(b);
+    c = wave_max(c);
+    d = wave_min(d);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+        red[4 * w + 0] = a;
+        red[4 * w + 1] = b;
+        red[4 * w + 2] = c;
+        red[4 * w + 3] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < nw; ++i) {
+            a = fmax(a, red[4 * i + 0]);
+            b = fmin(b, red[4 * i + 1]);
+            c = fmax(c, red[4 * i + 2]);
+            d = fmin(d, red[4 * i + 3]);
+        }
+    }
+}
+
+}  // namespace pvi

@@ -1,6 +1,8 @@
 // Per-family dispatch: kernel parameter blocks and launches.
 #include "families.h"
 
+#include <algorithm>
+
 namespace pvi {
 
 static int64_t ipow(int64_t b, int e) {
@@ -36,30 +38,177 @@ ADev make_adev(const pvi_mdp* p) {
     return a;
 }
 
-bool family_supported(const pvi_mdp* p) { return p->family == PVI_FAMILY_LEADTIME; }
+static BDev make_bdev(const pvi_mdp* p) {
+    BDev b{};
+    b.m = p->m;
+    b.r0 = p->rad[0];
+    b.r1 = p->rad[1];
+    b.r1pad = PVI_B_R1MAX;
+    b.na = (int)ipow(p->rad[0], p->m - 1);
+    b.nb = (int)ipow(p->rad[1], p->m - 1);
+    b.rows = p->b_rows;
+    b.d0max = p->dmax[0];
+    b.emax = p->b_emax;
+    b.ew = p->b_ew;
+    b.sw = p->b_sw;
+    b.gamma = p->d.gamma;
+    b.cvar0 = p->d.c_var[0];
+    b.cvar1 = p->d.c_var[1];
+    b.z = p->dev.z;
+    b.pmf0 = p->dev.pmf;
+    b.rexp0 = p->dev.rexp0;
+    b.e_pmf = p->dev.epmf;
+    b.e_cdf = p->dev.ecdf;
+    b.e_tail = p->dev.etail;
+    b.rexp1 = p->dev.rexp1;
+    b.ctl = p->dev.ctl;
+    b.partials = p->dev.partials;
+    b.pi = p->dev.pi;
+    b.gap = p->dev.gap;
+    return b;
+}
+
+static CDev make_cdev(const pvi_mdp* p) {
+    CDev c{};
+    const int R = p->rad[0];
+    c.R = R;
+    c.m = p->m;
+    c.P = p->P;
+    c.nzu = (int)ipow(R, p->m - 2);
+    c.nblk = ipow(R, p->m - 1);
+    c.npair = p->c_npair;
+    c.tab = p->c_tab;
+    c.xt = p->c_xt;
+    c.lpmax = p->c_lpmax;
+    c.dmax = p->dmax[0];
+    for (int i = 0; i < 10; ++i) c.pow_r[i] = (int)ipow(R, i);
+    c.gamma = p->d.gamma;
+    c.cfixed = p->d.c_fixed;
+    const auto& d = p->dev;
+    c.u = d.cu;
+    c.t0 = d.ct0;
+    c.t1 = d.ct1;
+    c.pmf = d.cpmf;
+    c.cdf = d.ccdf;
+    c.tail = d.ctail;
+    c.r0 = d.cr0;
+    c.binq = d.cbinq;
+    c.binm = d.cbinm;
+    c.pair_y = d.cpy;
+    c.pair_r = d.cpr;
+    c.pair_base = d.cpb;
+    c.ctl = d.ctl;
+    c.partials = d.partials;
+    c.pi = d.pi;
+    c.gap = d.gap;
+    return c;
+}
+
+static size_t c_table_entries(const pvi_mdp* p) {  // entries of one merge table
+    return (size_t)p->P * p->c_npair * ipow(p->rad[0], p->m - 1);
+}
 
 std::string family_support_msg(const pvi_mdp* p) {
-    if (family_supported(p)) return "ok";
+    if (p->family == PVI_FAMILY_LEADTIME) return "ok";
+    if (p->family == PVI_FAMILY_SUBST2) {
+        if (p->m < 2) return "scenario B needs m >= 2 on the GPU";
+        if (p->rad[1] > PVI_B_R1MAX) return "scenario B needs a_max[1] <= 15 on the GPU";
+        const size_t lds = sizeof(double) * ((size_t)p->b_rows * PVI_B_R1MAX + p->dmax[0] + 65);
+        if (lds > 65536) return "scenario B stage-2 table exceeds LDS (too many product-0 states)";
+        return "ok";
+    }
+    if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
+        if (!p->c_exogenous)
+            return "scenario C with order-dependent remaining life (rul_c1 != 0) has no GPU "
+                   "kernel";
+        if (p->m > 9) return "scenario C needs m <= 9 on the GPU";
+        const size_t lds = sizeof(double) * ((size_t)p->c_lpmax + 3 * (size_t)p->c_tab);
+        if (lds > 65536) return "scenario C demand table exceeds LDS";
+        return "ok";
+    }
     return "this family has no GPU kernel yet";
 }
+
+bool family_supported(const pvi_mdp* p) { return family_support_msg(p) == "ok"; }
 
 int family_tiles(const pvi_mdp* p) {
     if (p->family == PVI_FAMILY_LEADTIME) {
         const int R = p->rad[0];
         return (int)(ipow(R, p->L - 1) * (p->m >= 2 ? ipow(R, p->m - 2) : 1));
     }
+    if (p->family == PVI_FAMILY_SUBST2) return (int)ipow(p->rad[1], p->m - 1);
+    if (p->family == PVI_FAMILY_RUL_WEEKDAY)
+        return (int)(p->P * ((ipow(p->rad[0], p->m - 1) + 255) / 256));
     return 1;
 }
 
 size_t family_extra_bytes(const pvi_mdp* p) {
     if (p->family == PVI_FAMILY_LEADTIME)
         return sizeof(double) * (3 * (size_t)p->tab + p->a_r0.size());
+    if (p->family == PVI_FAMILY_SUBST2)
+        return sizeof(double) * ((size_t)p->b_rows * ipow(p->rad[1], p->m) + p->b_rexp0.size() +
+                                 3 * p->b_epmf.size() + p->b_rexp1.size() + p->pmf[0].size());
+    if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
+        const size_t ut = (size_t)p->ns * p->rad[0];
+        const size_t tt = p->m >= 3 ? c_table_entries(p) : 0;
+        return sizeof(double) * (ut + 2 * tt + 3 * p->c_pmf.size() + p->c_r0.size() +
+                                 p->c_binq.size() + p->c_binm.size());
+    }
     return 0;
 }
 
-pvi_status family_init(pvi_mdp*) { return PVI_OK; }
+template <class T>
+static hipError_t upload_vec(T** dst, const std::vector<T>& src) {
+    hipError_t e = hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(src.size(), 1));
+    if (e != hipSuccess || src.empty()) return e;
+    return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
 
-void family_free(pvi_mdp*) {}
+pvi_status family_init(pvi_mdp* p) {
+    auto& d = p->dev;
+    if (p->family == PVI_FAMILY_SUBST2) {
+        const size_t zn = (size_t)p->b_rows * ipow(p->rad[1], p->m);
+        if (hipMalloc((void**)&d.z, sizeof(double) * zn) != hipSuccess ||
+            upload_vec(&d.pmf, p->pmf[0]) != hipSuccess ||
+            upload_vec(&d.rexp0, p->b_rexp0) != hipSuccess ||
+            upload_vec(&d.epmf, p->b_epmf) != hipSuccess ||
+            upload_vec(&d.ecdf, p->b_ecdf) != hipSuccess ||
+            upload_vec(&d.etail, p->b_etail) != hipSuccess ||
+            upload_vec(&d.rexp1, p->b_rexp1) != hipSuccess)
+            return fail(PVI_E_NOMEM, "scenario B table allocation failed");
+    }
+    if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
+        const size_t ut = (size_t)p->ns * p->rad[0];
+        const size_t tt = p->m >= 3 ? c_table_entries(p) : 1;
+        if (hipMalloc(&d.cu, sizeof(double) * ut) != hipSuccess ||
+            hipMalloc(&d.ct0, sizeof(double) * tt) != hipSuccess ||
+            hipMalloc(&d.ct1, sizeof(double) * tt) != hipSuccess ||
+            upload_vec(&d.cpmf, p->c_pmf) != hipSuccess ||
+            upload_vec(&d.ccdf, p->c_cdf) != hipSuccess ||
+            upload_vec(&d.ctail, p->c_tail) != hipSuccess ||
+            upload_vec(&d.cr0, p->c_r0) != hipSuccess ||
+            upload_vec(&d.cbinq, p->c_binq) != hipSuccess ||
+            upload_vec(&d.cbinm, p->c_binm) != hipSuccess ||
+            upload_vec(&d.cpy, p->c_pair_y) != hipSuccess ||
+            upload_vec(&d.cpr, p->c_pair_r) != hipSuccess ||
+            upload_vec(&d.cpb, p->c_pair_base) != hipSuccess)
+            return fail(PVI_E_NOMEM, "scenario C table allocation failed");
+    }
+    return PVI_OK;
+}
+
+void family_free(pvi_mdp* p) {
+    auto& d = p->dev;
+    void* bufs[] = {d.z,    d.rexp0, d.epmf,  d.ecdf,  d.etail, d.rexp1, d.cu,  d.ct0,
+                    d.ct1,  d.cpmf,  d.ccdf,  d.ctail, d.cr0,   d.cbinq,  d.cbinm, d.cpy,
+                    d.cpr,  d.cpb};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    d.z = d.rexp0 = d.epmf = d.ecdf = d.etail = d.rexp1 = nullptr;
+    d.cu = d.ct0 = d.ct1 = nullptr;
+    d.cpmf = d.ccdf = d.ctail = d.cr0 = d.cbinq = d.cbinm = nullptr;
+    d.cpy = d.cpr = d.cpb = nullptr;
+}
 
 hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, const void* vin,
                          void* vout, hipStream_t s) {
@@ -68,6 +217,20 @@ hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, const voi
         a.v_in = vin;
         a.v_out = vout;
         return launch_backup_a(a, fp32, kahan, extract, s);
+    }
+    if (p->family == PVI_FAMILY_SUBST2) {
+        BDev b = make_bdev(p);
+        b.v_in = vin;
+        b.v_out = vout;
+        b.extract = extract;
+        return launch_backup_b(b, fp32, extract, s);
+    }
+    if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
+        CDev c = make_cdev(p);
+        c.v_in = vin;
+        c.v_out = vout;
+        c.extract = extract;
+        return launch_backup_c(c, fp32, extract, s);
     }
     return hipErrorInvalidValue;
 }

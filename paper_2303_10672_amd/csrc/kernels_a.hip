@@ -29,49 +29,10 @@
 #include <cfloat>
 #include <cmath>
 
+#include "device_common.h"
 #include "pvi_internal.h"
 
 namespace pvi {
-
-__device__ __forceinline__ int xcd_remap(int bid, int nb) {
-    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of tiles so the V blocks a range touches stay in one L2.
-    const int q = nb >> 3, r = nb & 7, x = bid & 7, l = bid >> 3;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Block-wide reduction of 4 values (max, min, max, min); result valid in thread 0.
-__device__ void block_reduce4(double& a, double& b, double& c, double& d, double* red) {
-    a = wave_max(a);
-    b = wave_min(b);
-    c = wave_max(c);
-    d = wave_min(d);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-    if (lane == 0) {
-        red[4 * w + 0] = a;
-        red[4 * w + 1] = b;
-        red[4 * w + 2] = c;
-        red[4 * w + 3] = d;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < nw; ++i) {
-            a = fmax(a, red[4 * i + 0]);
-            b = fmin(b, red[4 * i + 1]);
-            c = fmax(c, red[4 * i + 2]);
-            d = fmin(d, red[4 * i + 3]);
-        }
-    }
-}
 
 // Offset inside a next-state block of point j of a tile's descending path list.
 // The list is [col_{m-1} (Y_{m-1} points), ..., col_2 (Y_2 points), row (r2 points)]
@@ -111,16 +72,41 @@ __device__ __forceinline__ double lane_of<double, 2>(const double2& v, int i) {
     return i == 0 ? v.x : v.y;
 }
 
+// Accumulator over outcomes: FP64 multiply-add, or FP32 with Kahan compensation.
+template <typename VT, bool KAHAN>
+struct Acc {
+    using W = double;
+    double s = 0.0;
+    __device__ __forceinline__ void add(double w, VT u) { s = fma(w, (double)u, s); }
+    __device__ __forceinline__ double value() const { return s; }
+};
+template <>
+struct Acc<float, true> {
+    using W = float;
+    float s = 0.f, c = 0.f;
+    __device__ __forceinline__ void add(float w, float u) {
+        const float y = fmaf(w, u, -c);
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+
 // VT: storage type of V (float = centred FP32, double = FP64).
 // KAHAN: FP32 compensated accumulation (only with VT = float); otherwise FP64.
+// J: states (consecutive X_1) per lane.  Lanes with the same X_2 read the same
+//    staged values, so each value read from LDS feeds J multiply-adds; this keeps
+//    the LDS return path from limiting the kernel.
 // EXTRACT: write policy and Q gap instead of V (FP64 only).
-template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
-__global__ __launch_bounds__(1024) void backup_a_kernel(ADev p) {
+template <typename VT, bool KAHAN, int RMAX, int J, bool EXTRACT>
+__global__ __launch_bounds__(512) void backup_a_kernel(ADev p) {
     extern __shared__ __align__(16) unsigned char smem[];
     Ctl* ctl = p.ctl;
     if (!EXTRACT && ctl->stop) return;
     constexpr int W = VecLoad<VT>::W;
     using VV = typename VecLoad<VT>::V;
+    using AW = typename Acc<VT, KAHAN>::W;
 
     const int R = p.R, m = p.m, tid = threadIdx.x, bs = blockDim.x;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -159,108 +145,85 @@ __global__ __launch_bounds__(1024) void backup_a_kernel(ADev p) {
     }
     __syncthreads();
 
+    const int G = (R + J - 1) / J;
     const int ns_tile = p.r2 * R;
-    double best = -DBL_MAX, second = -DBL_MAX, out = 0.0, dv = 0.0;
-    int arg = 0;
-    const bool active = tid < ns_tile;
-    const int X2 = active ? tid / R : 0, X1 = active ? tid - (tid / R) * R : 0;
+    const bool active = tid < p.r2 * G;
+    const int X2 = active ? tid / G : 0;
+    const int x1_0 = active ? (tid - X2 * G) * J : 0;
+    double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
     if (active) {
         const int N = b + X2;
-        const int kmax = N == 0 ? 0 : max(0, min(N, p.dmax - X1));
-        if (KAHAN) {
-            float s[RMAX], c[RMAX];
+        const int kmax = N == 0 ? 0 : max(0, min(N, p.dmax - x1_0));
+        Acc<VT, KAHAN> acc[J][RMAX];
+        for (int k = 0; k <= kmax; ++k) {
+            AW w[J];
 #pragma unroll
-            for (int a = 0; a < RMAX; ++a) s[a] = c[a] = 0.f;
-            for (int k = 0; k <= kmax; ++k) {
-                const double wd = N == 0 ? 1.0
+            for (int i = 0; i < J; ++i) {
+                const int X1 = x1_0 + i;
+                // demand <= X_1 keeps y; X_1 + k removes k units; the last point
+                // collects every demand that empties y (tables are zero past d_max)
+                const double wd = N == 0 ? (k == 0 ? 1.0 : 0.0)
                                   : k == 0 ? sF[min(X1, p.dmax)]
                                   : k == N ? sG[X1 + N]
                                            : sP[X1 + k];
-                const float w = (float)wd;
-                const VV* row = reinterpret_cast<const VV*>(S + (N - k) * RMAX);
-#pragma unroll
-                for (int q = 0; q < RMAX / W; ++q) {
-                    const VV u = row[q];
-#pragma unroll
-                    for (int i = 0; i < W; ++i) {
-                        const int a = q * W + i;
-                        const float y = fmaf(w, (float)lane_of<VT, W>(u, i), -c[a]);
-                        const float t = s[a] + y;
-                        c[a] = (t - s[a]) - y;
-                        s[a] = t;
-                    }
-                }
+                w[i] = (AW)wd;
             }
+            const VV* row = reinterpret_cast<const VV*>(S + (N - k) * RMAX);
 #pragma unroll
-            for (int a = 0; a < RMAX; ++a) {
-                if (a < R) {
-                    const double q = -p.cvar * a + p.gamma * ((double)s[a] - (double)c[a]);
-                    if (q > best) {
-                        second = best;
-                        best = q;
-                        arg = a;
-                    } else if (q > second) {
-                        second = q;
-                    }
-                }
-            }
-        } else {
-            double acc[RMAX];
+            for (int q = 0; q < RMAX / W; ++q) {
+                const VV u = row[q];
 #pragma unroll
-            for (int a = 0; a < RMAX; ++a) acc[a] = 0.0;
-            for (int k = 0; k <= kmax; ++k) {
-                const double w = N == 0 ? 1.0
-                                 : k == 0 ? sF[min(X1, p.dmax)]
-                                 : k == N ? sG[X1 + N]
-                                          : sP[X1 + k];
-                const VV* row = reinterpret_cast<const VV*>(S + (N - k) * RMAX);
+                for (int e = 0; e < W; ++e) {
+                    const VT ue = lane_of<VT, W>(u, e);
 #pragma unroll
-                for (int q = 0; q < RMAX / W; ++q) {
-                    const VV u = row[q];
-#pragma unroll
-                    for (int i = 0; i < W; ++i)
-                        acc[q * W + i] = fma(w, (double)lane_of<VT, W>(u, i), acc[q * W + i]);
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < RMAX; ++a) {
-                if (a < R) {
-                    const double q = -p.cvar * a + p.gamma * acc[a];
-                    if (q > best) {
-                        second = best;
-                        best = q;
-                        arg = a;
-                    } else if (q > second) {
-                        second = q;
-                    }
+                    for (int i = 0; i < J; ++i) acc[i][q * W + e].add(w[i], ue);
                 }
             }
         }
-        const int xtot = X1 + X2 + b;
-        const double r0 = p.r0[X1 * p.xt + xtot];
-        const int64_t s_idx = (int64_t)tile * ns_tile + tid;
-        if (EXTRACT) {
-            p.pi[s_idx] = arg;
-            p.gap[s_idx] = R > 1 ? best - second : INFINITY;
-        } else {
-            const double mu = sizeof(VT) == 4 ? ctl->mu : 0.0;
-            out = r0 - mu + best;
-            const VT o = (VT)out;
-            out = (double)o;
-            reinterpret_cast<VT*>(p.v_out)[s_idx] = o;
-            dv = out - (double)vin[s_idx];
+        const double mu = (!EXTRACT && sizeof(VT) == 4) ? ctl->mu : 0.0;
+#pragma unroll
+        for (int i = 0; i < J; ++i) {
+            const int X1 = x1_0 + i;
+            if (X1 >= R) continue;
+            double best = -DBL_MAX, second = -DBL_MAX;
+            int arg = 0;
+#pragma unroll
+            for (int a = 0; a < RMAX; ++a) {
+                if (a < R) {
+                    const double q = -p.cvar * a + p.gamma * acc[i][a].value();
+                    if (q > best) {
+                        second = best;
+                        best = q;
+                        arg = a;
+                    } else if (q > second) {
+                        second = q;
+                    }
+                }
+            }
+            const int64_t s_idx = (int64_t)tile * ns_tile + X2 * R + X1;
+            if (EXTRACT) {
+                p.pi[s_idx] = arg;
+                p.gap[s_idx] = R > 1 ? best - second : INFINITY;
+            } else {
+                const double r0 = p.r0[X1 * p.xt + X1 + X2 + b];
+                const VT o = (VT)(r0 - mu + best);
+                reinterpret_cast<VT*>(p.v_out)[s_idx] = o;
+                const double out = (double)o, dv = out - (double)vin[s_idx];
+                dmx = fmax(dmx, dv);
+                dmn = fmin(dmn, dv);
+                vmx = fmax(vmx, out);
+                vmn = fmin(vmn, out);
+            }
         }
     }
     if (EXTRACT) return;
-    double a0 = active ? dv : -DBL_MAX, a1 = active ? dv : DBL_MAX;
-    double a2 = active ? out : -DBL_MAX, a3 = active ? out : DBL_MAX;
-    block_reduce4(a0, a1, a2, a3, red);
+    block_reduce4(dmx, dmn, vmx, vmn, red);
     if (tid == 0) {
         double* pp = p.partials + 4 * (size_t)tile;
-        pp[0] = a0;
-        pp[1] = a1;
-        pp[2] = a2;
-        pp[3] = a3;
+        pp[0] = dmx;
+        pp[1] = dmn;
+        pp[2] = vmx;
+        pp[3] = vmn;
     }
 }
 
@@ -336,13 +299,17 @@ __global__ void to_f32_kernel(const double* v64, float* v32, double c, int64_t n
 
 template <typename VT, bool KAHAN, bool EXTRACT, int RMAX>
 static hipError_t launch_a_r(const ADev& p, hipStream_t s) {
+    // states per lane: enough multiply-adds per LDS value to keep VALU busy
+    constexpr int J = KAHAN ? 2 : (RMAX <= 24 ? 4 : 3);
     const int lp_max = (p.m >= 2 ? (p.m - 2) * (p.R - 1) : 0) + p.r2;
     size_t bytes = sizeof(VT) * (size_t)lp_max * RMAX;
     bytes += sizeof(double) * (3 * (size_t)p.tab + 64);
     if (bytes > 65536) return hipErrorInvalidConfiguration;  // beyond the default LDS limit
-    const int ns_tile = p.r2 * p.R;
-    const int threads = ((ns_tile + 63) / 64) * 64;
-    hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT>), dim3(p.tiles),
+    if (p.tab < p.R + J + lp_max || p.tab < p.dmax + 2 + J) return hipErrorInvalidValue;
+    const int lanes = p.r2 * ((p.R + J - 1) / J);
+    const int threads = ((lanes + 63) / 64) * 64;
+    if (threads > 512) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, J, EXTRACT>), dim3(p.tiles),
                        dim3(threads), bytes, s, p);
     return hipGetLastError();
 }

@@ -1,0 +1,246 @@
+// Scenario C (weekday demand, random remaining life on arrival, capacity a_max per
+// life class, L = 0) Bellman backup.
+//
+// Follows the deterministic-transition update (Methods, "Value iteration") with T
+// from Appendix C (state-transition equation, reward equation, age-on-arrival
+// distribution).  The outcome is (d, y): demand d and the split y = (y_m..y_1) of
+// the order over remaining lives, with probability P(d|tau) Mult(y; a, p).
+// Because P factorises and the demand acts only on the post-arrival stock
+// z = (y_m, min(x_{m-1}+y_{m-1}, a_max), ..., min(x_1+y_1, a_max)), the sum is
+// taken in two exact stages:
+//
+//  stage U   U(tau, z) = sum_d P(d|tau) [ r(z, d) + gamma V(tau+1, f(z, d)) ]
+//            for every z in [0, a_max]^m.  Demand up to z_1 leaves (z_m..z_2)
+//            intact; z_1 + k removes k of them oldest first, so the sum walks a
+//            descending path list staged in LDS, as in scenario A.
+//  stage Y   Mult(y; a, p) = Bin(y_m; a, p_m) Bin(y_{m-1}; a-y_m, q_{m-1}) ...
+//            with q_j = p_j / (p_1 + ... + p_j), so the arrival sum is a chain of
+//            binomial merges, one life class at a time:
+//              T_2(.., x_2, x_1; r)  = sum_y Bin(y; r, q_2) U(.., c(x_2+y), c(x_1+r-y))
+//              T_j(.., x_j, ..; r)   = sum_y Bin(y; r, q_j) T_{j-1}(.., c(x_j+y), ..; r-y)
+//              Q(tau, x, a) = -C_f[a>0] + sum_y Bin(y; a, p_m) T_{m-1}(tau, y, x; a-y)
+//            where c(.) caps at a_max and r counts units still to place.
+// The remaining-life probabilities must not depend on the order size here
+// (exogenous case).  T tables are laid out [tau][(y_m, r) pair][x digits] so
+// consecutive lanes touch consecutive addresses.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "device_common.h"
+#include "pvi_internal.h"
+
+namespace pvi {
+
+// Offset in a next-state block of point j of the descending path list of the
+// upper digits Y[2..m-1] (see the scenario-A kernel for the construction).
+__device__ __forceinline__ int c_path_offset(int j, const int* Y, int m, const int* pw) {
+    int off = 0;
+    for (int i = m - 1; i >= 2; --i) {
+        if (j < Y[i]) return off + j * pw[i - 1];
+        j -= Y[i];
+        off += Y[i] * pw[i - 1];
+    }
+    return off + j;
+}
+
+// U[tau][z_m..z_1]: one workgroup per (tau, z_m..z_3), lanes over (z_2, 4 of z_1).
+template <typename VT>
+__global__ __launch_bounds__(256) void c_stage_u_kernel(CDev p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (!p.extract && p.ctl->stop) return;
+    constexpr int J = 4;
+    const int R = p.R, m = p.m, tid = threadIdx.x;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tau = tile / p.nzu;
+    int Y[10];
+    int b = 0;
+    {
+        int t = tile - tau * p.nzu;
+        for (int i = 2; i <= m - 1; ++i) {  // Y[i] = z_{i+1}
+            Y[i] = t % R;
+            t /= R;
+            b += Y[i];
+        }
+    }
+    const int lp = b + R;
+    double* S = reinterpret_cast<double*>(smem);
+    double* sP = S + p.lpmax;
+    double* sF = sP + p.tab;
+    double* sG = sF + p.tab;
+    const double* gP = p.pmf + (size_t)tau * p.tab;
+    const double* gF = p.cdf + (size_t)tau * p.tab;
+    const double* gG = p.tail + (size_t)tau * p.tab;
+    for (int i = tid; i < p.tab; i += blockDim.x) {
+        sP[i] = gP[i];
+        sF[i] = gF[i];
+        sG[i] = gG[i];
+    }
+    const int taun = tau + 1 == p.P ? 0 : tau + 1;
+    const VT* vblk = reinterpret_cast<const VT*>(p.v_in) + (int64_t)taun * p.nblk;
+    for (int j = tid; j < lp; j += blockDim.x) S[j] = (double)vblk[c_path_offset(j, Y, m, p.pow_r)];
+    __syncthreads();
+    const int G = (R + J - 1) / J;
+    if (tid >= R * G) return;
+    const int z2 = tid / G, z1_0 = (tid - z2 * G) * J;
+    const int N = b + z2;
+    const int kmax = N == 0 ? 0 : max(0, min(N, p.dmax - z1_0));
+    double acc[J] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k <= kmax; ++k) {
+        const double u = S[N - k];
+#pragma unroll
+        for (int i = 0; i < J; ++i) {
+            const int z1 = z1_0 + i;
+            const double w = N == 0 ? (k == 0 ? 1.0 : 0.0)
+                             : k == 0 ? sF[min(z1, p.dmax)]
+                             : k == N ? sG[z1 + N]
+                                      : sP[z1 + k];
+            acc[i] = fma(w, u, acc[i]);
+        }
+    }
+    VT* U = reinterpret_cast<VT*>(p.u);
+    const int64_t base = (int64_t)tile * R * R + (int64_t)z2 * R;
+    const double* r0 = p.r0 + (size_t)tau * R * p.xt;
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+        const int z1 = z1_0 + i;
+        if (z1 < R) U[base + z1] = (VT)(r0[z1 * p.xt + z1 + z2 + b] + p.gamma * acc[i]);
+    }
+}
+
+// One binomial merge of life class j (2 <= j <= m-1).  Block (x, y) = (digit
+// block of 256 lanes, (tau, y_m, r) triple); lanes are the m-1 digits (x_{m-1}..x_1).
+template <typename VT>
+__global__ __launch_bounds__(256) void c_merge_kernel(CDev p, int j, const void* in_,
+                                                      void* out_) {
+    if (!p.extract && p.ctl->stop) return;
+    const int64_t D = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (D >= p.nblk) return;
+    const int R = p.R;
+    const int trip = blockIdx.y;  // tau * npair + pair
+    const int tau = trip / p.npair, pair = trip - tau * p.npair;
+    const int ym = p.pair_y[pair], r = p.pair_r[pair];
+    const double* bq = p.binq + ((size_t)j * R + r) * R;  // Bin(y; r, q_j), y = 0..r
+    const int pwj = p.pow_r[j - 1];
+    const int dj = (int)((D / pwj) % R);
+    double acc = 0.0;
+    if (j == 2) {
+        // input is U[tau][y_m][z_{m-1}..z_1]; digit 1 takes the remaining r - y units
+        const VT* U = reinterpret_cast<const VT*>(in_) + ((int64_t)tau * R + ym) * p.nblk;
+        const int d1 = (int)(D % R);
+        const int64_t rest = D - (int64_t)dj * pwj - d1;
+        for (int y = 0; y <= r; ++y) {
+            const int z2 = min(dj + y, R - 1), z1 = min(d1 + r - y, R - 1);
+            acc = fma(bq[y], (double)U[rest + (int64_t)z2 * pwj + z1], acc);
+        }
+    } else {
+        const VT* T = reinterpret_cast<const VT*>(in_);
+        const int64_t rest = D - (int64_t)dj * pwj;
+        const int pbase = p.pair_base[ym];  // pair index of (y_m, 0)
+        for (int y = 0; y <= r; ++y) {
+            const int zj = min(dj + y, R - 1);
+            const int64_t row = (int64_t)tau * p.npair + pbase + (r - y);
+            acc = fma(bq[y], (double)T[row * p.nblk + rest + (int64_t)zj * pwj], acc);
+        }
+    }
+    reinterpret_cast<VT*>(out_)[(int64_t)trip * p.nblk + D] = (VT)acc;
+}
+
+// Q(tau, x, a) = -C_f [a > 0] + sum_y Bin(y; a, p_m) T_{m-1}(tau, y, x; a - y), then
+// the max over a.  One lane per state.
+template <typename VT, bool EXTRACT>
+__global__ __launch_bounds__(256) void c_final_kernel(CDev p, const void* tin) {
+    __shared__ double red[64];
+    __shared__ double bm[32 * 32];
+    if (!EXTRACT && p.ctl->stop) return;
+    const int R = p.R;
+    for (int i = threadIdx.x; i < R * R; i += blockDim.x) bm[i] = p.binm[i];
+    __syncthreads();
+    const int tau = blockIdx.y;
+    const int64_t D = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
+    if (D < p.nblk) {
+        const VT* T = reinterpret_cast<const VT*>(tin);
+        double best = -DBL_MAX, second = -DBL_MAX;
+        int arg = 0;
+        for (int a = 0; a < R; ++a) {
+            double acc = 0.0;
+            for (int y = 0; y <= a; ++y) {
+                double t;
+                if (p.m == 2) {
+                    // no middle life classes: T_1 is U with digit 1 capped
+                    const VT* U = T + ((int64_t)tau * R + y) * p.nblk;
+                    t = (double)U[min((int)D + (a - y), R - 1)];
+                } else {
+                    const int64_t row = (int64_t)tau * p.npair + p.pair_base[y] + (a - y);
+                    t = (double)T[row * p.nblk + D];
+                }
+                acc = fma(bm[a * R + y], t, acc);
+            }
+            const double q = (a > 0 ? -p.cfixed : 0.0) + acc;
+            if (q > best) {
+                second = best;
+                best = q;
+                arg = a;
+            } else if (q > second) {
+                second = q;
+            }
+        }
+        const int64_t s = (int64_t)tau * p.nblk + D;
+        if (EXTRACT) {
+            p.pi[s] = arg;
+            p.gap[s] = best - second;
+        } else {
+            const double mu = sizeof(VT) == 4 ? p.ctl->mu : 0.0;
+            const VT o = (VT)(best - mu);
+            reinterpret_cast<VT*>(p.v_out)[s] = o;
+            const double out = (double)o;
+            const double dv = out - (double)reinterpret_cast<const VT*>(p.v_in)[s];
+            dmx = dmn = dv;
+            vmx = vmn = out;
+        }
+    }
+    if (EXTRACT) return;
+    block_reduce4(dmx, dmn, vmx, vmn, red);
+    if (threadIdx.x == 0) {
+        double* pp = p.partials + 4 * ((size_t)tau * gridDim.x + blockIdx.x);
+        pp[0] = dmx;
+        pp[1] = dmn;
+        pp[2] = vmx;
+        pp[3] = vmn;
+    }
+}
+
+template <typename VT, bool EXTRACT>
+static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
+    const size_t ubytes = sizeof(double) * ((size_t)p.lpmax + 3 * (size_t)p.tab);
+    if (ubytes > 65536) return hipErrorInvalidConfiguration;
+    const int G = (p.R + 3) / 4;
+    const int threads = ((p.R * G + 63) / 64) * 64;
+    if (threads > 256 || p.R > 32) return hipErrorInvalidConfiguration;
+    if (p.tab < p.R + 4 + p.lpmax || p.tab < p.dmax + 6) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((c_stage_u_kernel<VT>), dim3(p.P * p.nzu), dim3(threads), ubytes, s, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned gx = (unsigned)((p.nblk + 255) / 256);
+    const void* in = p.u;
+    void* bufs[2] = {p.t0, p.t1};
+    for (int j = 2; j <= p.m - 1; ++j) {
+        void* out = bufs[j & 1];
+        hipLaunchKernelGGL((c_merge_kernel<VT>), dim3(gx, p.P * p.npair), dim3(256), 0, s, p, j,
+                           in, out);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        in = out;
+    }
+    hipLaunchKernelGGL((c_final_kernel<VT, EXTRACT>), dim3(gx, p.P), dim3(256), 0, s, p, in);
+    return hipGetLastError();
+}
+
+hipError_t launch_backup_c(const CDev& p, int storage_fp32, int extract, hipStream_t s) {
+    if (extract) return launch_c_t<double, true>(p, s);
+    if (storage_fp32) return launch_c_t<float, false>(p, s);
+    return launch_c_t<double, false>(p, s);
+}
+
+}  // namespace pvi

@@ -27,7 +27,10 @@ static bool is_finite(double x) { return std::isfinite(x); }
 static void build_a_tables(pvi_mdp* p) {
     const int R = p->rad[0], dm = p->dmax[0];
     const auto& P = p->pmf[0];
-    p->tab = dm + 2;
+    // the kernel reads P, F and G at up to X_1 + (path length) + (states per lane):
+    // pad with P = 0, F = 1, G = 0 beyond d_max
+    const int lp_max = (p->m >= 2 ? (p->m - 2) * (R - 1) : 0) + (p->m >= 2 ? R : 1);
+    p->tab = std::max(dm + 10, R + 8 + lp_max);
     p->a_pmf.assign(p->tab, 0.0);
     p->a_cdf.assign(p->tab, 1.0);
     p->a_tail.assign(p->tab, 0.0);
@@ -82,6 +85,169 @@ static void build_a_tables(pvi_mdp* p) {
     }
     p->executed_per_sweep = nh * ex * R;
     p->logical_per_sweep = p->ns * p->na * (int64_t)(dm + 1);
+}
+
+// Scenario B tables (Appendix B reward equation; substitution of the Scenario B
+// description): product-1 demand including substitutes given product-0 unmet
+// demand u, E[u][e] = sum_k Bin(k; u, rho) P1(e - k), and expected revenues.
+static void build_b_tables(pvi_mdp* p) {
+    const int d0 = p->dmax[0], d1 = p->dmax[1], m = p->m;
+    const int R0 = p->rad[0], R1 = p->rad[1];
+    const auto& P0 = p->pmf[0];
+    const auto& P1 = p->pmf[1];
+    const int na = (int)std::pow(R0, m - 1), nb = (int)std::pow(R1, m - 1);
+    p->b_rows = na + d0;
+    p->b_emax = d0 + d1;
+    p->b_ew = p->b_emax + 1;
+    p->b_sw = m * (R1 - 1) + 1;
+    p->b_rexp0.assign((size_t)m * (R0 - 1) + 1, 0.0);
+    for (size_t s0 = 0; s0 < p->b_rexp0.size(); ++s0) {
+        double e = 0.0;
+        for (int d = 0; d <= d0; ++d) e += P0[d] * std::min<double>(d, (double)s0);
+        p->b_rexp0[s0] = p->d.c_rev[0] * e;
+    }
+    const size_t ew = p->b_ew;
+    p->b_epmf.assign((size_t)(d0 + 1) * ew, 0.0);
+    p->b_ecdf.assign((size_t)(d0 + 1) * ew, 1.0);
+    p->b_etail.assign((size_t)(d0 + 1) * ew, 0.0);
+    p->b_rexp1.assign((size_t)(d0 + 1) * p->b_sw, 0.0);
+    for (int u = 0; u <= d0; ++u) {
+        double* E = p->b_epmf.data() + u * ew;
+        for (int k = 0; k <= u; ++k) {
+            const double bk = binom_pmf(k, u, p->d.subst_rho);
+            if (bk == 0.0) continue;
+            for (int d = 0; d <= d1; ++d) E[d + k] += bk * P1[d];
+        }
+        double c = 0.0;
+        for (size_t e = 0; e < ew; ++e) {
+            c += E[e];
+            p->b_ecdf[u * ew + e] = e + 1 == ew ? 1.0 : c;
+        }
+        double t = 0.0;
+        for (int e = (int)ew - 1; e >= 0; --e) {
+            t += E[e];
+            p->b_etail[u * ew + e] = t;
+        }
+        for (int s1 = 0; s1 < p->b_sw; ++s1) {
+            double r = 0.0;
+            for (size_t e = 0; e < ew; ++e) r += E[e] * std::min<double>((double)e, s1);
+            p->b_rexp1[(size_t)u * p->b_sw + s1] = p->d.c_rev[1] * r;
+        }
+    }
+    // stage 1: sum over the FIFO path of each (row, product-1 part); stage 2: d0 terms
+    int64_t ex1 = 0;
+    for (int ib = 0; ib < nb; ++ib)
+        for (int a1 = 0; a1 < R1; ++a1) {
+            int rest = ib, x1 = rest % R1, K = a1;
+            rest /= R1;
+            for (int j = 1; j <= m - 2; ++j) {
+                K += rest % R1;
+                rest /= R1;
+            }
+            for (int u = 0; u <= d0; ++u) {
+                const int emax = d1 + u;
+                const int kmax = K == 0 ? 0 : std::max(0, std::min(K, emax - x1));
+                ex1 += (int64_t)(kmax + 1) * (u == 0 ? na : 1);
+            }
+        }
+    p->executed_per_sweep = ex1 + p->ns * p->na * (int64_t)(d0 + 1);
+    p->logical_per_sweep = p->ns * p->na * (int64_t)(d0 + 1) * (d1 + 1);
+}
+
+// Scenario C tables (Appendix C): per-weekday demand with padding, the expected
+// one-day reward of a post-arrival stock vector z (holding counts the units that
+// expire, as the reward equation writes it), and the binomial factors of the
+// remaining-life multinomial.
+static void build_c_tables(pvi_mdp* p) {
+    const int R = p->rad[0], m = p->m, P = p->P, dm = p->dmax[0];
+    p->c_exogenous = true;
+    for (int k = 2; k <= m; ++k)
+        if (p->d.rul_c1[k - 1] != 0.0) p->c_exogenous = false;
+    p->c_lpmax = (m - 2) * (R - 1) + R;
+    p->c_tab = std::max(dm + 10, R + 8 + p->c_lpmax);
+    const int tab = p->c_tab;
+    p->c_pmf.assign((size_t)P * tab, 0.0);
+    p->c_cdf.assign((size_t)P * tab, 1.0);
+    p->c_tail.assign((size_t)P * tab, 0.0);
+    p->c_xt = m * (R - 1) + 1;
+    p->c_r0.assign((size_t)P * R * p->c_xt, 0.0);
+    const double ch = p->d.c_hold, cs = p->d.c_short, cw = p->d.c_waste;
+    for (int t = 0; t < P; ++t) {
+        const double* Pd = p->pmf[0].data() + (size_t)t * (dm + 1);
+        double c = 0.0;
+        for (int d = 0; d <= dm; ++d) {
+            p->c_pmf[(size_t)t * tab + d] = Pd[d];
+            c += Pd[d];
+            p->c_cdf[(size_t)t * tab + d] = d == dm ? 1.0 : c;
+        }
+        double tl = 0.0;
+        for (int d = dm; d >= 0; --d) {
+            tl += Pd[d];
+            p->c_tail[(size_t)t * tab + d] = tl;
+        }
+        for (int z1 = 0; z1 < R; ++z1)
+            for (int Z = z1; Z < p->c_xt; ++Z) {
+                double e = 0.0;
+                for (int d = 0; d <= dm; ++d)
+                    e += Pd[d] * (-ch * std::max(Z - d, 0) - cs * std::max(d - Z, 0) -
+                                  cw * std::max(z1 - d, 0));
+                p->c_r0[((size_t)t * R + z1) * p->c_xt + Z] = e;
+            }
+    }
+    // life probabilities (order-size independent in the exogenous case: row a = 0)
+    const double* pk = p->life.data();
+    p->c_binq.assign((size_t)m * R * R, 0.0);
+    double cum = pk[0];
+    for (int j = 2; j <= m - 1; ++j) {
+        cum += pk[j - 1];
+        const double q = cum > 0.0 ? pk[j - 1] / cum : 0.0;
+        for (int r = 0; r < R; ++r)
+            for (int y = 0; y <= r; ++y) p->c_binq[((size_t)j * R + r) * R + y] = binom_pmf(y, r, q);
+    }
+    p->c_binm.assign((size_t)R * R, 0.0);
+    for (int a = 0; a < R; ++a)
+        for (int y = 0; y <= a; ++y) p->c_binm[(size_t)a * R + y] = binom_pmf(y, a, pk[m - 1]);
+    p->c_pair_y.clear();
+    p->c_pair_r.clear();
+    p->c_pair_base.assign(R, 0);
+    for (int y = 0; y < R; ++y) {
+        p->c_pair_base[y] = (int32_t)p->c_pair_y.size();
+        for (int r = 0; r + y < R; ++r) {
+            p->c_pair_y.push_back(y);
+            p->c_pair_r.push_back(r);
+        }
+    }
+    p->c_npair = (int)p->c_pair_y.size();
+    // multiply-adds per sweep: U (FIFO path), each merge, and the final order sum
+    const int64_t nblk = p->ns / P;
+    int64_t nzu = 1;
+    for (int i = 0; i < m - 2; ++i) nzu *= R;
+    std::vector<int64_t> cnt(1, 1);
+    for (int i = 0; i < m - 2; ++i) {
+        std::vector<int64_t> nx(cnt.size() + R - 1, 0);
+        for (size_t b = 0; b < cnt.size(); ++b)
+            for (int v = 0; v < R; ++v) nx[b + v] += cnt[b];
+        cnt.swap(nx);
+    }
+    int64_t exu = 0;
+    for (size_t b = 0; b < cnt.size(); ++b)
+        for (int z2 = 0; z2 < R; ++z2)
+            for (int z1 = 0; z1 < R; ++z1) {
+                const int N = (int)b + z2;
+                exu += cnt[b] * ((N == 0 ? 0 : std::max(0, std::min(N, dm - z1))) + 1);
+            }
+    int64_t pair_terms = 0;
+    for (int i = 0; i < p->c_npair; ++i) pair_terms += p->c_pair_r[i] + 1;
+    const int64_t final_terms = (int64_t)R * (R + 1) / 2;
+    p->executed_per_sweep = P * (exu + (int64_t)(m - 2) * pair_terms * nblk + final_terms * nblk);
+    // logical: every (d, y) outcome of every (state, order): (d_max+1) C(a+m-1, m-1)
+    int64_t comps = 0;
+    for (int a = 0; a < R; ++a) {
+        int64_t c = 1;  // C(a+m-1, m-1)
+        for (int i = 1; i <= m - 1; ++i) c = c * (a + i) / i;
+        comps += c;
+    }
+    p->logical_per_sweep = p->ns * comps * (dm + 1);
 }
 
 }  // namespace pvi
@@ -207,6 +373,8 @@ pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out) {
         }
     }
     if (d.family == PVI_FAMILY_LEADTIME) build_a_tables(p);
+    if (d.family == PVI_FAMILY_SUBST2 && d.m >= 2) build_b_tables(p);
+    if (d.family == PVI_FAMILY_RUL_WEEKDAY) build_c_tables(p);
     *out = p;
     return PVI_OK;
 }

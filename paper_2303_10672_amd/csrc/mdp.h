@@ -26,6 +26,16 @@ struct pvi_mdp {
     int tab = 0, xt = 0;
     std::vector<double> a_pmf, a_cdf, a_tail, a_r0;
 
+    // Scenario B kernel tables
+    int b_rows = 0, b_emax = 0, b_ew = 0, b_sw = 0;
+    std::vector<double> b_rexp0, b_epmf, b_ecdf, b_etail, b_rexp1;
+
+    // Scenario C kernel tables
+    bool c_exogenous = true;
+    int c_tab = 0, c_xt = 0, c_lpmax = 0, c_npair = 0;
+    std::vector<double> c_pmf, c_cdf, c_tail, c_r0, c_binq, c_binm;
+    std::vector<int32_t> c_pair_y, c_pair_r, c_pair_base;
+
     int64_t logical_per_sweep = 0;
     int64_t executed_per_sweep = 0;
 
@@ -42,12 +52,21 @@ struct pvi_mdp {
         pvi::Ctl* ctl = nullptr;
         pvi::Ctl* h_ctl = nullptr;  // pinned host mirror
         double *pmf = nullptr, *cdf = nullptr, *tail = nullptr, *r0 = nullptr;
+        double *z = nullptr, *rexp0 = nullptr, *epmf = nullptr, *ecdf = nullptr,
+               *etail = nullptr, *rexp1 = nullptr;
+        void *cu = nullptr, *ct0 = nullptr, *ct1 = nullptr;
+        double *cpmf = nullptr, *ccdf = nullptr, *ctail = nullptr, *cr0 = nullptr,
+               *cbinq = nullptr, *cbinm = nullptr;
+        int32_t *cpy = nullptr, *cpr = nullptr, *cpb = nullptr;
         int tiles = 0;
         size_t bytes = 0;
         std::vector<hipEvent_t> ev;
     } dev;
 
-    // results of the last solve
+    // results of the last solve; have_result = 2 means they are in the host
+    // vectors below (batched solves of the request server)
+    std::vector<double> h_v, h_gap;
+    std::vector<int32_t> h_pi;
     int have_result = 0;
     int ret_buf = 0;  // v64 buffer holding V
     std::mutex mu;

@@ -66,7 +66,65 @@ struct ADev {
     double gamma, cvar;
 };
 
-struct Tables;  // host tables (tables.cpp)
+// ------------------------------------------------------------------ family B
+#define PVI_B_R1MAX 16  // product-1 order choices per kernel row (a_max[1] <= 15)
+struct BDev {
+    const void* v_in;
+    void* v_out;
+    int32_t* pi;
+    double* gap;
+    double* partials;   // [nb][4]
+    double* z;          // [rows][nb * r1] stage-1 table
+    const double* pmf0;   // [d0max+1]
+    const double* rexp0;  // [stock0]: c_rev0 E[min(d0, stock0)]
+    const double* e_pmf;  // [d0max+1][ew]: product-1 demand incl. substitutes, given u0
+    const double* e_cdf;
+    const double* e_tail;
+    const double* rexp1;  // [d0max+1][sw]: c_rev1 E[min(e, stock1) | u0]
+    Ctl* ctl;
+    int32_t m, r0, r1, r1pad, na, nb, rows, d0max, emax, ew, sw, extract;
+    double gamma, cvar0, cvar1;
+};
+
+
+// ------------------------------------------------------------------ family C
+struct CDev {
+    const void* v_in;
+    void* v_out;
+    int32_t* pi;
+    double* gap;
+    double* partials;     // [P * ceil(nblk/256)][4]
+    void* u;              // U[tau][z_m][z_{m-1}..z_1]
+    void* t0;             // merge ping-pong tables [tau][(y_m, r)][digits]
+    void* t1;
+    const double* pmf;    // [P][tab] per-weekday demand, zero past d_max
+    const double* cdf;    // [P][tab], one past d_max
+    const double* tail;   // [P][tab], zero past d_max
+    const double* r0;     // [P][R][xt] expected one-day reward of post-arrival stock
+    const double* binq;   // [m][R][R] Bin(y; r, q_j)
+    const double* binm;   // [R][R] Bin(y; a, p_m)
+    const int32_t* pair_y;
+    const int32_t* pair_r;
+    const int32_t* pair_base;
+    Ctl* ctl;
+    int64_t nblk;         // R^(m-1) states per weekday
+    int32_t R, m, P, nzu, npair, tab, xt, lpmax, dmax, extract;
+    int32_t pow_r[10];
+    double gamma, cfixed;
+};
+
+// ------------------------------------------------------------------ batched small instances
+struct BatchItem {
+    int32_t m, R, dmax, tab, xt, ns, nh, stride_a, stride_h, max_sweeps, fixed, fp32;
+    double gamma, cvar, thr;
+    const double *pmf, *cdf, *tail, *r0;  // scenario-A tables of this instance
+    double* v;                            // [ns] returned V (FP64)
+    int32_t* pi;                          // [ns] policy
+    double* gap;                          // [ns] best - second Q
+    double* stats;  // [8]: sweeps fp32, sweeps fp64, span, dmax, dmin, status
+};
+hipError_t launch_batch(const BatchItem* d_items, int n, size_t lds_bytes, int rmax,
+                        hipStream_t s);
 
 // launchers (kernels_a.hip)
 hipError_t launch_backup_a(const ADev& p, int storage_fp32, int acc_kahan, int extract,
@@ -77,5 +135,9 @@ hipError_t launch_to_f64(const float* v32, double* v64, const Ctl* ctl, int64_t 
                          hipStream_t s);
 hipError_t launch_to_f32(const double* v64, float* v32, double c, int64_t n, hipStream_t s);
 hipError_t launch_fill(double* v, double value, int64_t n, hipStream_t s);
+// kernels_c.hip
+hipError_t launch_backup_c(const CDev& p, int storage_fp32, int extract, hipStream_t s);
+// kernels_b.hip
+hipError_t launch_backup_b(const BDev& p, int storage_fp32, int extract, hipStream_t s);
 
 }  // namespace pvi

@@ -290,12 +290,14 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* o, pvi_result* res) {
         res->status = converged ? PVI_OK : PVI_E_NOT_CONVERGED;
         res->sweeps_fp32 = o32.sweeps;
         res->sweeps_fp64 = fp64_phase ? o64.sweeps : 0;
-        res->backup_launches = o32.timed + o64.timed;
+        res->backup_launches[0] = o64.timed;
+        res->backup_launches[1] = o32.timed;
         res->final_span = h.span;
         res->threshold = thr;
         res->dmax = h.dmax;
         res->dmin = h.dmin;
-        res->backup_ms = o32.backup_ms + o64.backup_ms;
+        res->backup_ms[0] = o64.backup_ms;
+        res->backup_ms[1] = o32.backup_ms;
         const int64_t sweeps = res->sweeps_fp32 + res->sweeps_fp64 + 1;
         res->logical_backups = p->logical_per_sweep * sweeps;
         res->executed_terms = p->executed_per_sweep * sweeps;
@@ -347,6 +349,11 @@ pvi_status policy_get(const pvi_mdp* cp, int32_t* policy, double* q_gap) {
     if (!p || !policy) return fail(PVI_E_INVALID, "policy_get: NULL argument");
     std::lock_guard<std::mutex> lock(p->mu);
     if (!p->have_result) return fail(PVI_E_NOT_READY, "policy_get: no solve has completed");
+    if (p->have_result == 2) {
+        std::memcpy(policy, p->h_pi.data(), sizeof(int32_t) * p->ns);
+        if (q_gap) std::memcpy(q_gap, p->h_gap.data(), sizeof(double) * p->ns);
+        return PVI_OK;
+    }
     PVI_HIP(hipSetDevice(p->dev.device));
     PVI_HIP(hipMemcpy(policy, p->dev.pi, sizeof(int32_t) * p->ns, hipMemcpyDeviceToHost));
     if (q_gap) PVI_HIP(hipMemcpy(q_gap, p->dev.gap, sizeof(double) * p->ns, hipMemcpyDeviceToHost));
@@ -358,6 +365,10 @@ pvi_status value_get(const pvi_mdp* cp, double* v) {
     if (!p || !v) return fail(PVI_E_INVALID, "value_get: NULL argument");
     std::lock_guard<std::mutex> lock(p->mu);
     if (!p->have_result) return fail(PVI_E_NOT_READY, "value_get: no solve has completed");
+    if (p->have_result == 2) {
+        std::memcpy(v, p->h_v.data(), sizeof(double) * p->ns);
+        return PVI_OK;
+    }
     PVI_HIP(hipSetDevice(p->dev.device));
     PVI_HIP(hipMemcpy(v, p->dev.v64[p->ret_buf], sizeof(double) * p->ns, hipMemcpyDeviceToHost));
     return PVI_OK;
@@ -368,6 +379,13 @@ pvi_status policy_get_device(const pvi_mdp* cp, int32_t* d_policy, void* stream)
     if (!p || !d_policy) return fail(PVI_E_INVALID, "policy_get_device: NULL argument");
     std::lock_guard<std::mutex> lock(p->mu);
     if (!p->have_result) return fail(PVI_E_NOT_READY, "policy_get_device: no solve yet");
+    if (p->have_result == 2) {
+        hipStream_t s2 = (hipStream_t)stream;
+        PVI_HIP(hipMemcpyAsync(d_policy, p->h_pi.data(), sizeof(int32_t) * p->ns,
+                               hipMemcpyHostToDevice, s2));
+        PVI_HIP(hipStreamSynchronize(s2));
+        return PVI_OK;
+    }
     PVI_HIP(hipSetDevice(p->dev.device));
     hipStream_t s = stream ? (hipStream_t)stream : p->dev.own;
     PVI_HIP(hipMemcpyAsync(d_policy, p->dev.pi, sizeof(int32_t) * p->ns,

@@ -62,15 +62,19 @@ class Opts(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int32), ("sweeps_fp32", ctypes.c_int32),
-        ("sweeps_fp64", ctypes.c_int32), ("backup_launches", ctypes.c_int32),
+        ("sweeps_fp64", ctypes.c_int32), ("backup_launches", ctypes.c_int32 * 2),
         ("final_span", ctypes.c_double), ("threshold", ctypes.c_double),
         ("dmax", ctypes.c_double), ("dmin", ctypes.c_double), ("wall_ms", ctypes.c_double),
-        ("backup_ms", ctypes.c_double), ("logical_backups", ctypes.c_int64),
+        ("backup_ms", ctypes.c_double * 2), ("logical_backups", ctypes.c_int64),
         ("executed_terms", ctypes.c_int64),
     ]
 
     def to_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
 
 
 _lib = None
@@ -301,3 +305,80 @@ def policy_get_device(m, d_policy_ptr, stream=None):
 
 def last_error():
     return load().pvi_last_error().decode(errors="replace")
+
+
+class Server:
+    """Request server (pvi_server_*): continuous batching of solves on one GPU."""
+
+    def __init__(self, hbm_budget_bytes=0, small_batch=256):
+        load()
+        h = ctypes.c_void_p()
+        _check(_lib.pvi_server_create(int(hbm_budget_bytes), int(small_batch), ctypes.byref(h)),
+               "pvi_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def close(self):
+        h, self.handle = self.handle, None
+        if h:
+            _check(_lib.pvi_server_destroy(h), "pvi_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, mdps, precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0):
+        """vi_batch_submit: returns one ticket per MDP (same options for all)."""
+        n = len(mdps)
+        arr = (ctypes.c_void_p * n)(*[m.handle for m in mdps])
+        o = make_opts(precision, eps, max_sweeps, fixed_sweeps, None, None, 0, False,
+                      mdps[0].sc if n else None)
+        t = (ctypes.c_uint64 * n)()
+        _check(_lib.vi_batch_submit(self.handle, arr, ctypes.byref(o), n, t), "vi_batch_submit")
+        tickets = list(t)
+        for tk, m in zip(tickets, mdps):
+            self._keep[tk] = m
+        return tickets
+
+    def poll(self, ticket):
+        r = Result()
+        st = _lib.vi_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(r))
+        return st, (r.to_dict() if st != PVI_E_NOT_READY else None)
+
+    def wait(self, ticket, timeout_us=-1):
+        r = Result()
+        st = _lib.vi_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_us), ctypes.byref(r))
+        return st, r.to_dict()
+
+    def stats(self):
+        p50, p99 = ctypes.c_double(), ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(_lib.pvi_server_stats(self.handle, ctypes.byref(p50), ctypes.byref(p99),
+                                     ctypes.byref(n)), "pvi_server_stats")
+        return {"p50_ms": p50.value, "p99_ms": p99.value, "completed": n.value}
+
+
+def pvi_server_create(hbm_budget_bytes=0, small_batch=256):
+    return Server(hbm_budget_bytes, small_batch)
+
+
+def pvi_server_destroy(server):
+    server.close()
+
+
+def vi_batch_submit(server, mdps, **kw):
+    return server.submit(mdps, **kw)
+
+
+def vi_poll(server, ticket):
+    return server.poll(ticket)
+
+
+def vi_wait(server, ticket, timeout_us=-1):
+    return server.wait(ticket, timeout_us)
+
+
+def pvi_server_stats(server):
+    return server.stats()

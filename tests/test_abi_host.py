@@ -32,7 +32,7 @@ def test_struct_sizes_match_header_layout():
     # pvi_mdp_desc: 5 int32 + 3x2 int32 + 2x7x2 doubles + 2 ptrs + 16 doubles + ...
     assert ctypes.sizeof(pvi.Desc) % 8 == 0
     assert ctypes.sizeof(pvi.Opts) == 48
-    assert ctypes.sizeof(pvi.Result) == 80
+    assert ctypes.sizeof(pvi.Result) == 96
 
 
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3])

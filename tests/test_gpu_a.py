@@ -26,6 +26,9 @@ SMALL = [
     W.scenario_a(m=4, L=1, a_max=6, d_max=12),
     W.scenario_a(m=2, L=3, a_max=5, d_max=4),     # d_max < a_max: clipped demand paths
     W.scenario_a(m=5, L=1, a_max=4, d_max=25),
+    W.scenario_a(m=2, L=1, a_max=31, d_max=40),   # 32 actions: the widest kernel
+    W.scenario_a(m=3, L=1, a_max=25, d_max=33,
+                 demand={"kind": "negbin", "mean": [6.0], "n": [3.0]}),
 ]
 IDS = [f"m{s['m']}L{s['L']}R{s['a_max'][0] + 1}D{s['d_max'][0]}" for s in SMALL]
 

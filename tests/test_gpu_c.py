@@ -1,0 +1,97 @@
+"""GPU parity of scenario C (weekday demand, random remaining life) through the C ABI.
+
+Tolerances as for scenarios A and B.  The oracle enumerates every (demand,
+arrival split) outcome; the GPU sums the same outcomes in two exact stages.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.oracle import Oracle
+from paper_2303_10672_amd import pvi
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [
+    W.scenario_c(m=3, a_max=4, d_max=8, means=[3.0, 4.0, 3.5, 5.0, 4.5, 2.0, 2.5],
+                 n=[5.0, 3.0, 4.0, 6.0, 5.0, 2.0, 3.0], c0=[0.0, 0.8, 1.5]),
+    W.scenario_c(m=4, a_max=3, d_max=6, n_periods=3, means=[2.0, 3.0, 2.5], n=[4.0, 5.0, 3.0],
+                 c0=[0.0, 0.5, 1.0, 2.0]),
+    W.scenario_c(m=2, a_max=5, d_max=7, n_periods=2, means=[3.0, 4.0], n=[5.0, 5.0],
+                 c0=[0.0, 1.0]),
+    W.scenario_c(m=5, a_max=3, d_max=5, n_periods=2, means=[2.0, 2.5], n=[5.0, 4.0],
+                 c0=[0.0, 1.6, 2.6, 2.8, 1.6]),
+    W.scenario_c(m=3, a_max=9, d_max=12, n_periods=7, c0=[0.0, 2.0, 0.5]),
+]
+IDS = ["m3-P7", "m4-P3", "m2-P2", "m5-P2", "m3-R10"]
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def vhat(V, res, g):
+    return V + g / (1.0 - g) * 0.5 * (res["dmax"] + res["dmin"])
+
+
+@pytest.mark.parametrize("sc", SMALL, ids=IDS)
+def test_one_backup(sc):
+    o = Oracle(sc)
+    m = pvi.mdp_create(sc)
+    V = W.random_values(o.n_states, seed=21, scale=20.0, offset=-300.0)
+    Vo, pio, gapo = o.sweep(V)
+    Vg, pig, gapg = pvi.vi_backup(m, V, "fp64")
+    assert relerr(Vg, Vo) < 1e-12
+    clear = gapo > 1e-9
+    assert np.array_equal(pig[clear], pio[clear])
+    assert np.allclose(gapg[clear], gapo[clear], rtol=1e-8, atol=1e-9)
+    V32, _, _ = pvi.vi_backup(m, V, "fp32")
+    assert relerr(V32, Vo) < 1e-6
+
+
+@pytest.mark.parametrize("sc", SMALL, ids=IDS)
+def test_converged(sc):
+    o = Oracle(sc)
+    ref = o.solve()
+    tight = o.solve(thr=1e-11)
+    m = pvi.mdp_create(sc)
+    res = pvi.vi_solve(m, precision="fp64")
+    assert res["sweeps_fp64"] == ref["sweeps"]
+    assert relerr(pvi.value_get(m), ref["V"]) < 1e-12
+    pol, _ = pvi.policy_get(m)
+    clear = tight["gap"] > 1e-6
+    assert np.array_equal(pol[clear], tight["pi"][clear])
+    g = sc["gamma"]
+    res = pvi.vi_solve(m, precision="fp32")
+    assert res["final_span"] < res["threshold"]
+    assert relerr(vhat(pvi.value_get(m), res, g), vhat(ref["V"], ref, g)) < 1e-5
+    pol, _ = pvi.policy_get(m)
+    assert np.array_equal(pol[clear], tight["pi"][clear])
+
+
+def test_endogenous_life_is_rejected_loudly():
+    sc = W.scenario_c(m=3, a_max=4, d_max=8, c1=[0.0, 0.1, -0.1])
+    m = pvi.mdp_create(sc)
+    with pytest.raises(pvi.PviError) as e:
+        pvi.vi_solve(m)
+    assert e.value.status == pvi.PVI_E_INVALID
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    sc = W.config3()
+    return sc, Oracle(sc), pvi.mdp_create(sc)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_config3_one_backup_sampled(cfg3, prec, tol):
+    sc, o, m = cfg3
+    V = W.random_values(o.n_states, seed=13, scale=30.0, offset=-900.0)
+    Vg, pig, _ = pvi.vi_backup(m, V, prec)
+    idx = W.sample_indices(o.n_states, 12, seed=5)
+    q = o.q_states(V, idx)
+    Vo = q.max(axis=1)
+    assert float(np.abs(Vg[idx] - Vo).max() / np.abs(Vo).max()) < tol
+    qs = np.sort(q, axis=1)
+    clear = (qs[:, -1] - qs[:, -2]) > 1e-9
+    assert np.array_equal(pig[idx][clear], q.argmax(axis=1)[clear])
