@@ -31,11 +31,26 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32_wide", choices=["fp32", "fp32_wide", "fp64"])
-    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--precision", default="fp64", choices=["fp32", "fp32_wide", "fp64"],
+                    help="precision of the headline solve; the other schedule is timed "
+                         "beside it (fp32_wide beside fp64, fp64 beside an FP32 mode)")
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="steps of the companion solve (default: steps // 2)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="config1", choices=["config1", "batch", "serving",
+                                                               "config2", "config3"],
+                    help="config1 (default, the headline), batch (many small solves: "
+                         "batched FP32 kernel vs one FP64 solve per call), serving (the "
+                         "request mix through the server), config2/config3 (one solve)")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="serving arrival rate per second (0: 0.7 x closed-loop rate)")
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (a known-traffic "
+                         "kernel for scaling HBM counters)")
     return ap.parse_args()
 
 
@@ -97,6 +112,135 @@ def cpu_baseline(sc, target_s):
                       f"of the {o.n_states} states, {dt:.1f} s"}
 
 
+def bench_batch(args, pvi, W):
+    """Many small scenario-A solves: one batched FP32 launch vs one FP64 solve per call."""
+    import torch
+    reqs = W.serving_mix(n_requests=4 * args.batch, seed=7, large_fraction=0.0, c_fraction=0.0)
+    scs = [sc for _, sc in reqs][:args.batch]
+    out = {}
+    for label, prec in (("batched_fp32", "fp32"), ("batched_fp64", "fp64")):
+        srv = pvi.Server(small_batch=args.batch)
+        warm = [pvi.mdp_create(sc) for sc in scs]
+        for t in srv.submit(warm, precision=prec):
+            srv.wait(t)
+        mdps = [pvi.mdp_create(sc) for sc in scs]
+        t0 = time.perf_counter()
+        ts = srv.submit(mdps, precision=prec)
+        res = [srv.wait(t)[1] for t in ts]
+        dt = time.perf_counter() - t0
+        srv.close()
+        logical = sum(r["logical_backups"] for r in res)
+        out[label] = {"solves_per_s": len(scs) / dt, "backups_per_s": logical / dt,
+                      "wall_ms": dt * 1e3}
+    mdps = [pvi.mdp_create(sc) for sc in scs]
+    pvi.vi_solve(mdps[0], precision="fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    logical = 0
+    for m in mdps:
+        logical += pvi.vi_solve(m, precision="fp64")["logical_backups"]
+    dt = time.perf_counter() - t0
+    out["one_solve_per_call_fp64"] = {"solves_per_s": len(scs) / dt,
+                                      "backups_per_s": logical / dt, "wall_ms": dt * 1e3}
+    b = out["batched_fp32"]
+    line = {
+        "metric": "small-instance solves/s: batched FP32 launch vs one FP64 solve per call",
+        "value": b["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(scs)} scenario-A instances, m in 2..3, L=1, order <= 10, "
+                               "Poisson(4) folded at 20, seeded cost jitter, gamma 0.99"},
+        "speedup_vs_one_solve_per_call_fp64": b["solves_per_s"] /
+        out["one_solve_per_call_fp64"]["solves_per_s"],
+        "detail": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serving(args, pvi, W):
+    """The request mix through the server: arrivals on a clock, p50/p99 latency."""
+    import threading
+    import torch
+    import numpy as np
+    mix = W.serving_mix(n_requests=args.requests, rate_per_s=1.0, seed=4)
+    scs = [sc for _, sc in mix]
+    gaps = np.diff([0.0] + [t for t, _ in mix])          # unit-rate inter-arrival times
+    # closed-loop pre-run on a prefix gives the saturated rate
+    srv = pvi.Server(small_batch=args.batch)
+    pre = scs[:min(200, len(scs))]
+    t0 = time.perf_counter()
+    ts = [srv.submit([pvi.mdp_create(sc)], precision="fp32")[0] for sc in pre]
+    for t in ts:
+        srv.wait(t)
+    sat = len(pre) / (time.perf_counter() - t0)
+    srv.close()
+    rate = args.rate if args.rate > 0 else 0.7 * sat
+    mdps = [pvi.mdp_create(sc) for sc in scs]
+    srv = pvi.Server(small_batch=args.batch)
+    tickets = [None] * len(mdps)
+    start = time.perf_counter()
+
+    def submitter():
+        t_next = start
+        for i, m in enumerate(mdps):
+            t_next += gaps[i] / rate
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = srv.submit([m], precision="fp32")[0]
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    status = [srv.wait(t) for t in tickets]
+    wall = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    lat = np.array([s[1]["wall_ms"] for s in status])
+    fam = np.array([sc["family"] + ("L" if sc["family"] == "A" and sc["m"] == 4 else "")
+                    for sc in scs])
+    per = {}
+    for f in sorted(set(fam)):
+        x = lat[fam == f]
+        per[f] = {"n": int(x.size), "p50_ms": float(np.percentile(x, 50)),
+                  "p99_ms": float(np.percentile(x, 99))}
+    ok = sum(1 for s in status if s[0] == pvi.PVI_OK)
+    line = {
+        "metric": "serving mix solves/s; p50/p99 solve latency (arrival to result)",
+        "value": len(mdps) / wall, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(mdps)} requests, exponential arrivals at {rate:.1f}/s "
+                               "(0.7 x closed-loop rate unless given); 70% small A, 25% C "
+                               "with order cap 10..20, 5% the m=4 L=2 A instance; FP32 "
+                               "schedule with FP64 check and polish"},
+        "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"]},
+        "per_class": per, "closed_loop_rate": sat, "completed_ok": ok,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_single(args, pvi, W, cfg):
+    """One full solve of config 2 or 3, FP64 and FP32 schedules."""
+    sc = W.config_by_index(cfg)
+    m = pvi.mdp_create(sc)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        pvi.vi_solve(m, precision=prec, max_sweeps=20000, allow_not_converged=True)
+        t0 = time.perf_counter()
+        r = pvi.vi_solve(m, precision=prec, max_sweeps=20000, time_kernels=True,
+                         allow_not_converged=True)
+        dt = time.perf_counter() - t0
+        out[prec] = {"backups_per_s": r["logical_backups"] / dt, "solve_ms": dt * 1e3,
+                     "sweeps_fp32": r["sweeps_fp32"], "sweeps_fp64": r["sweeps_fp64"],
+                     "status": r["status"], "executed_terms": r["executed_terms"],
+                     "backup_ms": list(r["backup_ms"]),
+                     "backup_launches": list(r["backup_launches"])}
+    line = {"metric": METRIC, "value": max(o["backups_per_s"] for o in out.values()),
+            "unit": "backups/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": f"config {cfg} one solve"}, "detail": out}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -109,6 +253,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return bench_batch(args, pvi, W)
+    if args.workload == "serving":
+        return bench_serving(args, pvi, W)
+    if args.workload in ("config2", "config3"):
+        return bench_single(args, pvi, W, int(args.workload[-1]))
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sc = W.config1()
     m = pvi.mdp_create(sc)
     stream = torch.cuda.Stream()
@@ -116,8 +273,10 @@ def main():
 
     main_run = time_solves(pvi, m, args.precision, args.steps, args.warmup, handle)
     fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
-    fp64_run = time_solves(pvi, m, "fp64", fp64_steps, 1, handle) \
-        if args.precision != "fp64" else main_run
+    other = "fp32_wide" if args.precision == "fp64" else "fp64"
+    other_run = time_solves(pvi, m, other, fp64_steps, 1, handle)
+    fp64_run = main_run if args.precision == "fp64" else other_run
+    fp32_run = other_run if args.precision == "fp64" else main_run
 
     value = main_run["logical"] / main_run["wall_s"]
     ms_per_step = main_run["wall_s"] * 1e3 / args.steps
@@ -158,11 +317,21 @@ def main():
                        "p99": percentile(main_run["lat_ms"], 0.99)},
         "fp64_plain": {
             "value": fp64_run["logical"] / fp64_run["wall_s"],
-            "ms_per_solve": fp64_run["wall_s"] * 1e3 / max(fp64_steps, 1),
+            "ms_per_solve": percentile(fp64_run["lat_ms"], 0.5),
             "sweeps": fp64_run["sweeps_fp64"] + 1,
             "avg_backup_kernel_ms": fp64_run["backup_ms"][0] / max(fp64_run["launches"][0], 1),
             "latency_ms": {"p50": percentile(fp64_run["lat_ms"], 0.5),
                            "p99": percentile(fp64_run["lat_ms"], 0.99)},
+        },
+        "fp32_schedule": {
+            "mode": args.precision if args.precision != "fp64" else "fp32_wide",
+            "value": fp32_run["logical"] / fp32_run["wall_s"],
+            "ms_per_solve": percentile(fp32_run["lat_ms"], 0.5),
+            "sweeps": {"fp32": fp32_run["sweeps_fp32"], "fp64": fp32_run["sweeps_fp64"],
+                       "extract": 1},
+            "avg_backup_kernel_ms": {
+                "fp32_storage": fp32_run["backup_ms"][1] / max(fp32_run["launches"][1], 1),
+                "fp64_polish": fp32_run["backup_ms"][0] / max(fp32_run["launches"][0], 1)},
         },
         "roofline": {
             "bound": "hbm",

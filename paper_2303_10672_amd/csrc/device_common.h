@@ -3,6 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
+#include <cmath>
+
+#include "pvi_internal.h"
+
 namespace pvi {
 
 __device__ __forceinline__ int xcd_remap(int bid, int nb) {
@@ -42,6 +47,44 @@ __device__ inline void block_reduce4(double& a, double& b, double& c, double& d,
             c = fmax(c, red[4 * i + 2]);
             d = fmin(d, red[4 * i + 3]);
         }
+    }
+}
+
+// Stopping rule applied to the reduced (max dv, min dv, max v', min v') of one sweep.
+// With FP32 storage (V = c + v) it also moves the centring: c <- gamma c + mu and
+// mu <- mu + mid(v').  Called by one thread after the whole sweep is reduced.
+__device__ inline void span_update(Ctl* ctl, double a0, double a1, double a2, double a3,
+                                   int fp32, int fixed, double gamma) {
+    double dmax = a0, dmin = a1;
+    if (fp32) {
+        const double shift = (gamma - 1.0) * ctl->c + ctl->mu;
+        dmax += shift;
+        dmin += shift;
+        ctl->c = gamma * ctl->c + ctl->mu;
+        ctl->mu += 0.5 * (a2 + a3);
+    }
+    const double span = dmax - dmin;
+    ctl->dmax = dmax;
+    ctl->dmin = dmin;
+    ctl->span = span;
+    ctl->sweeps += 1;
+    if (fixed) return;
+    if (fp32) {
+        const double vabs = fmax(fabs(a2), fabs(a3));
+        ctl->vabs = vabs;
+        if (span < ctl->best_span * 0.999) {
+            ctl->best_span = span;
+            ctl->stall = 0;
+        } else {
+            ctl->stall += 1;
+        }
+        if (span < ctl->thr || span <= ctl->floor32 * vabs || ctl->stall >= 3) {
+            ctl->stop = 1;
+            ctl->stop_sweep = ctl->sweeps;
+        }
+    } else if (span < ctl->thr) {
+        ctl->stop = 1;
+        ctl->stop_sweep = ctl->sweeps;
     }
 }
 

@@ -43,7 +43,7 @@ static BDev make_bdev(const pvi_mdp* p) {
     b.m = p->m;
     b.r0 = p->rad[0];
     b.r1 = p->rad[1];
-    b.r1pad = PVI_B_R1MAX;
+    b.r1pad = PVI_B_R1MAX + 2;  // row stride of the LDS Z block: 16-byte rows, fewer bank conflicts
     b.na = (int)ipow(p->rad[0], p->m - 1);
     b.nb = (int)ipow(p->rad[1], p->m - 1);
     b.rows = p->b_rows;
@@ -113,7 +113,7 @@ std::string family_support_msg(const pvi_mdp* p) {
     if (p->family == PVI_FAMILY_SUBST2) {
         if (p->m < 2) return "scenario B needs m >= 2 on the GPU";
         if (p->rad[1] > PVI_B_R1MAX) return "scenario B needs a_max[1] <= 15 on the GPU";
-        const size_t lds = sizeof(double) * ((size_t)p->b_rows * PVI_B_R1MAX + p->dmax[0] + 65);
+        const size_t lds = sizeof(double) * ((size_t)p->b_rows * (PVI_B_R1MAX + 2) + p->dmax[0] + 65);
         if (lds > 65536) return "scenario B stage-2 table exceeds LDS (too many product-0 states)";
         return "ok";
     }
@@ -210,12 +210,18 @@ void family_free(pvi_mdp* p) {
     d.cpy = d.cpr = d.cpb = nullptr;
 }
 
-hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, const void* vin,
-                         void* vout, hipStream_t s) {
+// No family fuses the span today: a device-wide release fence per workgroup (needed
+// for a last-workgroup reduction) writes back L2 on every XCD and cost more than
+// the separate single-workgroup span launch it would save.
+bool family_fused_span(const pvi_mdp*) { return false; }
+
+hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, int fixed,
+                         const void* vin, void* vout, hipStream_t s) {
     if (p->family == PVI_FAMILY_LEADTIME) {
         ADev a = make_adev(p);
         a.v_in = vin;
         a.v_out = vout;
+        a.fixed = fixed;
         return launch_backup_a(a, fp32, kahan, extract, s);
     }
     if (p->family == PVI_FAMILY_SUBST2) {

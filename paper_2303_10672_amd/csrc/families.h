@@ -15,7 +15,11 @@ pvi_status family_init(pvi_mdp* p);            // upload family tables
 void family_free(pvi_mdp* p);
 // One backup sweep vin -> vout (FP32 centred or FP64 storage), or, with
 // extract = 1, the FP64 policy/gap extraction of vin.
-hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, const void* vin,
-                         void* vout, hipStream_t s);
+// fixed = 1: the sweep belongs to a fixed-length run (no stopping rule).
+hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, int fixed,
+                         const void* vin, void* vout, hipStream_t s);
+// True when the family's backup kernel reduces the span itself (its last
+// workgroup applies the stopping rule), so no separate span launch follows it.
+bool family_fused_span(const pvi_mdp* p);
 
 }  // namespace pvi

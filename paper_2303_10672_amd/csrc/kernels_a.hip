@@ -72,6 +72,17 @@ __device__ __forceinline__ double lane_of<double, 2>(const double2& v, int i) {
     return i == 0 ? v.x : v.y;
 }
 
+template <typename VT>
+__device__ __forceinline__ typename VecLoad<VT>::V make_vec(const VT* v);
+template <>
+__device__ __forceinline__ float4 make_vec<float>(const float* v) {
+    return make_float4(v[0], v[1], v[2], v[3]);
+}
+template <>
+__device__ __forceinline__ double2 make_vec<double>(const double* v) {
+    return make_double2(v[0], v[1]);
+}
+
 // Accumulator over outcomes: FP64 multiply-add, or FP32 with Kahan compensation.
 template <typename VT, bool KAHAN>
 struct Acc {
@@ -95,18 +106,26 @@ struct Acc<float, true> {
 
 // VT: storage type of V (float = centred FP32, double = FP64).
 // KAHAN: FP32 compensated accumulation (only with VT = float); otherwise FP64.
-// J: states (consecutive X_1) per lane.  Lanes with the same X_2 read the same
-//    staged values, so each value read from LDS feeds J multiply-adds; this keeps
-//    the LDS return path from limiting the kernel.
+// Lanes: (X_2, group of J consecutive X_1, half of the actions).  Lanes with the
+//   same X_2 read the same staged values, so each LDS value feeds J multiply-adds;
+//   splitting the actions over two neighbouring lanes halves the accumulator
+//   registers, which doubles the waves a SIMD can hold.  The two halves merge
+//   their best and second-best Q with one lane shuffle (lower actions win ties).
+// Weights: k = 0 takes P(D <= X_1), 0 < k < N takes P(X_1 + k) (a shift register
+//   over X_1 needs one new table value per step), k = N takes P(D >= X_1 + N);
+//   the tables are zero (one for the CDF) past d_max, so clipping needs no test.
 // EXTRACT: write policy and Q gap instead of V (FP64 only).
-template <typename VT, bool KAHAN, int RMAX, int J, bool EXTRACT>
+template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
 __global__ __launch_bounds__(512) void backup_a_kernel(ADev p) {
     extern __shared__ __align__(16) unsigned char smem[];
     Ctl* ctl = p.ctl;
     if (!EXTRACT && ctl->stop) return;
+    constexpr int J = 4;
+    constexpr int RH = RMAX / 2;
     constexpr int W = VecLoad<VT>::W;
     using VV = typename VecLoad<VT>::V;
     using AW = typename Acc<VT, KAHAN>::W;
+    static_assert(RH % W == 0, "half row must be a whole number of vectors");
 
     const int R = p.R, m = p.m, tid = threadIdx.x, bs = blockDim.x;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -137,40 +156,40 @@ __global__ __launch_bounds__(512) void backup_a_kernel(ADev p) {
     }
     const VT* vin = reinterpret_cast<const VT*>(p.v_in);
     const int64_t hbase = (int64_t)h * p.stride_h;
-    for (int idx = tid; idx < lp * RMAX; idx += bs) {
-        const int a = idx / lp, j = idx - a * lp;
-        VT v = VT(0);
-        if (a < R) v = vin[(int64_t)a * p.stride_a + hbase + path_offset(j, Y, m, p.pow_y)];
-        S[j * RMAX + a] = v;
+    // one lane per path point: its block offset once, then every action's value
+    for (int j = tid; j < lp; j += bs) {
+        const VT* src = vin + hbase + path_offset(j, Y, m, p.pow_y);
+        VV* dst = reinterpret_cast<VV*>(S + j * RMAX);
+#pragma unroll
+        for (int q = 0; q < RMAX / W; ++q) {
+            VT v[W];
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                const int a = q * W + e;
+                v[e] = a < R ? src[(int64_t)a * p.stride_a] : VT(0);
+            }
+            dst[q] = make_vec<VT>(v);
+        }
     }
     __syncthreads();
 
     const int G = (R + J - 1) / J;
     const int ns_tile = p.r2 * R;
-    const bool active = tid < p.r2 * G;
-    const int X2 = active ? tid / G : 0;
-    const int x1_0 = active ? (tid - X2 * G) * J : 0;
-    double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
+    const int lanes = p.r2 * G * 2;
+    const bool active = tid < lanes;
+    const int half = tid & 1;
+    const int cell = tid >> 1;
+    const int X2 = active ? cell / G : 0;
+    const int x1_0 = active ? (cell - X2 * G) * J : 0;
+    const int a0 = half * RH;
+    Acc<VT, KAHAN> acc[J][RH];
     if (active) {
         const int N = b + X2;
-        const int kmax = N == 0 ? 0 : max(0, min(N, p.dmax - x1_0));
-        Acc<VT, KAHAN> acc[J][RMAX];
-        for (int k = 0; k <= kmax; ++k) {
-            AW w[J];
+        const VT* Sh = S + a0;
+        auto row_fma = [&](int pos, const AW* w) {
+            const VV* row = reinterpret_cast<const VV*>(Sh + pos * RMAX);
 #pragma unroll
-            for (int i = 0; i < J; ++i) {
-                const int X1 = x1_0 + i;
-                // demand <= X_1 keeps y; X_1 + k removes k units; the last point
-                // collects every demand that empties y (tables are zero past d_max)
-                const double wd = N == 0 ? (k == 0 ? 1.0 : 0.0)
-                                  : k == 0 ? sF[min(X1, p.dmax)]
-                                  : k == N ? sG[X1 + N]
-                                           : sP[X1 + k];
-                w[i] = (AW)wd;
-            }
-            const VV* row = reinterpret_cast<const VV*>(S + (N - k) * RMAX);
-#pragma unroll
-            for (int q = 0; q < RMAX / W; ++q) {
+            for (int q = 0; q < RH / W; ++q) {
                 const VV u = row[q];
 #pragma unroll
                 for (int e = 0; e < W; ++e) {
@@ -179,41 +198,86 @@ __global__ __launch_bounds__(512) void backup_a_kernel(ADev p) {
                     for (int i = 0; i < J; ++i) acc[i][q * W + e].add(w[i], ue);
                 }
             }
-        }
-        const double mu = (!EXTRACT && sizeof(VT) == 4) ? ctl->mu : 0.0;
+        };
+        AW w[J];
+        if (N == 0) {
 #pragma unroll
-        for (int i = 0; i < J; ++i) {
-            const int X1 = x1_0 + i;
-            if (X1 >= R) continue;
+            for (int i = 0; i < J; ++i) w[i] = (AW)1.0;
+            row_fma(0, w);
+        } else {
+            const int kmax = max(0, min(N, p.dmax - x1_0));
+#pragma unroll
+            for (int i = 0; i < J; ++i) w[i] = (AW)sF[min(x1_0 + i, p.dmax)];
+            row_fma(N, w);
+            const int kend = min(N - 1, kmax);
+#pragma unroll
+            for (int i = 0; i < J; ++i) w[i] = (AW)sP[x1_0 + i + 1];
+            for (int k = 1; k <= kend; ++k) {
+                row_fma(N - k, w);
+#pragma unroll
+                for (int i = 0; i < J - 1; ++i) w[i] = w[i + 1];
+                w[J - 1] = (AW)sP[x1_0 + J + k];
+            }
+            if (N <= kmax) {
+#pragma unroll
+                for (int i = 0; i < J; ++i) w[i] = (AW)sG[x1_0 + i + N];
+                row_fma(0, w);
+            }
+        }
+    }
+    const double mu = (!EXTRACT && sizeof(VT) == 4) ? ctl->mu : 0.0;
+    double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
+    double ca[RH];  // -c_var * a for this lane's actions (-inf past the last action)
+#pragma unroll
+    for (int e = 0; e < RH; ++e) ca[e] = a0 + e < R ? -p.cvar * (a0 + e) : -DBL_MAX;
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+        const int X1 = x1_0 + i;
+        if (EXTRACT) {
             double best = -DBL_MAX, second = -DBL_MAX;
             int arg = 0;
 #pragma unroll
-            for (int a = 0; a < RMAX; ++a) {
-                if (a < R) {
-                    const double q = -p.cvar * a + p.gamma * acc[i][a].value();
+            for (int e = 0; e < RH; ++e) {
+                if (a0 + e < R) {
+                    const double q = fma(p.gamma, acc[i][e].value(), ca[e]);
                     if (q > best) {
                         second = best;
                         best = q;
-                        arg = a;
+                        arg = a0 + e;
                     } else if (q > second) {
                         second = q;
                     }
                 }
             }
+            // merge with the other half (partner lane tid ^ 1); every lane takes part
+            const double ob = __shfl_xor(best, 1, 64);
+            const double os = __shfl_xor(second, 1, 64);
+            const int oa = __shfl_xor(arg, 1, 64);
+            const double lo_b = half ? ob : best, hi_b = half ? best : ob;
+            const int lo_a = half ? oa : arg, hi_a = half ? arg : oa;
+            const double B = hi_b > lo_b ? hi_b : lo_b;
+            const int A = hi_b > lo_b ? hi_a : lo_a;
+            const double S2 = fmax(fmin(best, ob), fmax(second, os));
+            if (!active || half || X1 >= R) continue;
             const int64_t s_idx = (int64_t)tile * ns_tile + X2 * R + X1;
-            if (EXTRACT) {
-                p.pi[s_idx] = arg;
-                p.gap[s_idx] = R > 1 ? best - second : INFINITY;
-            } else {
-                const double r0 = p.r0[X1 * p.xt + X1 + X2 + b];
-                const VT o = (VT)(r0 - mu + best);
-                reinterpret_cast<VT*>(p.v_out)[s_idx] = o;
-                const double out = (double)o, dv = out - (double)vin[s_idx];
-                dmx = fmax(dmx, dv);
-                dmn = fmin(dmn, dv);
-                vmx = fmax(vmx, out);
-                vmn = fmin(vmn, out);
-            }
+            p.pi[s_idx] = A;
+            p.gap[s_idx] = R > 1 ? B - S2 : INFINITY;
+        } else {
+            // a sweep needs only the max
+            double best = -DBL_MAX;
+#pragma unroll
+            for (int e = 0; e < RH; ++e) best = fmax(best, fma(p.gamma, acc[i][e].value(), ca[e]));
+            best = fmax(best, __shfl_xor(best, 1, 64));
+            if (!active || half || X1 >= R) continue;
+            const int64_t s_idx = (int64_t)tile * ns_tile + X2 * R + X1;
+            const double r0 = p.r0[X1 * p.xt + X1 + X2 + b];
+            const VT o = (VT)(r0 - mu + best);
+            reinterpret_cast<VT*>(p.v_out)[s_idx] = o;
+            const double out = (double)o, dv = out - (double)vin[s_idx];
+            dmx = fmax(dmx, dv);
+            dmn = fmin(dmn, dv);
+            vmx = fmax(vmx, out);
+            vmn = fmin(vmn, out);
         }
     }
     if (EXTRACT) return;
@@ -242,38 +306,7 @@ __global__ __launch_bounds__(1024) void span_kernel(Ctl* ctl, const double* part
     }
     block_reduce4(a0, a1, a2, a3, red);
     if (threadIdx.x != 0) return;
-    double dmax = a0, dmin = a1;
-    if (fp32) {
-        // V = c + v: V_new - V = ((gamma-1) c + mu) + (v_new - v)
-        const double shift = (gamma - 1.0) * ctl->c + ctl->mu;
-        dmax += shift;
-        dmin += shift;
-        ctl->c = gamma * ctl->c + ctl->mu;
-        ctl->mu += 0.5 * (a2 + a3);
-    }
-    const double span = dmax - dmin;
-    ctl->dmax = dmax;
-    ctl->dmin = dmin;
-    ctl->span = span;
-    ctl->sweeps += 1;
-    if (fixed) return;
-    if (fp32) {
-        const double vabs = fmax(fabs(a2), fabs(a3));
-        ctl->vabs = vabs;
-        if (span < ctl->best_span * 0.999) {
-            ctl->best_span = span;
-            ctl->stall = 0;
-        } else {
-            ctl->stall += 1;
-        }
-        if (span < ctl->thr || span <= ctl->floor32 * vabs || ctl->stall >= 3) {
-            ctl->stop = 1;
-            ctl->stop_sweep = ctl->sweeps;
-        }
-    } else if (span < ctl->thr) {
-        ctl->stop = 1;
-        ctl->stop_sweep = ctl->sweeps;
-    }
+    span_update(ctl, a0, a1, a2, a3, fp32, fixed, gamma);
 }
 
 __global__ void to_f64_kernel(const float* v32, double* v64, const Ctl* ctl, int64_t n) {
@@ -299,17 +332,16 @@ __global__ void to_f32_kernel(const double* v64, float* v32, double c, int64_t n
 
 template <typename VT, bool KAHAN, bool EXTRACT, int RMAX>
 static hipError_t launch_a_r(const ADev& p, hipStream_t s) {
-    // states per lane: enough multiply-adds per LDS value to keep VALU busy
-    constexpr int J = KAHAN ? 2 : (RMAX <= 24 ? 4 : 3);
+    constexpr int J = 4;  // states per lane (two lanes per group of states)
     const int lp_max = (p.m >= 2 ? (p.m - 2) * (p.R - 1) : 0) + p.r2;
     size_t bytes = sizeof(VT) * (size_t)lp_max * RMAX;
     bytes += sizeof(double) * (3 * (size_t)p.tab + 64);
     if (bytes > 65536) return hipErrorInvalidConfiguration;  // beyond the default LDS limit
     if (p.tab < p.R + J + lp_max || p.tab < p.dmax + 2 + J) return hipErrorInvalidValue;
-    const int lanes = p.r2 * ((p.R + J - 1) / J);
+    const int lanes = 2 * p.r2 * ((p.R + J - 1) / J);
     const int threads = ((lanes + 63) / 64) * 64;
     if (threads > 512) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, J, EXTRACT>), dim3(p.tiles),
+    hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT>), dim3(p.tiles),
                        dim3(threads), bytes, s, p);
     return hipGetLastError();
 }

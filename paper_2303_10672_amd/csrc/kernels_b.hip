@@ -23,6 +23,7 @@
 // and takes the max over the joint actions (a0 major, lowest index on ties).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -78,10 +79,25 @@ __global__ __launch_bounds__(256) void subst_stage1_kernel(BDev p) {
     p.z[idx] = p.rexp1[(size_t)u * p.sw + stock1] + p.gamma * acc;
 }
 
+// Merge two (best, second, argmax) triples; equal values go to the lower action.
+__device__ __forceinline__ void merge_best(double& b, double& s2, int& a, double ob, double os,
+                                           int oa) {
+    const bool take = ob > b || (ob == b && oa < a);
+    s2 = fmax(fmin(b, ob), fmax(s2, os));
+    if (take) {
+        b = ob;
+        a = oa;
+    }
+}
+
+// Stage 2: one workgroup per product-1 stock index; four neighbouring lanes share a
+// product-0 stock index and split its orders a0 (a0 = part, part + 4, ...), then
+// merge their best actions with two shuffles.
 template <typename VT, bool EXTRACT>
-__global__ __launch_bounds__(256) void subst_stage2_kernel(BDev p) {
+__global__ __launch_bounds__(1024) void subst_stage2_kernel(BDev p) {
     extern __shared__ __align__(16) unsigned char smem[];
     if (!EXTRACT && p.ctl->stop) return;
+    constexpr int NP = 4;
     const int ib = blockIdx.x, tid = threadIdx.x;
     const int R1 = p.r1, RP = p.r1pad;
     double* Zs = reinterpret_cast<double*>(smem);          // [rows][RP]
@@ -94,62 +110,78 @@ __global__ __launch_bounds__(256) void subst_stage2_kernel(BDev p) {
     for (int i = tid; i <= p.d0max; i += blockDim.x) P0[i] = p.pmf0[i];
     __syncthreads();
     const double mu = (!EXTRACT && sizeof(VT) == 4) ? p.ctl->mu : 0.0;
+    const int part = tid % NP, cells = blockDim.x / NP;
     double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
-    for (int ia = tid; ia < p.na; ia += blockDim.x) {
-        // product-0 stock by life: x0 = A_1 (oldest), w[1..m-2] = A_2..A_{m-1}
-        int w[8];
-        int rest = ia;
-        const int x0 = rest % p.r0;
-        rest /= p.r0;
-        int held = x0;
-        for (int j = 1; j <= p.m - 2; ++j) {
-            w[j] = rest % p.r0;
-            rest /= p.r0;
-            held += w[j];
-        }
+    for (int ia0 = 0; ia0 < p.na; ia0 += cells) {   // same trip count on every lane
+        const int ia = ia0 + tid / NP;
+        const bool active = ia < p.na;
         double best = -DBL_MAX, second = -DBL_MAX;
-        int arg = 0;
-        for (int a0 = 0; a0 < p.r0; ++a0) {
-            w[p.m - 1] = a0;
-            const int stock0 = held + a0;
-            double acc[PVI_B_R1MAX];
-#pragma unroll
-            for (int i = 0; i < PVI_B_R1MAX; ++i) acc[i] = 0.0;
-            for (int d0 = 0; d0 <= p.d0max; ++d0) {
-                const double pr = P0[d0];
-                int row;
-                if (d0 >= stock0) {
-                    row = d0 == stock0 ? 0 : p.na + (d0 - stock0) - 1;
-                } else {
-                    // units beyond the oldest ones deplete the younger stock, oldest first
-                    int r = d0 > x0 ? d0 - x0 : 0, off = 0, pw = 1;
-                    for (int j = 1; j <= p.m - 1; ++j) {
-                        const int take = min(r, w[j]);
-                        r -= take;
-                        off += (w[j] - take) * pw;
-                        pw *= p.r0;
-                    }
-                    row = off;
-                }
-                const double* zr = Zs + (size_t)row * RP;
-#pragma unroll
-                for (int i = 0; i < PVI_B_R1MAX; ++i) acc[i] = fma(pr, zr[i], acc[i]);
+        int arg = 0x7fffffff;
+        if (active) {
+            // product-0 stock by life: x0 = A_1 (oldest), w[1..m-2] = A_2..A_{m-1}
+            int w[8];
+            int rest = ia;
+            const int x0 = rest % p.r0;
+            rest /= p.r0;
+            int held = x0;
+            for (int j = 1; j <= p.m - 2; ++j) {
+                w[j] = rest % p.r0;
+                rest /= p.r0;
+                held += w[j];
             }
-            const double base = -p.cvar0 * a0 + p.rexp0[stock0];
+            for (int a0 = part; a0 < p.r0; a0 += NP) {
+                w[p.m - 1] = a0;
+                const int stock0 = held + a0;
+                double acc[PVI_B_R1MAX];
 #pragma unroll
-            for (int a1 = 0; a1 < PVI_B_R1MAX; ++a1) {
-                if (a1 < R1) {
-                    const double q = base - p.cvar1 * a1 + acc[a1];
-                    if (q > best) {
-                        second = best;
-                        best = q;
-                        arg = a0 * R1 + a1;
-                    } else if (q > second) {
-                        second = q;
+                for (int i = 0; i < PVI_B_R1MAX; ++i) acc[i] = 0.0;
+                for (int d0 = 0; d0 <= p.d0max; ++d0) {
+                    const double pr = P0[d0];
+                    int row;
+                    if (d0 >= stock0) {
+                        row = d0 == stock0 ? 0 : p.na + (d0 - stock0) - 1;
+                    } else {
+                        // demand beyond the oldest units depletes the younger ones
+                        int r = d0 > x0 ? d0 - x0 : 0, off = 0, pw = 1;
+                        for (int j = 1; j <= p.m - 1; ++j) {
+                            const int take = min(r, w[j]);
+                            r -= take;
+                            off += (w[j] - take) * pw;
+                            pw *= p.r0;
+                        }
+                        row = off;
+                    }
+                    const double2* zr = reinterpret_cast<const double2*>(Zs + (size_t)row * RP);
+#pragma unroll
+                    for (int i = 0; i < PVI_B_R1MAX / 2; ++i) {
+                        const double2 z = zr[i];
+                        acc[2 * i] = fma(pr, z.x, acc[2 * i]);
+                        acc[2 * i + 1] = fma(pr, z.y, acc[2 * i + 1]);
+                    }
+                }
+                const double base = -p.cvar0 * a0 + p.rexp0[stock0];
+#pragma unroll
+                for (int a1 = 0; a1 < PVI_B_R1MAX; ++a1) {
+                    if (a1 < R1) {
+                        const double q = base - p.cvar1 * a1 + acc[a1];
+                        if (q > best) {
+                            second = best;
+                            best = q;
+                            arg = a0 * R1 + a1;
+                        } else if (q > second) {
+                            second = q;
+                        }
                     }
                 }
             }
         }
+        for (int o = 1; o < NP; o <<= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const double os = __shfl_xor(second, o, 64);
+            const int oa = __shfl_xor(arg, o, 64);
+            merge_best(best, second, arg, ob, os, oa);
+        }
+        if (!active || part != 0) continue;
         const int64_t s = (int64_t)ia * p.nb + ib;
         if (EXTRACT) {
             p.pi[s] = arg;
@@ -185,7 +217,9 @@ static hipError_t launch_b_t(const BDev& p, hipStream_t s) {
     if (e != hipSuccess) return e;
     const size_t bytes = sizeof(double) * ((size_t)p.rows * p.r1pad + p.d0max + 1 + 64);
     if (bytes > 65536) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((subst_stage2_kernel<VT, EXTRACT>), dim3(p.nb), dim3(256), bytes, s, p);
+    // four lanes per product-0 state; at most 1024 lanes
+    const int threads = (int)std::min<int64_t>(1024, ((int64_t)p.na * 4 + 63) / 64 * 64);
+    hipLaunchKernelGGL((subst_stage2_kernel<VT, EXTRACT>), dim3(p.nb), dim3(threads), bytes, s, p);
     return hipGetLastError();
 }
 

@@ -109,42 +109,74 @@ __global__ __launch_bounds__(256) void c_stage_u_kernel(CDev p) {
     }
 }
 
-// One binomial merge of life class j (2 <= j <= m-1).  Block (x, y) = (digit
-// block of 256 lanes, (tau, y_m, r) triple); lanes are the m-1 digits (x_{m-1}..x_1).
+// First merge (life class 2) straight from U.  One workgroup per (tau, y_m, digits
+// above 2): the R x R slab U[.., z_2, z_1] sits in LDS and each lane (x_2, x_1)
+// produces T_2 for every remaining count r:
+//   T_2(r) = sum_{y<=r} Bin(y; r, q_2) U(.., c(x_2 + y), c(x_1 + r - y)).
 template <typename VT>
-__global__ __launch_bounds__(256) void c_merge_kernel(CDev p, int j, const void* in_,
-                                                      void* out_) {
+__global__ __launch_bounds__(1024) void c_merge2_kernel(CDev p, const void* in_, void* out_) {
+    __shared__ double slab[32 * 32];
+    __shared__ double bq[32 * 32];
     if (!p.extract && p.ctl->stop) return;
-    const int64_t D = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (D >= p.nblk) return;
-    const int R = p.R;
-    const int trip = blockIdx.y;  // tau * npair + pair
-    const int tau = trip / p.npair, pair = trip - tau * p.npair;
-    const int ym = p.pair_y[pair], r = p.pair_r[pair];
-    const double* bq = p.binq + ((size_t)j * R + r) * R;  // Bin(y; r, q_j), y = 0..r
-    const int pwj = p.pow_r[j - 1];
-    const int dj = (int)((D / pwj) % R);
-    double acc = 0.0;
-    if (j == 2) {
-        // input is U[tau][y_m][z_{m-1}..z_1]; digit 1 takes the remaining r - y units
-        const VT* U = reinterpret_cast<const VT*>(in_) + ((int64_t)tau * R + ym) * p.nblk;
-        const int d1 = (int)(D % R);
-        const int64_t rest = D - (int64_t)dj * pwj - d1;
-        for (int y = 0; y <= r; ++y) {
-            const int z2 = min(dj + y, R - 1), z1 = min(d1 + r - y, R - 1);
-            acc = fma(bq[y], (double)U[rest + (int64_t)z2 * pwj + z1], acc);
-        }
-    } else {
-        const VT* T = reinterpret_cast<const VT*>(in_);
-        const int64_t rest = D - (int64_t)dj * pwj;
-        const int pbase = p.pair_base[ym];  // pair index of (y_m, 0)
-        for (int y = 0; y <= r; ++y) {
-            const int zj = min(dj + y, R - 1);
-            const int64_t row = (int64_t)tau * p.npair + pbase + (r - y);
-            acc = fma(bq[y], (double)T[row * p.nblk + rest + (int64_t)zj * pwj], acc);
-        }
+    const int R = p.R, tid = threadIdx.x;
+    const int tym = blockIdx.y, tau = tym / R, ym = tym - tau * R;
+    const int64_t hi = blockIdx.x;  // digits 3..m-1
+    const int nr = R - ym;          // r = 0 .. a_max - y_m
+    const VT* U = reinterpret_cast<const VT*>(in_) + ((int64_t)tau * R + ym) * p.nblk + hi * R * R;
+    for (int i = tid; i < R * R; i += blockDim.x) {
+        slab[i] = (double)U[i];
+        bq[i] = p.binq[(size_t)2 * R * R + i];
     }
-    reinterpret_cast<VT*>(out_)[(int64_t)trip * p.nblk + D] = (VT)acc;
+    __syncthreads();
+    if (tid >= R * R) return;
+    const int x2 = tid / R, x1 = tid - x2 * R;
+    VT* T = reinterpret_cast<VT*>(out_);
+    const int64_t row0 = (int64_t)tau * p.npair + p.pair_base[ym];
+    for (int r = 0; r < nr; ++r) {
+        double acc = 0.0;
+        for (int y = 0; y <= r; ++y)
+            acc = fma(bq[r * R + y], slab[min(x2 + y, R - 1) * R + min(x1 + r - y, R - 1)], acc);
+        T[(row0 + r) * p.nblk + hi * R * R + tid] = (VT)acc;
+    }
+}
+
+// Merge of life class j >= 3.  One workgroup per (tau, y_m, digits above j, block of
+// LB consecutive values of the digits below j); the slab in[r'][z_j][lo] for every
+// remaining count r' is staged in LDS once, and each lane (x_j, lo) produces
+//   T_j(r) = sum_{y<=r} Bin(y; r, q_j) T_{j-1}(.., c(x_j + y), ..; r - y)
+// for every r.  Lanes with consecutive lo touch consecutive addresses.
+template <typename VT, int LB>
+__global__ __launch_bounds__(512) void c_merge_kernel(CDev p, int j, const void* in_,
+                                                      void* out_) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (!p.extract && p.ctl->stop) return;
+    const int R = p.R, tid = threadIdx.x;
+    VT* slab = reinterpret_cast<VT*>(smem);                        // [r'][z][LB]
+    double* bq = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)R * R * LB);
+    const int tym = blockIdx.y, tau = tym / R, ym = tym - tau * R;
+    const int nr = R - ym;
+    const int64_t nlo = p.pow_r[j - 1];            // R^(j-1) values below digit j
+    const int64_t nlob = (nlo + LB - 1) / LB;
+    const int64_t hi = blockIdx.x / nlob;
+    const int64_t lo0 = (blockIdx.x - hi * nlob) * LB;
+    const int64_t base = hi * nlo * R + lo0;        // digits above j, digit j = 0, lo0
+    const int64_t row0 = (int64_t)tau * p.npair + p.pair_base[ym];
+    const VT* in = reinterpret_cast<const VT*>(in_);
+    for (int i = tid; i < nr * R * LB; i += blockDim.x) {
+        const int l = i % LB, z = (i / LB) % R, rr = i / (LB * R);
+        slab[i] = lo0 + l < nlo ? in[(row0 + rr) * p.nblk + base + (int64_t)z * nlo + l] : VT(0);
+    }
+    for (int i = tid; i < R * R; i += blockDim.x) bq[i] = p.binq[((size_t)j * R) * R + i];
+    __syncthreads();
+    const int l = tid % LB, xj = tid / LB;
+    if (xj >= R || lo0 + l >= nlo) return;
+    VT* out = reinterpret_cast<VT*>(out_);
+    for (int r = 0; r < nr; ++r) {
+        double acc = 0.0;
+        for (int y = 0; y <= r; ++y)
+            acc = fma(bq[r * R + y], (double)slab[((r - y) * R + min(xj + y, R - 1)) * LB + l], acc);
+        out[(row0 + r) * p.nblk + base + (int64_t)xj * nlo + l] = (VT)acc;
+    }
 }
 
 // Q(tau, x, a) = -C_f [a > 0] + sum_y Bin(y; a, p_m) T_{m-1}(tau, y, x; a - y), then
@@ -228,8 +260,33 @@ static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
     void* bufs[2] = {p.t0, p.t1};
     for (int j = 2; j <= p.m - 1; ++j) {
         void* out = bufs[j & 1];
-        hipLaunchKernelGGL((c_merge_kernel<VT>), dim3(gx, p.P * p.npair), dim3(256), 0, s, p, j,
-                           in, out);
+        if (j == 2) {
+            const int threads = ((p.R * p.R + 63) / 64) * 64;
+            hipLaunchKernelGGL((c_merge2_kernel<VT>), dim3((unsigned)(p.nblk / (p.R * p.R)), p.P * p.R),
+                               dim3(threads), 0, s, p, in, out);
+        } else {
+            // widest block of low digits whose slab stays within 32 KB of LDS, so
+            // several workgroups share a CU and overlap their loads with compute
+            auto lds_for = [&](int lb) {
+                return sizeof(VT) * (size_t)p.R * p.R * lb + sizeof(double) * p.R * p.R;
+            };
+            const int lb = lds_for(16) <= 32768 ? 16 : lds_for(8) <= 32768 ? 8 : 4;
+            if (lds_for(lb) > 65536) return hipErrorInvalidConfiguration;
+            const int64_t nlo = p.pow_r[j - 1];
+            const int64_t nlob = (nlo + lb - 1) / lb;
+            const int64_t nhi = p.nblk / (nlo * p.R);
+            const int threads = ((p.R * lb + 63) / 64) * 64;
+            const dim3 grid((unsigned)(nhi * nlob), p.P * p.R);
+            if (lb == 16)
+                hipLaunchKernelGGL((c_merge_kernel<VT, 16>), grid, dim3(threads), lds_for(lb), s, p,
+                                   j, in, out);
+            else if (lb == 8)
+                hipLaunchKernelGGL((c_merge_kernel<VT, 8>), grid, dim3(threads), lds_for(lb), s, p,
+                                   j, in, out);
+            else
+                hipLaunchKernelGGL((c_merge_kernel<VT, 4>), grid, dim3(threads), lds_for(lb), s, p,
+                                   j, in, out);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         in = out;
     }

@@ -63,6 +63,7 @@ struct ADev {
     int32_t r2;         // R if m >= 2 else 1
     int32_t tiles;      // nh * nz
     int32_t pow_y[8];   // R^(i-1), weight of next-state digit i inside a block
+    int32_t fixed;      // 1: fixed number of sweeps, the stopping rule is not applied
     double gamma, cvar;
 };
 

@@ -141,6 +141,18 @@ void small_worker(pvi_server* S) {
     hipStream_t stream;
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return;
     Arena ar;
+    // take the arena up front so the first batch does not pay for allocation
+    {
+        const size_t want = size_t(32) << 20;
+        if (hipMalloc((void**)&ar.d, want) == hipSuccess &&
+            hipHostMalloc((void**)&ar.h, want, hipHostMallocDefault) == hipSuccess) {
+            ar.bytes = want;
+        } else {
+            if (ar.d) (void)hipFree(ar.d);
+            if (ar.h) (void)hipHostFree(ar.h);
+            ar = Arena{};
+        }
+    }
     for (;;) {
         std::vector<Request*> batch;
         {

@@ -159,10 +159,11 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
             const void* vin = ph.fp32 ? (const void*)d.v32[launched & 1] : d.v64[launched & 1];
             void* vout = ph.fp32 ? (void*)d.v32[(launched + 1) & 1] : d.v64[(launched + 1) & 1];
             if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i], s));
-            PVI_HIP(family_backup(p, ph.fp32, ph.kahan, 0, vin, vout, s));
+            PVI_HIP(family_backup(p, ph.fp32, ph.kahan, 0, ph.fixed > 0, vin, vout, s));
             if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i + 1], s));
-            PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, ph.fp32 ? 1 : 0, ph.fixed > 0,
-                                p->d.gamma, s));
+            if (!family_fused_span(p))
+                PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, ph.fp32 ? 1 : 0, ph.fixed > 0,
+                                    p->d.gamma, s));
             ++launched;
         }
         PVI_HIP(hipMemcpyAsync(d.h_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -280,7 +281,7 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* o, pvi_result* res) {
         p->ret_buf = 0;
     }
     // policy and Q gap from one more FP64 backup of the returned V
-    PVI_HIP(family_backup(p, 0, 0, 1, d.v64[p->ret_buf], nullptr, s));
+    PVI_HIP(family_backup(p, 0, 0, 1, 0, d.v64[p->ret_buf], nullptr, s));
     PVI_HIP(hipStreamSynchronize(s));
     p->have_result = 1;
     const bool converged = o->fixed_sweeps > 0 || o64.stopped;
@@ -323,17 +324,19 @@ pvi_status vi_backup(pvi_mdp* p, int32_t precision, const double* v_in, double* 
     PVI_HIP(hipMemcpyAsync(d.v64[0], v_in, sizeof(double) * p->ns, hipMemcpyHostToDevice, s));
     if (precision == PVI_FP64) {
         if ((st = init_ctl(p, s, -1.0, 0.0)) != PVI_OK) return st;
-        PVI_HIP(family_backup(p, 0, 0, 0, d.v64[0], d.v64[1], s));
-        PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, 0, 1, p->d.gamma, s));
+        PVI_HIP(family_backup(p, 0, 0, 0, 1, d.v64[0], d.v64[1], s));
+        if (!family_fused_span(p))
+            PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, 0, 1, p->d.gamma, s));
     } else {
         const double c0 = midrange(v_in, p->ns);
         PVI_HIP(launch_to_f32(d.v64[0], d.v32[0], c0, p->ns, s));
         if ((st = init_ctl(p, s, -1.0, c0)) != PVI_OK) return st;
-        PVI_HIP(family_backup(p, 1, precision == PVI_FP32, 0, d.v32[0], d.v32[1], s));
-        PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, 1, 1, p->d.gamma, s));
+        PVI_HIP(family_backup(p, 1, precision == PVI_FP32, 0, 1, d.v32[0], d.v32[1], s));
+        if (!family_fused_span(p))
+            PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, 1, 1, p->d.gamma, s));
         PVI_HIP(launch_to_f64(d.v32[1], d.v64[1], d.ctl, p->ns, s));
     }
-    PVI_HIP(family_backup(p, 0, 0, 1, d.v64[0], nullptr, s));
+    PVI_HIP(family_backup(p, 0, 0, 1, 0, d.v64[0], nullptr, s));
     if (v_out)
         PVI_HIP(hipMemcpyAsync(v_out, d.v64[1], sizeof(double) * p->ns, hipMemcpyDeviceToHost, s));
     if (policy)
