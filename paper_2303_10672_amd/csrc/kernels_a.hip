@@ -104,30 +104,29 @@ struct Acc<float, true> {
     __device__ __forceinline__ double value() const { return (double)s - (double)c; }
 };
 
-// VT: storage type of V (float = centred FP32, double = FP64).
-// KAHAN: FP32 compensated accumulation (only with VT = float); otherwise FP64.
-// Lanes: (X_2, group of J consecutive X_1, half of the actions).  Lanes with the
-//   same X_2 read the same staged values, so each LDS value feeds J multiply-adds;
-//   splitting the actions over two neighbouring lanes halves the accumulator
-//   registers, which doubles the waves a SIMD can hold.  The two halves merge
-//   their best and second-best Q with one lane shuffle (lower actions win ties).
-// Weights: k = 0 takes P(D <= X_1), 0 < k < N takes P(X_1 + k) (a shift register
-//   over X_1 needs one new table value per step), k = N takes P(D >= X_1 + N);
-//   the tables are zero (one for the CDF) past d_max, so clipping needs no test.
+// One wavefront per tile; VT: storage type of V (float = centred FP32, double = FP64);
+// KAHAN: FP32 compensated accumulation (only with VT = float), else FP64.
 // EXTRACT: write policy and Q gap instead of V (FP64 only).
+//
+// For a state (X_2, X_1) of the tile put N = b + X_2 (its path length, b the sum
+// of the tile's fixed digits) and u = X_1 + N.  For N >= 1,
+//   E = F(X_1) S[N] + C(u, N) + G(u) S[0],   C(u, N) = sum_{j=1}^{N-1} P(u - j) S[j],
+// with F = P(D <= .), G = P(D >= .) and S the staged path list.  For a fixed u,
+// C(u, N) is a running sum over the path points, so lane u accumulates it once for
+// every action (in registers) while N walks up the list, and emits the states of
+// its diagonal (X_1 = u - N in [0, R)) as N passes them.  The single-point state
+// (N = 0, only when b = 0) takes S[0] for every demand.  All actions live in one
+// lane, so the max needs no exchange.
 template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
-__global__ __launch_bounds__(512) void backup_a_kernel(ADev p) {
+__global__ __launch_bounds__(64) void backup_a_kernel(ADev p) {
     extern __shared__ __align__(16) unsigned char smem[];
     Ctl* ctl = p.ctl;
     if (!EXTRACT && ctl->stop) return;
-    constexpr int J = 4;
-    constexpr int RH = RMAX / 2;
     constexpr int W = VecLoad<VT>::W;
     using VV = typename VecLoad<VT>::V;
     using AW = typename Acc<VT, KAHAN>::W;
-    static_assert(RH % W == 0, "half row must be a whole number of vectors");
 
-    const int R = p.R, m = p.m, tid = threadIdx.x, bs = blockDim.x;
+    const int R = p.R, m = p.m, lane = threadIdx.x;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int h = tile / p.nz;
     int Y[9];
@@ -147,9 +146,8 @@ __global__ __launch_bounds__(512) void backup_a_kernel(ADev p) {
     double* sP = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)lp * RMAX);
     double* sF = sP + p.tab;
     double* sG = sF + p.tab;
-    double* red = sG + p.tab;
 
-    for (int i = tid; i < p.tab; i += bs) {
+    for (int i = lane; i < p.tab; i += 64) {
         sP[i] = p.pmf[i];
         sF[i] = p.cdf[i];
         sG[i] = p.tail[i];
@@ -157,7 +155,7 @@ __global__ __launch_bounds__(512) void backup_a_kernel(ADev p) {
     const VT* vin = reinterpret_cast<const VT*>(p.v_in);
     const int64_t hbase = (int64_t)h * p.stride_h;
     // one lane per path point: its block offset once, then every action's value
-    for (int j = tid; j < lp; j += bs) {
+    for (int j = lane; j < lp; j += 64) {
         const VT* src = vin + hbase + path_offset(j, Y, m, p.pow_y);
         VV* dst = reinterpret_cast<VV*>(S + j * RMAX);
 #pragma unroll
@@ -173,103 +171,18 @@ __global__ __launch_bounds__(512) void backup_a_kernel(ADev p) {
     }
     __syncthreads();
 
-    const int G = (R + J - 1) / J;
     const int ns_tile = p.r2 * R;
-    const int lanes = p.r2 * G * 2;
-    const bool active = tid < lanes;
-    const int half = tid & 1;
-    const int cell = tid >> 1;
-    const int X2 = active ? cell / G : 0;
-    const int x1_0 = active ? (cell - X2 * G) * J : 0;
-    const int a0 = half * RH;
-    Acc<VT, KAHAN> acc[J][RH];
-    if (active) {
-        const int N = b + X2;
-        const VT* Sh = S + a0;
-        auto row_fma = [&](int pos, const AW* w) {
-            const VV* row = reinterpret_cast<const VV*>(Sh + pos * RMAX);
-#pragma unroll
-            for (int q = 0; q < RH / W; ++q) {
-                const VV u = row[q];
-#pragma unroll
-                for (int e = 0; e < W; ++e) {
-                    const VT ue = lane_of<VT, W>(u, e);
-#pragma unroll
-                    for (int i = 0; i < J; ++i) acc[i][q * W + e].add(w[i], ue);
-                }
-            }
-        };
-        AW w[J];
-        if (N == 0) {
-#pragma unroll
-            for (int i = 0; i < J; ++i) w[i] = (AW)1.0;
-            row_fma(0, w);
-        } else {
-            const int kmax = max(0, min(N, p.dmax - x1_0));
-#pragma unroll
-            for (int i = 0; i < J; ++i) w[i] = (AW)sF[min(x1_0 + i, p.dmax)];
-            row_fma(N, w);
-            const int kend = min(N - 1, kmax);
-#pragma unroll
-            for (int i = 0; i < J; ++i) w[i] = (AW)sP[x1_0 + i + 1];
-            for (int k = 1; k <= kend; ++k) {
-                row_fma(N - k, w);
-#pragma unroll
-                for (int i = 0; i < J - 1; ++i) w[i] = w[i + 1];
-                w[J - 1] = (AW)sP[x1_0 + J + k];
-            }
-            if (N <= kmax) {
-#pragma unroll
-                for (int i = 0; i < J; ++i) w[i] = (AW)sG[x1_0 + i + N];
-                row_fma(0, w);
-            }
-        }
-    }
     const double mu = (!EXTRACT && sizeof(VT) == 4) ? ctl->mu : 0.0;
     double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
-    double ca[RH];  // -c_var * a for this lane's actions (-inf past the last action)
-#pragma unroll
-    for (int e = 0; e < RH; ++e) ca[e] = a0 + e < R ? -p.cvar * (a0 + e) : -DBL_MAX;
-#pragma unroll
-    for (int i = 0; i < J; ++i) {
-        const int X1 = x1_0 + i;
+
+    // Writes one state from the Q of its actions: the policy and gap, or V' and
+    // the running max/min of V' - V and of V'.
+    auto finish = [&](int X2, int X1, double best, double second, int arg) {
+        const int64_t s_idx = (int64_t)tile * ns_tile + X2 * R + X1;
         if (EXTRACT) {
-            double best = -DBL_MAX, second = -DBL_MAX;
-            int arg = 0;
-#pragma unroll
-            for (int e = 0; e < RH; ++e) {
-                if (a0 + e < R) {
-                    const double q = fma(p.gamma, acc[i][e].value(), ca[e]);
-                    if (q > best) {
-                        second = best;
-                        best = q;
-                        arg = a0 + e;
-                    } else if (q > second) {
-                        second = q;
-                    }
-                }
-            }
-            // merge with the other half (partner lane tid ^ 1); every lane takes part
-            const double ob = __shfl_xor(best, 1, 64);
-            const double os = __shfl_xor(second, 1, 64);
-            const int oa = __shfl_xor(arg, 1, 64);
-            const double lo_b = half ? ob : best, hi_b = half ? best : ob;
-            const int lo_a = half ? oa : arg, hi_a = half ? arg : oa;
-            const double B = hi_b > lo_b ? hi_b : lo_b;
-            const int A = hi_b > lo_b ? hi_a : lo_a;
-            const double S2 = fmax(fmin(best, ob), fmax(second, os));
-            if (!active || half || X1 >= R) continue;
-            const int64_t s_idx = (int64_t)tile * ns_tile + X2 * R + X1;
-            p.pi[s_idx] = A;
-            p.gap[s_idx] = R > 1 ? B - S2 : INFINITY;
+            p.pi[s_idx] = arg;
+            p.gap[s_idx] = R > 1 ? best - second : INFINITY;
         } else {
-            // a sweep needs only the max
-            double best = -DBL_MAX;
-#pragma unroll
-            for (int e = 0; e < RH; ++e) best = fmax(best, fma(p.gamma, acc[i][e].value(), ca[e]));
-            best = fmax(best, __shfl_xor(best, 1, 64));
-            if (!active || half || X1 >= R) continue;
-            const int64_t s_idx = (int64_t)tile * ns_tile + X2 * R + X1;
             const double r0 = p.r0[X1 * p.xt + X1 + X2 + b];
             const VT o = (VT)(r0 - mu + best);
             reinterpret_cast<VT*>(p.v_out)[s_idx] = o;
@@ -279,10 +192,87 @@ __global__ __launch_bounds__(512) void backup_a_kernel(ADev p) {
             vmx = fmax(vmx, out);
             vmn = fmin(vmn, out);
         }
+    };
+    auto take = [&](double qv, int a, double& best, double& second, int& arg) {
+        if (EXTRACT) {
+            if (qv > best) {
+                second = best;
+                best = qv;
+                arg = a;
+            } else if (qv > second) {
+                second = qv;
+            }
+        } else {
+            best = fmax(best, qv);
+        }
+    };
+
+    // N = 0 (only when b = 0): nothing left to deplete, every demand lands on S[0]
+    if (b == 0 && lane < R) {
+        const VV* rz = reinterpret_cast<const VV*>(S);
+        double best = -DBL_MAX, second = -DBL_MAX;
+        int arg = 0;
+#pragma unroll
+        for (int q = 0; q < RMAX / W; ++q) {
+            const VV s0 = rz[q];
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                const int a = q * W + e;
+                if (a < R)
+                    take(fma(p.gamma, (double)lane_of<VT, W>(s0, e), -p.cvar * a), a, best,
+                         second, arg);
+            }
+        }
+        finish(0, lane, best, second, arg);
+    }
+    const int nmin = b > 1 ? b : 1, nmax = b + p.r2 - 1;
+    const int u = nmin + lane;  // this lane's diagonal
+    const bool live = u <= nmax + R - 1;
+    Acc<VT, KAHAN> acc[RMAX];
+    for (int N = 1; N <= nmax; ++N) {
+        const int X1 = u - N;
+        if (N >= nmin && live && X1 >= 0 && X1 < R) {
+            // E_a = F(X_1) S[N][a] + C(u, N) + G(u) S[0][a]
+            const double fw = sF[min(X1, p.dmax)], gw = sG[u];
+            const VV* rN = reinterpret_cast<const VV*>(S + N * RMAX);
+            const VV* rz = reinterpret_cast<const VV*>(S);
+            double best = -DBL_MAX, second = -DBL_MAX;
+            int arg = 0;
+#pragma unroll
+            for (int q = 0; q < RMAX / W; ++q) {
+                const VV sn = rN[q], s0 = rz[q];
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    const int a = q * W + e;
+                    if (a < R) {
+                        const double ev = fma(gw, (double)lane_of<VT, W>(s0, e),
+                                              fma(fw, (double)lane_of<VT, W>(sn, e),
+                                                  acc[a].value()));
+                        take(fma(p.gamma, ev, -p.cvar * a), a, best, second, arg);
+                    }
+                }
+            }
+            finish(N - b, X1, best, second, arg);
+        }
+        if (N == nmax) break;
+        // add path point j = N with weight P(u - N) (zero past d_max or below 1);
+        // lanes past the last diagonal add nothing and read nothing
+        const int di = u - N;
+        const AW w = (AW)(live && di >= 1 ? sP[di] : 0.0);
+        const VV* rj = reinterpret_cast<const VV*>(S + N * RMAX);
+#pragma unroll
+        for (int q = 0; q < RMAX / W; ++q) {
+            const VV sj = rj[q];
+#pragma unroll
+            for (int e = 0; e < W; ++e) acc[q * W + e].add(w, lane_of<VT, W>(sj, e));
+        }
     }
     if (EXTRACT) return;
-    block_reduce4(dmx, dmn, vmx, vmn, red);
-    if (tid == 0) {
+    dmx = wave_max(dmx);
+    dmn = wave_min(dmn);
+    vmx = wave_max(vmx);
+    vmn = wave_min(vmn);
+    if (lane == 0) {
         double* pp = p.partials + 4 * (size_t)tile;
         pp[0] = dmx;
         pp[1] = dmn;
@@ -332,17 +322,15 @@ __global__ void to_f32_kernel(const double* v64, float* v32, double c, int64_t n
 
 template <typename VT, bool KAHAN, bool EXTRACT, int RMAX>
 static hipError_t launch_a_r(const ADev& p, hipStream_t s) {
-    constexpr int J = 4;  // states per lane (two lanes per group of states)
     const int lp_max = (p.m >= 2 ? (p.m - 2) * (p.R - 1) : 0) + p.r2;
     size_t bytes = sizeof(VT) * (size_t)lp_max * RMAX;
-    bytes += sizeof(double) * (3 * (size_t)p.tab + 64);
+    bytes += sizeof(double) * 3 * (size_t)p.tab;
     if (bytes > 65536) return hipErrorInvalidConfiguration;  // beyond the default LDS limit
-    if (p.tab < p.R + J + lp_max || p.tab < p.dmax + 2 + J) return hipErrorInvalidValue;
-    const int lanes = 2 * p.r2 * ((p.R + J - 1) / J);
-    const int threads = ((lanes + 63) / 64) * 64;
-    if (threads > 512) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT>), dim3(p.tiles),
-                       dim3(threads), bytes, s, p);
+    // lanes cover u = N + X_1 for every emitted state: at most 2R - 1 diagonals
+    if (p.r2 + p.R - 1 > 64) return hipErrorInvalidConfiguration;
+    if (p.tab < p.R + lp_max + 1 || p.tab < p.dmax + 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT>), dim3(p.tiles), dim3(64),
+                       bytes, s, p);
     return hipGetLastError();
 }
 
