@@ -104,6 +104,14 @@ struct Acc<float, true> {
     __device__ __forceinline__ double value() const { return (double)s - (double)c; }
 };
 
+// Value staged for the padding actions R <= a < RMAX: so negative that their Q
+// never wins the max, small enough that weighted sums of it (total weight <= 1)
+// stay finite.  With it the action loops need no bound check.
+template <typename VT>
+__device__ constexpr VT kPadValue = VT(-1e30);
+template <>
+__device__ constexpr double kPadValue<double> = -1e300;
+
 // One wavefront per tile; VT: storage type of V (float = centred FP32, double = FP64);
 // KAHAN: FP32 compensated accumulation (only with VT = float), else FP64.
 // EXTRACT: write policy and Q gap instead of V (FP64 only).
@@ -147,10 +155,13 @@ __global__ __launch_bounds__(64) void backup_a_kernel(ADev p) {
     double* sF = sP + p.tab;
     double* sG = sF + p.tab;
 
+    // weights staged premultiplied by gamma, so that sums of weighted values are
+    // already discounted
+    const double g = p.gamma;
     for (int i = lane; i < p.tab; i += 64) {
-        sP[i] = p.pmf[i];
-        sF[i] = p.cdf[i];
-        sG[i] = p.tail[i];
+        sP[i] = g * p.pmf[i];
+        sF[i] = g * p.cdf[i];
+        sG[i] = g * p.tail[i];
     }
     const VT* vin = reinterpret_cast<const VT*>(p.v_in);
     const int64_t hbase = (int64_t)h * p.stride_h;
@@ -164,7 +175,7 @@ __global__ __launch_bounds__(64) void backup_a_kernel(ADev p) {
 #pragma unroll
             for (int e = 0; e < W; ++e) {
                 const int a = q * W + e;
-                v[e] = a < R ? src[(int64_t)a * p.stride_a] : VT(0);
+                v[e] = a < R ? src[(int64_t)a * p.stride_a] : kPadValue<VT>;
             }
             dst[q] = make_vec<VT>(v);
         }
@@ -177,16 +188,18 @@ __global__ __launch_bounds__(64) void backup_a_kernel(ADev p) {
 
     // Writes one state from the Q of its actions: the policy and gap, or V' and
     // the running max/min of V' - V and of V'.
-    auto finish = [&](int X2, int X1, double best, double second, int arg) {
+    // r0n and vold are the state's reward-table entry and its current value,
+    // loaded ahead of time by the caller.
+    auto finish = [&](int X2, int X1, double best, double second, int arg, double r0n,
+                      double vold) {
         const int64_t s_idx = (int64_t)tile * ns_tile + X2 * R + X1;
         if (EXTRACT) {
             p.pi[s_idx] = arg;
             p.gap[s_idx] = R > 1 ? best - second : INFINITY;
         } else {
-            const double r0 = p.r0[X1 * p.xt + X1 + X2 + b];
-            const VT o = (VT)(r0 - mu + best);
+            const VT o = (VT)(r0n - mu + best);
             reinterpret_cast<VT*>(p.v_out)[s_idx] = o;
-            const double out = (double)o, dv = out - (double)vin[s_idx];
+            const double out = (double)o, dv = out - vold;
             dmx = fmax(dmx, dv);
             dmn = fmin(dmn, dv);
             vmx = fmax(vmx, out);
@@ -209,6 +222,11 @@ __global__ __launch_bounds__(64) void backup_a_kernel(ADev p) {
 
     // N = 0 (only when b = 0): nothing left to deplete, every demand lands on S[0]
     if (b == 0 && lane < R) {
+        double r0n = 0.0, vold = 0.0;
+        if (!EXTRACT) {
+            r0n = p.r0[lane * p.xt + lane];
+            vold = (double)vin[(int64_t)tile * ns_tile + lane];
+        }
         const VV* rz = reinterpret_cast<const VV*>(S);
         double best = -DBL_MAX, second = -DBL_MAX;
         int arg = 0;
@@ -218,53 +236,102 @@ __global__ __launch_bounds__(64) void backup_a_kernel(ADev p) {
 #pragma unroll
             for (int e = 0; e < W; ++e) {
                 const int a = q * W + e;
-                if (a < R)
-                    take(fma(p.gamma, (double)lane_of<VT, W>(s0, e), -p.cvar * a), a, best,
-                         second, arg);
+                take(fma(g, (double)lane_of<VT, W>(s0, e), -p.cvar * a), a, best, second, arg);
             }
         }
-        finish(0, lane, best, second, arg);
+        finish(0, lane, best, second, arg, r0n, vold);
     }
     const int nmin = b > 1 ? b : 1, nmax = b + p.r2 - 1;
     const int u = nmin + lane;  // this lane's diagonal
     const bool live = u <= nmax + R - 1;
+    // The accumulator starts from the j = 0 term G(u) S[0] (and, for FP64
+    // accumulation, the order cost), so a state needs only F(X_1) S[N] on top.
     Acc<VT, KAHAN> acc[RMAX];
-    for (int N = 1; N <= nmax; ++N) {
-        const int X1 = u - N;
-        if (N >= nmin && live && X1 >= 0 && X1 < R) {
-            // E_a = F(X_1) S[N][a] + C(u, N) + G(u) S[0][a]
-            const double fw = sF[min(X1, p.dmax)], gw = sG[u];
-            const VV* rN = reinterpret_cast<const VV*>(S + N * RMAX);
-            const VV* rz = reinterpret_cast<const VV*>(S);
-            double best = -DBL_MAX, second = -DBL_MAX;
-            int arg = 0;
-#pragma unroll
-            for (int q = 0; q < RMAX / W; ++q) {
-                const VV sn = rN[q], s0 = rz[q];
-#pragma unroll
-                for (int e = 0; e < W; ++e) {
-                    const int a = q * W + e;
-                    if (a < R) {
-                        const double ev = fma(gw, (double)lane_of<VT, W>(s0, e),
-                                              fma(fw, (double)lane_of<VT, W>(sn, e),
-                                                  acc[a].value()));
-                        take(fma(p.gamma, ev, -p.cvar * a), a, best, second, arg);
-                    }
-                }
-            }
-            finish(N - b, X1, best, second, arg);
-        }
-        if (N == nmax) break;
-        // add path point j = N with weight P(u - N) (zero past d_max or below 1);
-        // lanes past the last diagonal add nothing and read nothing
-        const int di = u - N;
-        const AW w = (AW)(live && di >= 1 ? sP[di] : 0.0);
-        const VV* rj = reinterpret_cast<const VV*>(S + N * RMAX);
+    {
+        const AW g0 = (AW)(live ? sG[u] : 0.0);
+        const VV* rz = reinterpret_cast<const VV*>(S);
 #pragma unroll
         for (int q = 0; q < RMAX / W; ++q) {
-            const VV sj = rj[q];
+            const VV s0 = rz[q];
 #pragma unroll
-            for (int e = 0; e < W; ++e) acc[q * W + e].add(w, lane_of<VT, W>(sj, e));
+            for (int e = 0; e < W; ++e) {
+                const int a = q * W + e;
+                if constexpr (KAHAN)
+                    acc[a].add(g0, lane_of<VT, W>(s0, e));
+                else
+                    acc[a].s = fma((double)g0, (double)lane_of<VT, W>(s0, e), -p.cvar * a);
+            }
+        }
+    }
+    // The lane's state at step N is X_1 = u - N, X_2 = N - b; its reward-table
+    // entry and old value are fetched one step ahead so the loads overlap the
+    // arithmetic.
+    auto emits = [&](int N) {
+        const int X1 = u - N;
+        return N >= nmin && N <= nmax && live && X1 >= 0 && X1 < R;
+    };
+    double r0n = 0.0, vold = 0.0;
+    auto prefetch = [&](int N) {
+        if (!EXTRACT && emits(N)) {
+            const int X1 = u - N, X2 = N - b;
+            r0n = p.r0[X1 * p.xt + X1 + X2 + b];
+            vold = (double)vin[(int64_t)tile * ns_tile + X2 * R + X1];
+        }
+    };
+    prefetch(1);
+    for (int N = 1; N <= nmax; ++N) {
+        // one read of path point N serves the states emitted here and the running sum
+        const VV* rN = reinterpret_cast<const VV*>(S + N * RMAX);
+        VV sn[RMAX / W];
+#pragma unroll
+        for (int q = 0; q < RMAX / W; ++q) sn[q] = rN[q];
+        // both weights read up front (clamped indices, always in the table) so the
+        // reads overlap the arithmetic
+        const int di = u - N;  // = X_1 of the state emitted here
+        const double fwr = sF[min(max(di, 0), p.dmax)];
+        const double pwr = sP[min(max(di, 0), p.tab - 1)];
+        const double r0c = r0n, voldc = vold;
+        prefetch(N + 1);
+        if (emits(N)) {
+            // Q_a = gamma (F(X_1) S[N][a] + C(u, N) + G(u) S[0][a]) - c_var a
+            double best = -DBL_MAX, second = -DBL_MAX;
+            int arg = 0;
+            if constexpr (EXTRACT) {
+#pragma unroll
+                for (int q = 0; q < RMAX / W; ++q) {
+#pragma unroll
+                    for (int e = 0; e < W; ++e) {
+                        const int a = q * W + e;
+                        const double sv = (double)lane_of<VT, W>(sn[q], e);
+                        take(fma(fwr, sv, acc[a].value()), a, best, second, arg);
+                    }
+                }
+            } else {
+                // four independent max chains, merged at the end
+                double bq[4] = {-DBL_MAX, -DBL_MAX, -DBL_MAX, -DBL_MAX};
+#pragma unroll
+                for (int q = 0; q < RMAX / W; ++q) {
+#pragma unroll
+                    for (int e = 0; e < W; ++e) {
+                        const int a = q * W + e;
+                        const double sv = (double)lane_of<VT, W>(sn[q], e);
+                        const double qv = KAHAN ? fma(fwr, sv, acc[a].value()) - p.cvar * a
+                                                : fma(fwr, sv, acc[a].value());
+                        bq[a & 3] = fmax(bq[a & 3], qv);
+                    }
+                }
+                best = fmax(fmax(bq[0], bq[1]), fmax(bq[2], bq[3]));
+            }
+            finish(N - b, di, best, second, arg, r0c, voldc);
+        }
+        if (N == nmax) break;
+        // add path point j = N with weight P(u - N) (zero below 1; the table is
+        // zero past d_max); lanes past the last diagonal add nothing
+        const AW w = (AW)(live && di >= 1 ? pwr : 0.0);
+#pragma unroll
+        for (int q = 0; q < RMAX / W; ++q) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) acc[q * W + e].add(w, lane_of<VT, W>(sn[q], e));
         }
     }
     if (EXTRACT) return;

@@ -59,8 +59,11 @@ static void build_a_tables(pvi_mdp* p) {
             }
             p->a_r0[(size_t)x1 * p->xt + X] = e;
         }
-    // multiply-adds the kernel runs per sweep: for every state and action,
-    // min(K, d_max - X_1) + 1 terms (1 when K = 0), K = X_2 + ... + X_m
+    // multiply-adds that contribute to a result, per sweep, in the per-diagonal
+    // prefix-sum scheme: for a tile of digit sum b (of X_m..X_3) and one action,
+    // every live diagonal u in [max(b,1), b + r2 + R - 2] accumulates once per path
+    // point (N = 0 .. b + r2 - 2, the first being the G(u) S[0] start), and every
+    // one of the r2 * R states adds F(X_1) S[N] once
     const int nz_dig = std::max(p->m - 2, 0);
     std::vector<int64_t> cnt(1, 1);  // number of (X_m..X_3) with digit sum b
     for (int i = 0; i < nz_dig; ++i) {
@@ -74,13 +77,9 @@ static void build_a_tables(pvi_mdp* p) {
     const int r2 = p->m >= 2 ? R : 1;
     int64_t ex = 0;
     for (size_t b = 0; b < cnt.size(); ++b) {
-        int64_t per = 0;
-        for (int x2 = 0; x2 < r2; ++x2)
-            for (int x1 = 0; x1 < R; ++x1) {
-                const int N = (int)b + x2;
-                const int kmax = N == 0 ? 0 : std::max(0, std::min(N, dm - x1));
-                per += kmax + 1;
-            }
+        const int nmin = std::max((int)b, 1), nmax = (int)b + r2 - 1;
+        const int64_t live = std::max(0, nmax + R - 1 - nmin + 1);
+        const int64_t per = (nmax >= 1 ? live * nmax : 0) + (int64_t)r2 * R;
         ex += cnt[b] * per;
     }
     p->executed_per_sweep = nh * ex * R;
