@@ -22,6 +22,10 @@ ADev make_adev(const pvi_mdp* p) {
     a.nz = p->m >= 2 ? (int)ipow(R, p->m - 2) : 1;
     a.r2 = p->m >= 2 ? R : 1;
     a.tiles = (int)(ipow(R, p->L - 1) * a.nz);
+    a.G = p->a_G;
+    a.CH = p->a_CH;
+    a.groups = p->dev.agroups;
+    a.ngroups = p->a_G > 0 ? (int)(p->a_groups.size() / p->a_G) : 0;
     a.stride_a = ipow(R, p->m + p->L - 2);
     a.stride_h = ipow(R, p->m - 1);
     for (int i = 0; i < 8; ++i) a.pow_y[i] = (int)ipow(R, i);
@@ -132,10 +136,8 @@ std::string family_support_msg(const pvi_mdp* p) {
 bool family_supported(const pvi_mdp* p) { return family_support_msg(p) == "ok"; }
 
 int family_tiles(const pvi_mdp* p) {
-    if (p->family == PVI_FAMILY_LEADTIME) {
-        const int R = p->rad[0];
-        return (int)(ipow(R, p->L - 1) * (p->m >= 2 ? ipow(R, p->m - 2) : 1));
-    }
+    if (p->family == PVI_FAMILY_LEADTIME)  // one span partial per tile group
+        return p->a_G > 0 ? (int)(p->a_groups.size() / p->a_G) : 1;
     if (p->family == PVI_FAMILY_SUBST2) return (int)ipow(p->rad[1], p->m - 1);
     if (p->family == PVI_FAMILY_RUL_WEEKDAY)
         return (int)(p->P * ((ipow(p->rad[0], p->m - 1) + 255) / 256));
@@ -144,7 +146,8 @@ int family_tiles(const pvi_mdp* p) {
 
 size_t family_extra_bytes(const pvi_mdp* p) {
     if (p->family == PVI_FAMILY_LEADTIME)
-        return sizeof(double) * (3 * (size_t)p->tab + p->a_r0.size());
+        return sizeof(double) * (3 * (size_t)p->tab + p->a_r0.size()) +
+               sizeof(int32_t) * p->a_groups.size();
     if (p->family == PVI_FAMILY_SUBST2)
         return sizeof(double) * ((size_t)p->b_rows * ipow(p->rad[1], p->m) + p->b_rexp0.size() +
                                  3 * p->b_epmf.size() + p->b_rexp1.size() + p->pmf[0].size());
@@ -166,6 +169,8 @@ static hipError_t upload_vec(T** dst, const std::vector<T>& src) {
 
 pvi_status family_init(pvi_mdp* p) {
     auto& d = p->dev;
+    if (p->family == PVI_FAMILY_LEADTIME && upload_vec(&d.agroups, p->a_groups) != hipSuccess)
+        return fail(PVI_E_NOMEM, "scenario A work list allocation failed");
     if (p->family == PVI_FAMILY_SUBST2) {
         const size_t zn = (size_t)p->b_rows * ipow(p->rad[1], p->m);
         if (hipMalloc((void**)&d.z, sizeof(double) * zn) != hipSuccess ||
@@ -201,13 +206,14 @@ void family_free(pvi_mdp* p) {
     auto& d = p->dev;
     void* bufs[] = {d.z,    d.rexp0, d.epmf,  d.ecdf,  d.etail, d.rexp1, d.cu,  d.ct0,
                     d.ct1,  d.cpmf,  d.ccdf,  d.ctail, d.cr0,   d.cbinq,  d.cbinm, d.cpy,
-                    d.cpr,  d.cpb};
+                    d.cpr,  d.cpb, d.agroups};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     d.z = d.rexp0 = d.epmf = d.ecdf = d.etail = d.rexp1 = nullptr;
     d.cu = d.ct0 = d.ct1 = nullptr;
     d.cpmf = d.ccdf = d.ctail = d.cr0 = d.cbinq = d.cbinm = nullptr;
     d.cpy = d.cpr = d.cpb = nullptr;
+    d.agroups = nullptr;
 }
 
 // No family fuses the span today: a device-wide release fence per workgroup (needed

@@ -16,14 +16,13 @@
 //         E_a(X_1, y) = F(X_1) V[path_0] + sum_{0<k<K} P(X_1+k) V[path_k]
 //                       + P(D >= X_1+K) V[path_K],
 //     where path_k is y depleted by k units.  For a fixed (X_m..X_3) the paths of
-//     all X_2 lie on one descending list of (m-1)(R-1)+1 points at most, so a
-//     workgroup stages that list for every action in LDS and each lane (one
-//     state (X_2, X_1)) walks its own suffix of it.  Per state and action this
-//     is K+1 <= d_max+1 multiply-adds instead of d_max+1 gathers.
+//     all X_2 lie on one descending list of (m-1)(R-1)+1 points at most, and a
+//     per-diagonal prefix sum over that list (kernel comment below) gives every
+//     state of the tile for every action.
 //
-// Workgroup = one tile (O, X_m..X_3) of R*R states (X_2, X_1); lanes = states.
-// Ties in the max go to the lowest action.  No atomics: every reduction is a
-// fixed tree, so reruns are bit-identical.
+// Wavefront = G tiles (O, X_m..X_3) of one digit sum, R lanes per tile; the tile's
+// path list streams through LDS.  Ties in the max go to the lowest action.  No
+// atomics: every reduction is a fixed tree, so reruns are bit-identical.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -112,87 +111,133 @@ __device__ constexpr VT kPadValue = VT(-1e30);
 template <>
 __device__ constexpr double kPadValue<double> = -1e300;
 
-// One wavefront per tile; VT: storage type of V (float = centred FP32, double = FP64);
-// KAHAN: FP32 compensated accumulation (only with VT = float), else FP64.
-// EXTRACT: write policy and Q gap instead of V (FP64 only).
+// One wavefront per group of G tiles of equal digit sum b; VT: storage type of V
+// (float = centred FP32, double = FP64); KAHAN: FP32 compensated accumulation (only
+// with VT = float), else FP64.  EXTRACT: write policy and Q gap instead of V (FP64).
 //
-// For a state (X_2, X_1) of the tile put N = b + X_2 (its path length, b the sum
-// of the tile's fixed digits) and u = X_1 + N.  For N >= 1,
+// For a state (X_2, X_1) of a tile put N = b + X_2 (its path length) and
+// u = X_1 + N.  For N >= 1,
 //   E = F(X_1) S[N] + C(u, N) + G(u) S[0],   C(u, N) = sum_{j=1}^{N-1} P(u - j) S[j],
-// with F = P(D <= .), G = P(D >= .) and S the staged path list.  For a fixed u,
-// C(u, N) is a running sum over the path points, so lane u accumulates it once for
-// every action (in registers) while N walks up the list, and emits the states of
-// its diagonal (X_1 = u - N in [0, R)) as N passes them.  The single-point state
-// (N = 0, only when b = 0) takes S[0] for every demand.  All actions live in one
-// lane, so the max needs no exchange.
+// with F = P(D <= .), G = P(D >= .) and S the tile's path list.  For a fixed u,
+// C(u, N) is a running sum over the path points, walked once for every action while
+// N moves up the list; the states of diagonal u (X_1 = u - N in [0, R)) are emitted
+// as N passes them.  The live diagonals are u in [n0, n0 + 2R - 2], n0 = max(b, 1).
+// Lane l of a tile carries two of them, u1 = n0 + l and u2 = u1 + R: at every step
+// N in [n0, b + R - 1] exactly one of the two is on the emitting window
+// [N, N + R - 1] (u1 while u1 >= N, then u2), so each of the R lanes emits one state
+// per step and a wavefront of G = floor(64 / R) tiles keeps nearly every lane busy.
+// The lane keeps A1 = C(u1) and D = C(u2) - C(u1); the emitted running sum is
+// A1 + m D with m in {0, 1}, one multiply-add.  The path list streams through LDS in
+// chunks of CH points, double buffered: the next chunk's values are loaded into
+// registers while the current one is used.  The single-point state (N = 0, b = 0)
+// takes S[0] for every demand.  All actions of a state live in one lane, so the max
+// needs no exchange.  Weights are staged premultiplied by gamma.
 template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
-__global__ __launch_bounds__(64) void backup_a_kernel(ADev p) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void backup_a_body(const ADev& p, unsigned char* smem) {
     Ctl* ctl = p.ctl;
     if (!EXTRACT && ctl->stop) return;
     constexpr int W = VecLoad<VT>::W;
+    constexpr int SPL = 8;              // actions one staging lane loads
+    constexpr int NSPLIT = RMAX / SPL;  // staging lanes per path point
     using VV = typename VecLoad<VT>::V;
     using AW = typename Acc<VT, KAHAN>::W;
 
-    const int R = p.R, m = p.m, lane = threadIdx.x;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int h = tile / p.nz;
-    int Y[9];
+    const int R = p.R, m = p.m, G = p.G, CH = p.CH, lane = threadIdx.x;
+    const int grp = xcd_remap(blockIdx.x, gridDim.x);
+    const int32_t* gt = p.groups + (size_t)grp * G;
+    const int first = gt[0];  // a group's first slot always holds a tile
+
+    // compute role: tile slot g, position l; lanes past G * R and the slots of a
+    // short group repeat tile `first` without writing anything
+    int g = lane / R;
+    const int l = lane - g * R;
+    bool valid = g < G;
+    if (!valid) g = 0;
+    int tile = gt[g];
+    if (tile < 0) {
+        valid = false;
+        tile = first;
+    }
     int b = 0;
     {
-        int t = tile - h * p.nz;
+        int t = tile % p.nz;
         for (int i = 2; i <= m - 1; ++i) {
-            Y[i] = t % R;
+            b += t % R;
             t /= R;
-            b += Y[i];
         }
     }
-    const int lp = b + p.r2;
+    const int lp = b + p.r2;  // path points 0 .. lp - 1, the same for the whole group
 
-    VT* S = reinterpret_cast<VT*>(smem);
-    // RMAX is a multiple of 8, so the staged block ends on a 32-byte boundary.
-    double* sP = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)lp * RMAX);
+    // staging role: action slice sh, tile slot sg, point sj of every chunk
+    const int npair = G * CH;
+    const bool stager = lane < NSPLIT * npair;
+    const int sh = lane / npair, spair = lane - sh * npair;
+    const int sg = spair / CH, sj = spair - sg * CH;
+    int64_t s_base = 0;
+    int sY[9];
+    {
+        int st = stager ? gt[sg] : first;
+        if (st < 0) st = first;
+        const int sht = st / p.nz;
+        int t = st - sht * p.nz;
+        for (int i = 2; i <= m - 1; ++i) {
+            sY[i] = t % R;
+            t /= R;
+        }
+        s_base = (int64_t)sht * p.stride_h;
+    }
+
+    VT* buf = reinterpret_cast<VT*>(smem);  // [2][G][CH][RMAX]
+    // RMAX is a multiple of 8, so every staged row starts on a 32-byte boundary
+    double* sP = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)2 * npair * RMAX);
     double* sF = sP + p.tab;
     double* sG = sF + p.tab;
-
-    // weights staged premultiplied by gamma, so that sums of weighted values are
-    // already discounted
-    const double g = p.gamma;
-    for (int i = lane; i < p.tab; i += 64) {
-        sP[i] = g * p.pmf[i];
-        sF[i] = g * p.cdf[i];
-        sG[i] = g * p.tail[i];
-    }
     const VT* vin = reinterpret_cast<const VT*>(p.v_in);
-    const int64_t hbase = (int64_t)h * p.stride_h;
-    // one lane per path point: its block offset once, then every action's value
-    for (int j = lane; j < lp; j += 64) {
-        const VT* src = vin + hbase + path_offset(j, Y, m, p.pow_y);
-        VV* dst = reinterpret_cast<VV*>(S + j * RMAX);
+
+    VT pre[SPL];
+    auto load_chunk = [&](int c) {
+        const int j = c * CH + sj;
+        if (stager && j < lp) {
+            const VT* src = vin + s_base + path_offset(j, sY, m, p.pow_y);
 #pragma unroll
-        for (int q = 0; q < RMAX / W; ++q) {
-            VT v[W];
-#pragma unroll
-            for (int e = 0; e < W; ++e) {
-                const int a = q * W + e;
-                v[e] = a < R ? src[(int64_t)a * p.stride_a] : kPadValue<VT>;
+            for (int e = 0; e < SPL; ++e) {
+                const int a = sh * SPL + e;
+                pre[e] = a < R ? src[(int64_t)a * p.stride_a] : kPadValue<VT>;
             }
-            dst[q] = make_vec<VT>(v);
         }
+    };
+    auto store_chunk = [&](int c) {
+        if (stager && c * CH + sj < lp) {
+            VV* dst = reinterpret_cast<VV*>(buf + ((size_t)((c & 1) * G + sg) * CH + sj) * RMAX +
+                                            sh * SPL);
+#pragma unroll
+            for (int q = 0; q < SPL / W; ++q) dst[q] = make_vec<VT>(&pre[q * W]);
+        }
+    };
+
+    load_chunk(0);
+    const double gm = p.gamma;
+    for (int i = lane; i < p.tab; i += 64) {
+        sP[i] = gm * p.pmf[i];
+        sF[i] = gm * p.cdf[i];
+        sG[i] = gm * p.tail[i];
     }
+    store_chunk(0);
     __syncthreads();
+    const int nchunks = (lp + CH - 1) / CH;
+    if (nchunks > 1) load_chunk(1);
 
     const int ns_tile = p.r2 * R;
+    const int64_t tbase = (int64_t)tile * ns_tile;
     const double mu = (!EXTRACT && sizeof(VT) == 4) ? ctl->mu : 0.0;
+    const double cv = p.cvar;
     double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
 
-    // Writes one state from the Q of its actions: the policy and gap, or V' and
-    // the running max/min of V' - V and of V'.
     // r0n and vold are the state's reward-table entry and its current value,
-    // loaded ahead of time by the caller.
+    // loaded ahead of time by the caller
     auto finish = [&](int X2, int X1, double best, double second, int arg, double r0n,
                       double vold) {
-        const int64_t s_idx = (int64_t)tile * ns_tile + X2 * R + X1;
+        const int64_t s_idx = tbase + X2 * R + X1;
         if (EXTRACT) {
             p.pi[s_idx] = arg;
             p.gap[s_idx] = R > 1 ? best - second : INFINITY;
@@ -207,131 +252,142 @@ __global__ __launch_bounds__(64) void backup_a_kernel(ADev p) {
         }
     };
     auto take = [&](double qv, int a, double& best, double& second, int& arg) {
-        if (EXTRACT) {
-            if (qv > best) {
-                second = best;
-                best = qv;
-                arg = a;
-            } else if (qv > second) {
-                second = qv;
-            }
-        } else {
-            best = fmax(best, qv);
+        if (qv > best) {
+            second = best;
+            best = qv;
+            arg = a;
+        } else if (qv > second) {
+            second = qv;
         }
     };
 
+    const VV* row0 = reinterpret_cast<const VV*>(buf + (size_t)g * CH * RMAX);
     // N = 0 (only when b = 0): nothing left to deplete, every demand lands on S[0]
-    if (b == 0 && lane < R) {
+    if (b == 0 && valid) {
         double r0n = 0.0, vold = 0.0;
         if (!EXTRACT) {
-            r0n = p.r0[lane * p.xt + lane];
-            vold = (double)vin[(int64_t)tile * ns_tile + lane];
+            r0n = p.r0[l * p.xt + l];
+            vold = (double)vin[tbase + l];
         }
-        const VV* rz = reinterpret_cast<const VV*>(S);
         double best = -DBL_MAX, second = -DBL_MAX;
         int arg = 0;
 #pragma unroll
         for (int q = 0; q < RMAX / W; ++q) {
-            const VV s0 = rz[q];
+            const VV s0 = row0[q];
 #pragma unroll
             for (int e = 0; e < W; ++e) {
                 const int a = q * W + e;
-                take(fma(g, (double)lane_of<VT, W>(s0, e), -p.cvar * a), a, best, second, arg);
+                const double qv = fma(gm, (double)lane_of<VT, W>(s0, e), -cv * a);
+                if (EXTRACT)
+                    take(qv, a, best, second, arg);
+                else
+                    best = fmax(best, qv);
             }
         }
-        finish(0, lane, best, second, arg, r0n, vold);
+        finish(0, l, best, second, arg, r0n, vold);
     }
-    const int nmin = b > 1 ? b : 1, nmax = b + p.r2 - 1;
-    const int u = nmin + lane;  // this lane's diagonal
-    const bool live = u <= nmax + R - 1;
-    // The accumulator starts from the j = 0 term G(u) S[0] (and, for FP64
-    // accumulation, the order cost), so a state needs only F(X_1) S[N] on top.
-    Acc<VT, KAHAN> acc[RMAX];
+
+    const int n0 = b > 1 ? b : 1, nmax = lp - 1;
+    const int u1 = n0 + l, u2 = u1 + R;
+    // start from the j = 0 term G(u) S[0] (and, with FP64 accumulation, the order
+    // cost, which the difference D does not carry)
+    Acc<VT, KAHAN> A1[RMAX], D[RMAX];
     {
-        const AW g0 = (AW)(live ? sG[u] : 0.0);
-        const VV* rz = reinterpret_cast<const VV*>(S);
+        const double g1 = sG[u1], g2 = sG[u2];
+        const AW gd = (AW)(g2 - g1);
 #pragma unroll
         for (int q = 0; q < RMAX / W; ++q) {
-            const VV s0 = rz[q];
+            const VV s0 = row0[q];
 #pragma unroll
             for (int e = 0; e < W; ++e) {
                 const int a = q * W + e;
+                const VT sv = lane_of<VT, W>(s0, e);
                 if constexpr (KAHAN)
-                    acc[a].add(g0, lane_of<VT, W>(s0, e));
+                    A1[a].add((AW)g1, sv);
                 else
-                    acc[a].s = fma((double)g0, (double)lane_of<VT, W>(s0, e), -p.cvar * a);
+                    A1[a].s = fma(g1, (double)sv, -cv * a);
+                D[a].add(gd, sv);
             }
         }
     }
-    // The lane's state at step N is X_1 = u - N, X_2 = N - b; its reward-table
-    // entry and old value are fetched one step ahead so the loads overlap the
-    // arithmetic.
-    auto emits = [&](int N) {
-        const int X1 = u - N;
-        return N >= nmin && N <= nmax && live && X1 >= 0 && X1 < R;
-    };
+
+    // the state emitted at step N: X_1 = u1 - N while u1 >= N, else u2 - N; its
+    // reward-table entry and old value are fetched one step ahead
     double r0n = 0.0, vold = 0.0;
     auto prefetch = [&](int N) {
-        if (!EXTRACT && emits(N)) {
-            const int X1 = u - N, X2 = N - b;
+        if (!EXTRACT && valid && N >= n0 && N <= nmax) {
+            const int X1 = (u1 >= N ? u1 : u2) - N, X2 = N - b;
             r0n = p.r0[X1 * p.xt + X1 + X2 + b];
-            vold = (double)vin[(int64_t)tile * ns_tile + X2 * R + X1];
+            vold = (double)vin[tbase + X2 * R + X1];
         }
     };
     prefetch(1);
+    int c = 0, cj = 0;  // chunk of the current point and position inside it
     for (int N = 1; N <= nmax; ++N) {
-        // one read of path point N serves the states emitted here and the running sum
-        const VV* rN = reinterpret_cast<const VV*>(S + N * RMAX);
-        VV sn[RMAX / W];
-#pragma unroll
-        for (int q = 0; q < RMAX / W; ++q) sn[q] = rN[q];
-        // both weights read up front (clamped indices, always in the table) so the
-        // reads overlap the arithmetic
-        const int di = u - N;  // = X_1 of the state emitted here
-        const double fwr = sF[min(max(di, 0), p.dmax)];
-        const double pwr = sP[min(max(di, 0), p.tab - 1)];
+        if (++cj == CH) {  // entering chunk c + 1: publish it, start loading the next
+            cj = 0;
+            ++c;
+            store_chunk(c);
+            __syncthreads();
+            if (c + 1 < nchunks) load_chunk(c + 1);
+        }
+        // point N serves the emitted state and both running sums; each pair (or
+        // quad) of actions is read, used and dropped, so the row is never held whole
+        const VV* rN = reinterpret_cast<const VV*>(buf + ((size_t)((c & 1) * G + g) * CH + cj) * RMAX);
+        const int d1 = u1 - N, d2 = u2 - N;
+        const bool on2 = d1 < 0;
+        const int X1 = on2 ? d2 : d1;
+        const double fwr = sF[min(max(X1, 0), p.dmax)];
+        const double pw1 = sP[min(max(d1, 0), p.tab - 1)];
+        const double pw2 = sP[min(max(d2, 0), p.tab - 1)];
+        // weight P(u - N) for u - N >= 1 (the table is zero past d_max); a finished
+        // diagonal (u - N <= 0) adds nothing
+        const double w1d = d1 >= 1 ? pw1 : 0.0;
+        const AW w1 = (AW)w1d;
+        const AW wd = (AW)((d2 >= 1 ? pw2 : 0.0) - w1d);
+        const bool last = N == nmax;  // the sums are not needed after the last point
         const double r0c = r0n, voldc = vold;
         prefetch(N + 1);
-        if (emits(N)) {
+        if (N >= n0) {  // uniform: every lane of the group emits from here on
             // Q_a = gamma (F(X_1) S[N][a] + C(u, N) + G(u) S[0][a]) - c_var a
+            const double msel = on2 ? 1.0 : 0.0;
             double best = -DBL_MAX, second = -DBL_MAX;
             int arg = 0;
-            if constexpr (EXTRACT) {
+            double bq[4] = {-DBL_MAX, -DBL_MAX, -DBL_MAX, -DBL_MAX};
 #pragma unroll
-                for (int q = 0; q < RMAX / W; ++q) {
+            for (int q = 0; q < RMAX / W; ++q) {
+                const VV sq = rN[q];
 #pragma unroll
-                    for (int e = 0; e < W; ++e) {
-                        const int a = q * W + e;
-                        const double sv = (double)lane_of<VT, W>(sn[q], e);
-                        take(fma(fwr, sv, acc[a].value()), a, best, second, arg);
-                    }
-                }
-            } else {
-                // four independent max chains, merged at the end
-                double bq[4] = {-DBL_MAX, -DBL_MAX, -DBL_MAX, -DBL_MAX};
-#pragma unroll
-                for (int q = 0; q < RMAX / W; ++q) {
-#pragma unroll
-                    for (int e = 0; e < W; ++e) {
-                        const int a = q * W + e;
-                        const double sv = (double)lane_of<VT, W>(sn[q], e);
-                        const double qv = KAHAN ? fma(fwr, sv, acc[a].value()) - p.cvar * a
-                                                : fma(fwr, sv, acc[a].value());
+                for (int e = 0; e < W; ++e) {
+                    const int a = q * W + e;
+                    const VT svt = lane_of<VT, W>(sq, e);
+                    const double sv = (double)svt;
+                    const double run = fma(msel, D[a].value(), A1[a].value());
+                    if constexpr (EXTRACT) {
+                        take(fma(fwr, sv, run), a, best, second, arg);
+                    } else {
+                        const double qv = KAHAN ? fma(fwr, sv, run) - cv * a : fma(fwr, sv, run);
                         bq[a & 3] = fmax(bq[a & 3], qv);
                     }
+                    if (!last) {
+                        A1[a].add(w1, svt);
+                        D[a].add(wd, svt);
+                    }
                 }
-                best = fmax(fmax(bq[0], bq[1]), fmax(bq[2], bq[3]));
             }
-            finish(N - b, di, best, second, arg, r0c, voldc);
-        }
-        if (N == nmax) break;
-        // add path point j = N with weight P(u - N) (zero below 1; the table is
-        // zero past d_max); lanes past the last diagonal add nothing
-        const AW w = (AW)(live && di >= 1 ? pwr : 0.0);
+            if (!EXTRACT) best = fmax(fmax(bq[0], bq[1]), fmax(bq[2], bq[3]));
+            if (valid) finish(N - b, X1, best, second, arg, r0c, voldc);
+        } else {
 #pragma unroll
-        for (int q = 0; q < RMAX / W; ++q) {
+            for (int q = 0; q < RMAX / W; ++q) {
+                const VV sq = rN[q];
 #pragma unroll
-            for (int e = 0; e < W; ++e) acc[q * W + e].add(w, lane_of<VT, W>(sn[q], e));
+                for (int e = 0; e < W; ++e) {
+                    const VT svt = lane_of<VT, W>(sq, e);
+                    A1[q * W + e].add(w1, svt);
+                    D[q * W + e].add(wd, svt);
+                }
+            }
         }
     }
     if (EXTRACT) return;
@@ -340,12 +396,28 @@ __global__ __launch_bounds__(64) void backup_a_kernel(ADev p) {
     vmx = wave_max(vmx);
     vmn = wave_min(vmn);
     if (lane == 0) {
-        double* pp = p.partials + 4 * (size_t)tile;
+        double* pp = p.partials + 4 * (size_t)grp;
         pp[0] = dmx;
         pp[1] = dmn;
         pp[2] = vmx;
         pp[3] = vmn;
     }
+}
+
+// Two entry points of one body: the first asks for two wavefronts per SIMD (its
+// registers fit in 256), the second has the whole register file for the variants
+// that would spill at that budget (FP32 compensated sums at RMAX >= 24, RMAX = 32).
+template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void
+backup_a_kernel(ADev p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    backup_a_body<VT, KAHAN, RMAX, EXTRACT>(p, smem);
+}
+
+template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
+__global__ __launch_bounds__(64) void backup_a_wide_kernel(ADev p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    backup_a_body<VT, KAHAN, RMAX, EXTRACT>(p, smem);
 }
 
 // Single-workgroup reduction of the per-tile partials and the stopping rule.
@@ -390,14 +462,22 @@ __global__ void to_f32_kernel(const double* v64, float* v32, double c, int64_t n
 template <typename VT, bool KAHAN, bool EXTRACT, int RMAX>
 static hipError_t launch_a_r(const ADev& p, hipStream_t s) {
     const int lp_max = (p.m >= 2 ? (p.m - 2) * (p.R - 1) : 0) + p.r2;
-    size_t bytes = sizeof(VT) * (size_t)lp_max * RMAX;
+    // lanes: G tiles of R lanes; staging: RMAX / 8 action slices of G x CH points
+    if (p.G < 1 || p.G * p.R > 64 || p.CH < 1 || (RMAX / 8) * p.G * p.CH > 64 ||
+        p.ngroups < 1)
+        return hipErrorInvalidConfiguration;
+    size_t bytes = sizeof(VT) * (size_t)2 * p.G * p.CH * RMAX;
     bytes += sizeof(double) * 3 * (size_t)p.tab;
-    if (bytes > 65536) return hipErrorInvalidConfiguration;  // beyond the default LDS limit
-    // lanes cover u = N + X_1 for every emitted state: at most 2R - 1 diagonals
-    if (p.r2 + p.R - 1 > 64) return hipErrorInvalidConfiguration;
-    if (p.tab < p.R + lp_max + 1 || p.tab < p.dmax + 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT>), dim3(p.tiles), dim3(64),
-                       bytes, s, p);
+    if (bytes > 65536) return hipErrorInvalidConfiguration;
+    // G is read at u2 <= b + 2R and P, F at clamped indices
+    if (p.tab < 2 * p.R + lp_max + 1 || p.tab < p.dmax + 2) return hipErrorInvalidValue;
+    constexpr bool wide = RMAX == 32 || (KAHAN && RMAX >= 24);
+    if constexpr (wide)
+        hipLaunchKernelGGL((backup_a_wide_kernel<VT, KAHAN, RMAX, EXTRACT>), dim3(p.ngroups),
+                           dim3(64), bytes, s, p);
+    else
+        hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT>), dim3(p.ngroups),
+                           dim3(64), bytes, s, p);
     return hipGetLastError();
 }
 

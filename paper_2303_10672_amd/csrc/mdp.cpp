@@ -21,16 +21,22 @@ pvi_status fail(pvi_status st, const std::string& msg) {
 
 static bool is_finite(double x) { return std::isfinite(x); }
 
+static int64_t ipow_i(int64_t b, int e) {
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
 // Scenario A expected one-day reward without the order cost, as a table over
 // (X_1, total stock): sum_d P(d) (-C_h [X - d - W]^+ - C_s [d - X]^+ - C_w W),
 // W = [X_1 - d]^+ (Appendix A, reward equation).
 static void build_a_tables(pvi_mdp* p) {
     const int R = p->rad[0], dm = p->dmax[0];
     const auto& P = p->pmf[0];
-    // the kernel reads P, F and G at up to X_1 + (path length) + (states per lane):
+    // the kernel reads P, F and G at up to 2R + (path length):
     // pad with P = 0, F = 1, G = 0 beyond d_max
     const int lp_max = (p->m >= 2 ? (p->m - 2) * (R - 1) : 0) + (p->m >= 2 ? R : 1);
-    p->tab = std::max(dm + 10, R + 8 + lp_max);
+    p->tab = std::max(dm + 10, 2 * R + 8 + lp_max);
     p->a_pmf.assign(p->tab, 0.0);
     p->a_cdf.assign(p->tab, 1.0);
     p->a_tail.assign(p->tab, 0.0);
@@ -83,6 +89,43 @@ static void build_a_tables(pvi_mdp* p) {
         ex += cnt[b] * per;
     }
     p->executed_per_sweep = nh * ex * R;
+
+    // Work list of the backup kernel.  One wavefront takes G = floor(64 / R) tiles
+    // of equal digit sum b (so their loops run in lockstep), R lanes each.  Tiles are
+    // listed per block of G in-transit vectors, digit sums in descending order (the
+    // longest tiles start first), and inside one digit sum by (X_m..X_3) then
+    // in-transit vector, so a full group is one (X_m..X_3) over G in-transit vectors.
+    p->a_G = std::min(16, std::max(1, 64 / R));
+    // the kernel pads the actions to RMAX = 8, 16, 24 or 32 and stages each path
+    // point with RMAX / 8 lanes of 8 actions: CH points per chunk fill <= 64 lanes
+    const int rmax = R <= 8 ? 8 : R <= 16 ? 16 : R <= 24 ? 24 : 32;
+    p->a_CH = std::max(1, 64 / ((rmax / 8) * p->a_G));
+    const int G = p->a_G;
+    const int64_t nzt = p->m >= 2 ? (int64_t)ipow_i(R, p->m - 2) : 1;
+    std::vector<int> zsum(nzt, 0);
+    for (int64_t z = 0; z < nzt; ++z) {
+        int64_t t = z;
+        for (int i = 2; i <= p->m - 1; ++i) {
+            zsum[z] += (int)(t % R);
+            t /= R;
+        }
+    }
+    const int bmax = std::max(0, p->m - 2) * (R - 1);
+    p->a_groups.clear();
+    for (int64_t hb = 0; hb < nh; hb += G) {
+        const int64_t he = std::min<int64_t>(hb + G, nh);
+        for (int b = bmax; b >= 0; --b) {
+            int fill = 0;
+            for (int64_t z = 0; z < nzt; ++z) {
+                if (zsum[z] != b) continue;
+                for (int64_t h = hb; h < he; ++h) {
+                    p->a_groups.push_back((int32_t)(h * nzt + z));
+                    if (++fill == G) fill = 0;
+                }
+            }
+            for (; fill != 0 && fill < G; ++fill) p->a_groups.push_back(-1);
+        }
+    }
     p->logical_per_sweep = p->ns * p->na * (int64_t)(dm + 1);
 }
 

@@ -25,6 +25,10 @@ struct pvi_mdp {
     // Scenario A kernel tables
     int tab = 0, xt = 0;
     std::vector<double> a_pmf, a_cdf, a_tail, a_r0;
+    // scenario-A kernel work list: groups of a_G tiles with one digit sum each
+    // (-1 pads a short group), a_CH path points staged per chunk
+    std::vector<int32_t> a_groups;
+    int a_G = 0, a_CH = 0;
 
     // Scenario B kernel tables
     int b_rows = 0, b_emax = 0, b_ew = 0, b_sw = 0;
@@ -52,6 +56,7 @@ struct pvi_mdp {
         pvi::Ctl* ctl = nullptr;
         pvi::Ctl* h_ctl = nullptr;  // pinned host mirror
         double *pmf = nullptr, *cdf = nullptr, *tail = nullptr, *r0 = nullptr;
+        int32_t* agroups = nullptr;
         double *z = nullptr, *rexp0 = nullptr, *epmf = nullptr, *ecdf = nullptr,
                *etail = nullptr, *rexp1 = nullptr;
         void *cu = nullptr, *ct0 = nullptr, *ct1 = nullptr;

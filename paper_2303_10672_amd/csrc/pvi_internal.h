@@ -50,7 +50,7 @@ struct ADev {
     void* v_out;
     int32_t* pi;        // extraction only
     double* gap;        // extraction only
-    double* partials;   // [tiles][4]: max dv, min dv, max v_out, min v_out
+    double* partials;   // [ngroups][4]: max dv, min dv, max v_out, min v_out
     const double* r0;   // [R][xt]: expected one-day reward without the order cost
     const double* pmf;  // [tab]: P(d), zero beyond d_max
     const double* cdf;  // [tab]: P(D <= d), one beyond d_max
@@ -62,6 +62,8 @@ struct ADev {
     int32_t nz;         // R^(m-2) tiles per in-transit vector (1 if m <= 2)
     int32_t r2;         // R if m >= 2 else 1
     int32_t tiles;      // nh * nz
+    const int32_t* groups;  // [ngroups][G] tile ids, equal digit sum per group, -1 = none
+    int32_t G, CH, ngroups; // tiles per wavefront, path points per staged chunk
     int32_t pow_y[8];   // R^(i-1), weight of next-state digit i inside a block
     int32_t fixed;      // 1: fixed number of sweeps, the stopping rule is not applied
     double gamma, cvar;
