@@ -103,6 +103,14 @@ struct Acc<float, true> {
     __device__ __forceinline__ double value() const { return (double)s - (double)c; }
 };
 
+// Orders a wavefront's LDS stores before its later LDS reads of other lanes' data
+// (no instruction: LDS requests of one wavefront are served in issue order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Value staged for the padding actions R <= a < RMAX: so negative that their Q
 // never wins the max, small enough that weighted sums of it (total weight <= 1)
 // stay finite.  With it the action loops need no bound check.
@@ -133,7 +141,7 @@ __device__ constexpr double kPadValue<double> = -1e300;
 // takes S[0] for every demand.  All actions of a state live in one lane, so the max
 // needs no exchange.  Weights are staged premultiplied by gamma.
 template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
-__device__ __forceinline__ void backup_a_body(const ADev& p, unsigned char* smem) {
+__device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
     Ctl* ctl = p.ctl;
     if (!EXTRACT && ctl->stop) return;
     constexpr int W = VecLoad<VT>::W;
@@ -147,44 +155,40 @@ __device__ __forceinline__ void backup_a_body(const ADev& p, unsigned char* smem
     const int32_t* gt = p.groups + (size_t)grp * G;
     const int first = gt[0];  // a group's first slot always holds a tile
 
-    // compute role: tile slot g, position l; lanes past G * R and the slots of a
-    // short group repeat tile `first` without writing anything
+    // compute role: tile slot g, position l.  Lanes past G * R and the slots of a
+    // short group repeat a lane of tile `first`: they compute and store exactly that
+    // lane's values, so every lane loads and stores unconditionally (which also
+    // lets the compiler count outstanding memory operations exactly).
     int g = lane / R;
     const int l = lane - g * R;
-    bool valid = g < G;
-    if (!valid) g = 0;
+    if (g >= G) g = 0;
     int tile = gt[g];
-    if (tile < 0) {
-        valid = false;
-        tile = first;
-    }
+    if (tile < 0) tile = first;
+    // digit sum of the group's tiles (equal for all of them), taken from the first
+    // so that it and the loop bounds are wavefront-uniform
     int b = 0;
     {
-        int t = tile % p.nz;
+        int t = first % p.nz;
         for (int i = 2; i <= m - 1; ++i) {
             b += t % R;
             t /= R;
         }
     }
-    const int lp = b + p.r2;  // path points 0 .. lp - 1, the same for the whole group
+    const int lp = b + p.r2;  // path points 0 .. lp - 1
+    const int lpm = (m >= 2 ? (m - 2) * (R - 1) : 0) + p.r2;  // longest path list
 
-    // staging role: action slice sh, tile slot sg, point sj of every chunk
+    // staging role: action slice sh, tile slot sg, point sj of every chunk; lanes
+    // past the stagers repeat the first stager's loads and store nothing
     const int npair = G * CH;
     const bool stager = lane < NSPLIT * npair;
-    const int sh = lane / npair, spair = lane - sh * npair;
+    const int sl = stager ? lane : 0;
+    const int sh = sl / npair, spair = sl - sh * npair;
     const int sg = spair / CH, sj = spair - sg * CH;
     int64_t s_base = 0;
-    int sY[9];
     {
-        int st = stager ? gt[sg] : first;
+        int st = gt[sg];
         if (st < 0) st = first;
-        const int sht = st / p.nz;
-        int t = st - sht * p.nz;
-        for (int i = 2; i <= m - 1; ++i) {
-            sY[i] = t % R;
-            t /= R;
-        }
-        s_base = (int64_t)sht * p.stride_h;
+        s_base = (int64_t)(st / p.nz) * p.stride_h;
     }
 
     VT* buf = reinterpret_cast<VT*>(smem);  // [2][G][CH][RMAX]
@@ -192,38 +196,52 @@ __device__ __forceinline__ void backup_a_body(const ADev& p, unsigned char* smem
     double* sP = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)2 * npair * RMAX);
     double* sF = sP + p.tab;
     double* sG = sF + p.tab;
+    int* soff = reinterpret_cast<int*>(sG + p.tab);  // [G][lpm] block offset of each point
     const VT* vin = reinterpret_cast<const VT*>(p.v_in);
 
-    VT pre[SPL];
-    auto load_chunk = [&](int c) {
-        const int j = c * CH + sj;
-        if (stager && j < lp) {
-            const VT* src = vin + s_base + path_offset(j, sY, m, p.pow_y);
-#pragma unroll
-            for (int e = 0; e < SPL; ++e) {
-                const int a = sh * SPL + e;
-                pre[e] = a < R ? src[(int64_t)a * p.stride_a] : kPadValue<VT>;
-            }
-        }
-    };
-    auto store_chunk = [&](int c) {
-        if (stager && c * CH + sj < lp) {
-            VV* dst = reinterpret_cast<VV*>(buf + ((size_t)((c & 1) * G + sg) * CH + sj) * RMAX +
-                                            sh * SPL);
-#pragma unroll
-            for (int q = 0; q < SPL / W; ++q) dst[q] = make_vec<VT>(&pre[q * W]);
-        }
-    };
-
-    load_chunk(0);
     const double gm = p.gamma;
     for (int i = lane; i < p.tab; i += 64) {
         sP[i] = gm * p.pmf[i];
         sF[i] = gm * p.cdf[i];
         sG[i] = gm * p.tail[i];
     }
+    for (int i = lane; i < G * lp; i += 64) {
+        const int gg = i / lp, j = i - gg * lp;
+        int st = gt[gg];
+        if (st < 0) st = first;
+        int t = st % p.nz, Y[9];
+        for (int k = 2; k <= m - 1; ++k) {
+            Y[k] = t % R;
+            t /= R;
+        }
+        soff[gg * lpm + j] = path_offset(j, Y, m, p.pow_y);
+    }
+    wave_sync();
+
+    VT pre[SPL];
+    auto load_chunk = [&](int c) {
+        const int j = min(c * CH + sj, lp - 1);
+        const VT* src = vin + s_base + soff[sg * lpm + j];
+        // raw loads only: the padding is applied when the chunk is stored, so the
+        // loads stay in flight until then
+#pragma unroll
+        for (int e = 0; e < SPL; ++e) pre[e] = src[(int64_t)min(sh * SPL + e, R - 1) * p.stride_a];
+    };
+    auto store_chunk = [&](int c) {
+        if (stager && c * CH + sj < lp) {
+            VV* dst = reinterpret_cast<VV*>(buf + ((size_t)((c & 1) * G + sg) * CH + sj) * RMAX +
+                                            sh * SPL);
+            VT v[SPL];
+#pragma unroll
+            for (int e = 0; e < SPL; ++e) v[e] = sh * SPL + e < R ? pre[e] : kPadValue<VT>;
+#pragma unroll
+            for (int q = 0; q < SPL / W; ++q) dst[q] = make_vec<VT>(&v[q * W]);
+        }
+    };
+
+    load_chunk(0);
     store_chunk(0);
-    __syncthreads();
+    wave_sync();
     const int nchunks = (lp + CH - 1) / CH;
     if (nchunks > 1) load_chunk(1);
 
@@ -263,7 +281,7 @@ __device__ __forceinline__ void backup_a_body(const ADev& p, unsigned char* smem
 
     const VV* row0 = reinterpret_cast<const VV*>(buf + (size_t)g * CH * RMAX);
     // N = 0 (only when b = 0): nothing left to deplete, every demand lands on S[0]
-    if (b == 0 && valid) {
+    if (b == 0) {
         double r0n = 0.0, vold = 0.0;
         if (!EXTRACT) {
             r0n = p.r0[l * p.xt + l];
@@ -311,84 +329,117 @@ __device__ __forceinline__ void backup_a_body(const ADev& p, unsigned char* smem
         }
     }
 
-    // the state emitted at step N: X_1 = u1 - N while u1 >= N, else u2 - N; its
-    // reward-table entry and old value are fetched one step ahead
-    double r0n = 0.0, vold = 0.0;
-    auto prefetch = [&](int N) {
-        if (!EXTRACT && valid && N >= n0 && N <= nmax) {
-            const int X1 = (u1 >= N ? u1 : u2) - N, X2 = N - b;
-            r0n = p.r0[X1 * p.xt + X1 + X2 + b];
-            vold = (double)vin[tbase + X2 * R + X1];
+    // the state emitted at step N: X_1 = u1 - N while u1 >= N, else u2 - N.  Its
+    // reward-table entry and old value (a read of V that may go to HBM) are fetched
+    // three steps ahead into one of three register slots; the loop is unrolled by
+    // three so each slot is used and then refilled in place, without register moves
+    // that would force the loads to complete early.
+    constexpr int PD = 3;
+    auto prefetch = [&](int N, double& r0s, double& vs) {
+        if constexpr (!EXTRACT) {
+            // steps outside [n0, nmax] emit nothing: clamp to an in-range state
+            const int X1 = min(max((u1 >= N ? u1 : u2) - N, 0), R - 1);
+            const int X2 = min(max(N - b, 0), p.r2 - 1);
+            r0s = p.r0[X1 * p.xt + X1 + X2 + b];
+            vs = (double)vin[tbase + X2 * R + X1];
         }
     };
-    prefetch(1);
     int c = 0, cj = 0;  // chunk of the current point and position inside it
-    for (int N = 1; N <= nmax; ++N) {
-        if (++cj == CH) {  // entering chunk c + 1: publish it, start loading the next
+    // moves to the next point; on entering chunk c + 1 publishes it and starts
+    // loading chunk c + 2
+    auto advance = [&]() {
+        if (++cj == CH) {
             cj = 0;
             ++c;
             store_chunk(c);
-            __syncthreads();
+            // the workgroup is this one wavefront, whose LDS operations run in
+            // issue order: only the compiler has to keep the stores before the reads
+            wave_sync();
             if (c + 1 < nchunks) load_chunk(c + 1);
         }
-        // point N serves the emitted state and both running sums; each pair (or
-        // quad) of actions is read, used and dropped, so the row is never held whole
-        const VV* rN = reinterpret_cast<const VV*>(buf + ((size_t)((c & 1) * G + g) * CH + cj) * RMAX);
+    };
+    auto point = [&]() {
+        return reinterpret_cast<const VV*>(buf + ((size_t)((c & 1) * G + g) * CH + cj) * RMAX);
+    };
+    // weights of point N for the two running sums: P(u - N) for u - N >= 1 (the
+    // table is zero past d_max); a finished diagonal (u - N <= 0) adds nothing
+    auto weights = [&](int N, AW& w1, AW& wd) {
         const int d1 = u1 - N, d2 = u2 - N;
-        const bool on2 = d1 < 0;
-        const int X1 = on2 ? d2 : d1;
-        const double fwr = sF[min(max(X1, 0), p.dmax)];
         const double pw1 = sP[min(max(d1, 0), p.tab - 1)];
         const double pw2 = sP[min(max(d2, 0), p.tab - 1)];
-        // weight P(u - N) for u - N >= 1 (the table is zero past d_max); a finished
-        // diagonal (u - N <= 0) adds nothing
         const double w1d = d1 >= 1 ? pw1 : 0.0;
-        const AW w1 = (AW)w1d;
-        const AW wd = (AW)((d2 >= 1 ? pw2 : 0.0) - w1d);
-        const bool last = N == nmax;  // the sums are not needed after the last point
-        const double r0c = r0n, voldc = vold;
-        prefetch(N + 1);
-        if (N >= n0) {  // uniform: every lane of the group emits from here on
-            // Q_a = gamma (F(X_1) S[N][a] + C(u, N) + G(u) S[0][a]) - c_var a
-            const double msel = on2 ? 1.0 : 0.0;
-            double best = -DBL_MAX, second = -DBL_MAX;
-            int arg = 0;
-            double bq[4] = {-DBL_MAX, -DBL_MAX, -DBL_MAX, -DBL_MAX};
+        w1 = (AW)w1d;
+        wd = (AW)((d2 >= 1 ? pw2 : 0.0) - w1d);
+    };
+
+    // points 1 .. n0 - 1 precede every state of the group: running sums only
+    for (int N = 1; N < n0; ++N) {
+        advance();
+        const VV* rN = point();
+        AW w1, wd;
+        weights(N, w1, wd);
 #pragma unroll
-            for (int q = 0; q < RMAX / W; ++q) {
-                const VV sq = rN[q];
+        for (int q = 0; q < RMAX / W; ++q) {
+            const VV sq = rN[q];
 #pragma unroll
-                for (int e = 0; e < W; ++e) {
-                    const int a = q * W + e;
-                    const VT svt = lane_of<VT, W>(sq, e);
-                    const double sv = (double)svt;
-                    const double run = fma(msel, D[a].value(), A1[a].value());
-                    if constexpr (EXTRACT) {
-                        take(fma(fwr, sv, run), a, best, second, arg);
-                    } else {
-                        const double qv = KAHAN ? fma(fwr, sv, run) - cv * a : fma(fwr, sv, run);
-                        bq[a & 3] = fmax(bq[a & 3], qv);
-                    }
-                    if (!last) {
-                        A1[a].add(w1, svt);
-                        D[a].add(wd, svt);
-                    }
-                }
-            }
-            if (!EXTRACT) best = fmax(fmax(bq[0], bq[1]), fmax(bq[2], bq[3]));
-            if (valid) finish(N - b, X1, best, second, arg, r0c, voldc);
-        } else {
-#pragma unroll
-            for (int q = 0; q < RMAX / W; ++q) {
-                const VV sq = rN[q];
-#pragma unroll
-                for (int e = 0; e < W; ++e) {
-                    const VT svt = lane_of<VT, W>(sq, e);
-                    A1[q * W + e].add(w1, svt);
-                    D[q * W + e].add(wd, svt);
-                }
+            for (int e = 0; e < W; ++e) {
+                const VT svt = lane_of<VT, W>(sq, e);
+                A1[q * W + e].add(w1, svt);
+                D[q * W + e].add(wd, svt);
             }
         }
+    }
+
+    // points n0 .. nmax: every lane emits one state per point.  Each pair (or
+    // quad) of actions of the point is read, used for the state and both sums,
+    // and dropped, so the row is never held whole.  The sums are also advanced
+    // after the last point (unused), which keeps the body free of branches.
+    auto step = [&](int N, double& r0s, double& vs) {
+        advance();
+        const VV* rN = point();
+        AW w1, wd;
+        weights(N, w1, wd);
+        const bool on2 = u1 < N;
+        const int X1 = (on2 ? u2 : u1) - N;
+        const double fwr = sF[min(max(X1, 0), p.dmax)];
+        // Q_a = gamma (F(X_1) S[N][a] + C(u, N) + G(u) S[0][a]) - c_var a
+        const double msel = on2 ? 1.0 : 0.0;
+        double best = -DBL_MAX, second = -DBL_MAX;
+        int arg = 0;
+        double bq[4] = {-DBL_MAX, -DBL_MAX, -DBL_MAX, -DBL_MAX};
+#pragma unroll
+        for (int q = 0; q < RMAX / W; ++q) {
+            const VV sq = rN[q];
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                const int a = q * W + e;
+                const VT svt = lane_of<VT, W>(sq, e);
+                const double sv = (double)svt;
+                const double run = fma(msel, D[a].value(), A1[a].value());
+                if constexpr (EXTRACT) {
+                    take(fma(fwr, sv, run), a, best, second, arg);
+                } else {
+                    const double qv = KAHAN ? fma(fwr, sv, run) - cv * a : fma(fwr, sv, run);
+                    bq[a & 3] = fmax(bq[a & 3], qv);
+                }
+                A1[a].add(w1, svt);
+                D[a].add(wd, svt);
+            }
+        }
+        if (!EXTRACT) best = fmax(fmax(bq[0], bq[1]), fmax(bq[2], bq[3]));
+        finish(N - b, X1, best, second, arg, r0s, vs);
+        prefetch(N + PD, r0s, vs);  // the slot is consumed: refill it for step N + PD
+    };
+    double ra = 0.0, va = 0.0, rb = 0.0, vb = 0.0, rc = 0.0, vc = 0.0;
+    prefetch(n0, ra, va);
+    prefetch(n0 + 1, rb, vb);
+    prefetch(n0 + 2, rc, vc);
+    for (int N = n0; N <= nmax; N += PD) {
+        step(N, ra, va);
+        if (N + 1 > nmax) break;
+        step(N + 1, rb, vb);
+        if (N + 2 > nmax) break;
+        step(N + 2, rc, vc);
     }
     if (EXTRACT) return;
     dmx = wave_max(dmx);
@@ -406,7 +457,7 @@ __device__ __forceinline__ void backup_a_body(const ADev& p, unsigned char* smem
 
 // Two entry points of one body: the first asks for two wavefronts per SIMD (its
 // registers fit in 256), the second has the whole register file for the variants
-// that would spill at that budget (FP32 compensated sums at RMAX >= 24, RMAX = 32).
+// that would spill at that budget (RMAX = 32, FP32 compensated sums at RMAX >= 16).
 template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void
 backup_a_kernel(ADev p) {
@@ -467,11 +518,11 @@ static hipError_t launch_a_r(const ADev& p, hipStream_t s) {
         p.ngroups < 1)
         return hipErrorInvalidConfiguration;
     size_t bytes = sizeof(VT) * (size_t)2 * p.G * p.CH * RMAX;
-    bytes += sizeof(double) * 3 * (size_t)p.tab;
+    bytes += sizeof(double) * 3 * (size_t)p.tab + sizeof(int) * (size_t)p.G * lp_max;
     if (bytes > 65536) return hipErrorInvalidConfiguration;
     // G is read at u2 <= b + 2R and P, F at clamped indices
     if (p.tab < 2 * p.R + lp_max + 1 || p.tab < p.dmax + 2) return hipErrorInvalidValue;
-    constexpr bool wide = RMAX == 32 || (KAHAN && RMAX >= 24);
+    constexpr bool wide = RMAX == 32 || (KAHAN && RMAX >= 16);
     if constexpr (wide)
         hipLaunchKernelGGL((backup_a_wide_kernel<VT, KAHAN, RMAX, EXTRACT>), dim3(p.ngroups),
                            dim3(64), bytes, s, p);
