@@ -92,9 +92,9 @@ static void build_a_tables(pvi_mdp* p) {
 
     // Work list of the backup kernel.  One wavefront takes G = floor(64 / R) tiles
     // of equal digit sum b (so their loops run in lockstep), R lanes each.  Tiles are
-    // listed per block of G in-transit vectors, digit sums in descending order (the
-    // longest tiles start first), and inside one digit sum by (X_m..X_3) then
-    // in-transit vector, so a full group is one (X_m..X_3) over G in-transit vectors.
+    // grouped per block of G in-transit vectors and, inside one digit sum, by
+    // (X_m..X_3) then in-transit vector, so a full group is one (X_m..X_3) over G
+    // in-transit vectors.
     p->a_G = std::min(16, std::max(1, 64 / R));
     // the kernel pads the actions to RMAX = 8, 16, 24 or 32 and stages each path
     // point with RMAX / 8 lanes of 8 actions: CH points per chunk fill <= 64 lanes
@@ -125,6 +125,29 @@ static void build_a_tables(pvi_mdp* p) {
             }
             for (; fill != 0 && fill < G; ++fill) p->a_groups.push_back(-1);
         }
+    }
+    // Workgroups are dispatched round-robin over the 8 XCDs and the kernel gives
+    // XCD x a contiguous range of groups (its L2 then holds the V blocks of those
+    // in-transit vectors).  Sorting each range by digit sum, longest path first,
+    // makes the in-order dispatch onto freed slots a longest-first list schedule,
+    // which shortens the tail of the launch.
+    {
+        const int ng = (int)(p->a_groups.size() / G), q = ng >> 3, r = ng & 7;
+        std::vector<int32_t> sorted;
+        sorted.reserve(p->a_groups.size());
+        for (int x = 0; x < 8; ++x) {
+            const int lo = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+            const int cnt = q + (x < r ? 1 : 0);
+            std::vector<int> idx(cnt);
+            for (int k = 0; k < cnt; ++k) idx[k] = lo + k;
+            auto bsum = [&](int grp) { return zsum[p->a_groups[(size_t)grp * G] % nzt]; };
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int a, int b) { return bsum(a) > bsum(b); });
+            for (int k : idx)
+                sorted.insert(sorted.end(), p->a_groups.begin() + (size_t)k * G,
+                              p->a_groups.begin() + (size_t)(k + 1) * G);
+        }
+        p->a_groups.swap(sorted);
     }
     p->logical_per_sweep = p->ns * p->na * (int64_t)(dm + 1);
 }
