@@ -241,6 +241,31 @@ def bench_single(args, pvi, W, cfg):
     print(json.dumps(line), flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "backup_a_kernel_m4L2_hbm_traffic.md")
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2303_10672_amd",
+                             "csrc", "kernels_a.hip")
+
+
+def measured_traffic():
+    """HBM bytes per full FP64 sweep of the scenario-A backup, from the committed
+    counter summary, or None when the kernel source has changed since it was taken
+    (the summary records the source's SHA-256)."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    fetch = re.search(r"hbm_fetch_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    write = re.search(r"hbm_write_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (sha and fetch and write) or sha.group(1) != src:
+        return None
+    return float(fetch.group(1)), float(write.group(1))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -291,6 +316,15 @@ def main():
     executed_per_launch = main_run["executed"] / (args.steps * sweeps)
     fma_tflops = 2.0 * executed_per_launch / avg_kernel_s / 1e12
 
+    # counters were taken on the FP64 kernel: only that kernel's line carries them
+    meas = measured_traffic() if dom == 0 else None
+    traffic = (meas[0] + meas[1]) if meas else None
+    traffic_detail = None
+    if meas:
+        traffic_detail = {"unit": "bytes per launch", "fetch": meas[0], "write": meas[1],
+                          "source": os.path.relpath(TRAFFIC_PROFILE,
+                                                    os.path.dirname(os.path.abspath(__file__))),
+                          "compulsory": 16.0 * m.n_states}
     out = {
         "metric": METRIC,
         "value": value,
@@ -339,7 +373,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_detail": traffic_detail,
             "kernel": "backup_a_kernel<" + ("double" if dom == 0 else "float") + ">",
             "launches_timed": launches,
             "avg_kernel_ms": avg_kernel_s * 1e3,
