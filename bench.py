@@ -45,6 +45,8 @@ def parse():
                          "batched FP32 kernel vs one FP64 solve per call), serving (the "
                          "request mix through the server), config2/config3 (one solve)")
     ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--prerun", type=int, default=200,
+                    help="requests in the closed-loop pre-run that sets the saturated rate")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving arrival rate per second (0: 0.7 x closed-loop rate)")
     ap.add_argument("--batch", type=int, default=256)
@@ -166,11 +168,14 @@ def bench_serving(args, pvi, W):
     gaps = np.diff([0.0] + [t for t, _ in mix])          # unit-rate inter-arrival times
     # closed-loop pre-run on a prefix gives the saturated rate
     srv = pvi.Server(small_batch=args.batch)
-    pre = scs[:min(200, len(scs))]
+    pre = scs[:min(args.prerun, len(scs))]
     t0 = time.perf_counter()
     ts = [srv.submit([pvi.mdp_create(sc)], precision="fp32")[0] for sc in pre]
-    for t in ts:
+    for i, t in enumerate(ts):
         srv.wait(t)
+        if (i + 1) % 10 == 0 or i + 1 == len(ts):
+            print(f"closed-loop pre-run: {i + 1}/{len(ts)} requests done", file=sys.stderr,
+                  flush=True)
     sat = len(pre) / (time.perf_counter() - t0)
     srv.close()
     rate = args.rate if args.rate > 0 else 0.7 * sat
@@ -187,11 +192,17 @@ def bench_serving(args, pvi, W):
             if d > 0:
                 time.sleep(d)
             tickets[i] = srv.submit([m], precision="fp32")[0]
+            if (i + 1) % 20 == 0:
+                print(f"submitted: {i + 1}/{len(mdps)} requests", file=sys.stderr, flush=True)
 
     th = threading.Thread(target=submitter)
     th.start()
     th.join()
-    status = [srv.wait(t) for t in tickets]
+    status = []
+    for i, t in enumerate(tickets):
+        status.append(srv.wait(t))
+        if (i + 1) % 10 == 0 or i + 1 == len(tickets):
+            print(f"served: {i + 1}/{len(tickets)} requests done", file=sys.stderr, flush=True)
     wall = time.perf_counter() - start
     st = srv.stats()
     srv.close()
