@@ -47,7 +47,7 @@ class _OrMdp(ctypes.Structure):
         ("pmf1", ctypes.POINTER(ctypes.c_double)), ("rul_p", ctypes.POINTER(ctypes.c_double)),
         ("rho", ctypes.c_double), ("c_var", ctypes.c_double * 2), ("c_fixed", ctypes.c_double),
         ("c_hold", ctypes.c_double), ("c_short", ctypes.c_double), ("c_waste", ctypes.c_double),
-        ("c_rev", ctypes.c_double * 2), ("gamma", ctypes.c_double),
+        ("c_rev", ctypes.c_double * 2), ("gamma", ctypes.c_double), ("issuing", ctypes.c_int32),
     ]
 
 
@@ -73,8 +73,8 @@ def _load():
         lib.or_sweep.argtypes = [P(_OrMdp), P(ctypes.c_double), P(ctypes.c_double),
                                  P(ctypes.c_int32), P(ctypes.c_double)]
         lib.or_solve.argtypes = [P(_OrMdp), ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
-                                 P(ctypes.c_double), P(ctypes.c_int32), P(ctypes.c_double),
-                                 P(ctypes.c_double)]
+                                 ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int32),
+                                 P(ctypes.c_double), P(ctypes.c_double)]
         lib.or_transition.argtypes = [P(_OrMdp), ctypes.c_int64, ctypes.c_int32,
                                       P(ctypes.c_int32), P(ctypes.c_int64), P(ctypes.c_double)]
         lib.or_arrival_prob.restype = ctypes.c_double
@@ -173,6 +173,7 @@ class Oracle:
         self.s.c_short, self.s.c_waste = c["short"], c["waste"]
         self.s.c_rev[0], self.s.c_rev[1] = c["rev"]
         self.s.gamma = sc["gamma"]
+        self.s.issuing = {"fifo": 0, "lifo": 1}[sc.get("issuing", "fifo")]
         self.ref = ctypes.byref(self.s)
         self.n_states = int(self.lib.or_num_states(self.ref))
         self.n_actions = int(self.lib.or_num_actions(self.ref))
@@ -221,14 +222,19 @@ class Oracle:
         self.lib.or_sweep(self.ref, _dp(V), _dp(Vn), _ip(pi), _dp(gap))
         return Vn, pi, gap
 
-    def solve(self, thr=None, max_sweeps=100000, fixed_sweeps=0, v0=None):
-        """Value iteration.  Returns dict(V, pi, gap, sweeps, span, dmax, dmin, converged)."""
+    def solve(self, thr=None, max_sweeps=100000, fixed_sweeps=0, v0=None, stop_rule="span"):
+        """Value iteration.  Returns dict(V, pi, gap, sweeps, span, dmax, dmin, converged).
+
+        stop_rule "span": max(V'-V) - min(V'-V) < thr (Appendix B); "supnorm":
+        max |V' - V| < thr (Appendix A).
+        """
         thr = self.threshold if thr is None else float(thr)
         V = np.zeros(self.n_states) if v0 is None else np.array(v0, dtype=np.float64)
         pi = np.zeros(self.n_states, dtype=np.int32)
         gap = np.zeros(self.n_states)
         st = np.zeros(4)
-        rc = self.lib.or_solve(self.ref, thr, int(max_sweeps), int(fixed_sweeps), _dp(V),
+        rule = {"span": 0, "supnorm": 1}[stop_rule]
+        rc = self.lib.or_solve(self.ref, thr, int(max_sweeps), int(fixed_sweeps), rule, _dp(V),
                                _ip(pi), _dp(gap), _dp(st))
         return {"V": V, "pi": pi, "gap": gap, "sweeps": int(st[0]), "span": st[1],
                 "dmax": st[2], "dmin": st[3], "converged": rc == 0}

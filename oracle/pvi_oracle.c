@@ -45,6 +45,7 @@ typedef struct {
     double rho;
     double c_var[2], c_fixed, c_hold, c_short, c_waste, c_rev[2];
     double gamma;
+    int32_t issuing;     /* A: 0 = FIFO (eq:demoor:fifo), 1 = LIFO (eq:demoor:lifo) */
 } or_mdp;
 
 static double pos(double x) { return x > 0.0 ? x : 0.0; }
@@ -113,12 +114,26 @@ static void trans_a(const or_mdp* p, const int32_t* dig, int a, int d, int32_t* 
     for (int j = 1; j <= m; ++j) X[j] = dig[(L - 1) + (m - j)];
     int Xtot = 0;
     for (int j = 1; j <= m; ++j) Xtot += X[j];
-    int W = ipos(X[1] - d); /* units expiring at the end of the day */
-    int Xn[OR_MAXD + 1], On[OR_MAXD + 1];
-    int cum = 0;
-    for (int j = 1; j <= m - 1; ++j) {
-        cum += X[j];
-        Xn[j] = ipos(X[j + 1] - ipos(d - cum));
+    int W, Xn[OR_MAXD + 1], On[OR_MAXD + 1];
+    if (p->issuing == 1) {
+        /* LIFO (eq:demoor:lifo): the youngest units go first; X_{j+1} meets the
+           demand left after X_m .. X_{j+2}, and X_1 only what the others could not */
+        int above = 0; /* X_2 + ... + X_m */
+        for (int k = 2; k <= m; ++k) above += X[k];
+        W = ipos(X[1] - ipos(d - above));
+        for (int j = 1; j <= m - 1; ++j) {
+            int younger = 0; /* X_{j+2} + ... + X_m */
+            for (int k = j + 2; k <= m; ++k) younger += X[k];
+            Xn[j] = ipos(X[j + 1] - ipos(d - younger));
+        }
+    } else {
+        /* FIFO (eq:demoor:fifo): the oldest units go first */
+        W = ipos(X[1] - d); /* units expiring at the end of the day */
+        int cum = 0;
+        for (int j = 1; j <= m - 1; ++j) {
+            cum += X[j];
+            Xn[j] = ipos(X[j + 1] - ipos(d - cum));
+        }
     }
     Xn[m] = (L >= 2) ? O[1] : a;
     if (L >= 2) {
@@ -377,8 +392,10 @@ int or_sweep(const or_mdp* p, const double* V, double* Vnew, int32_t* pi, double
  * positive (no early stop), or at max_sweeps (returns 1).  The policy comes from
  * one more backup of V_ret.  out_stats = {sweeps, final span, max dV, min dV}.
  */
+/* stop_rule 0: span rule, max(V'-V) - min(V'-V) < thr (Appendix B);
+   stop_rule 1: sup-norm rule, max |V' - V| < thr (Appendix A). */
 int or_solve(const or_mdp* p, double thr, int32_t max_sweeps, int32_t fixed_sweeps,
-             double* V, int32_t* pi, double* gap, double* out_stats) {
+             int32_t stop_rule, double* V, int32_t* pi, double* gap, double* out_stats) {
     int64_t ns = or_num_states(p);
     double* Vn = (double*)malloc(sizeof(double) * ns);
     double* Vx = (double*)malloc(sizeof(double) * ns);
@@ -397,7 +414,8 @@ int or_solve(const or_mdp* p, double thr, int32_t max_sweeps, int32_t fixed_swee
         }
         span = dmax - dmin;
         memcpy(V, Vn, sizeof(double) * ns);
-        if (fixed_sweeps <= 0 && span < thr) {
+        const double crit = stop_rule == 1 ? fmax(fabs(dmax), fabs(dmin)) : span;
+        if (fixed_sweeps <= 0 && crit < thr) {
             rc = 0;
             break;
         }

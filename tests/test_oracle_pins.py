@@ -136,7 +136,8 @@ def _golden_scenario(case):
     if s["family"] == "A":
         return W.scenario_a(m=s["m"], L=s["L"], a_max=s["a_max"], d_max=s["d_max"],
                             costs=W.scenarios._costs(var=(c["var"], 0), hold=c["hold"],
-                                                     short=c["short"], waste=c["waste"]))
+                                                     short=c["short"], waste=c["waste"]),
+                            issuing=s.get("issuing", "fifo"))
     if s["family"] == "B":
         return W.scenario_b(m=s["m"], a_max=s["a_max"], d_max=s["d_max"],
                             costs=W.scenarios._costs(var=c["var"], rev=c["rev"]))
@@ -171,10 +172,14 @@ SMALL = [
     W.scenario_a(m=3, L=2, a_max=2, d_max=8),
     W.scenario_a(m=1, L=1, a_max=4, d_max=8),
     W.scenario_a(m=1, L=3, a_max=2, d_max=5),
+    W.scenario_a(m=3, L=1, a_max=3, d_max=9, issuing="lifo"),
+    W.scenario_a(m=3, L=2, a_max=2, d_max=8, issuing="lifo"),
+    W.scenario_a(m=4, L=1, a_max=2, d_max=8, issuing="lifo"),
 ]
 
 
-@pytest.mark.parametrize("sc", SMALL, ids=lambda s: f"A-m{s['m']}-L{s['L']}")
+@pytest.mark.parametrize("sc", SMALL,
+                         ids=lambda s: f"A-m{s['m']}-L{s['L']}-{s.get('issuing', 'fifo')}")
 def test_transitions_a_match_unit_model(sc):
     o = Oracle(sc)
     for s in range(o.n_states):
@@ -209,9 +214,13 @@ def test_transitions_c_match_unit_model():
                 assert sn == sn2 and r == pytest.approx(r2, abs=1e-12)
 
 
-def test_conservation_a():
-    """on hand + arriving = issued + wasted + carried, for every transition (m=3, L=2)."""
-    sc = SMALL[3]
+@pytest.mark.parametrize("issuing", ["fifo", "lifo"])
+def test_conservation_a(issuing):
+    """on hand + arriving = issued + wasted + carried, for every transition (m=3, L=2).
+
+    FIFO wastes what the demand leaves of X_1; LIFO wastes what it leaves of X_1 after
+    the younger units X_2..X_m are gone."""
+    sc = W.scenario_a(m=3, L=2, a_max=2, d_max=8, issuing=issuing)
     o = Oracle(sc)
     m, L = sc["m"], sc["L"]
     for s in range(o.n_states):
@@ -222,9 +231,30 @@ def test_conservation_a():
                 sn, _ = o.transition(s, a, [d])
                 nd = o.decode(sn)
                 issued = min(d, stock)
-                wasted = max(int(dig[-1]) - d, 0)
+                younger = stock - int(dig[-1]) if issuing == "lifo" else 0
+                wasted = max(int(dig[-1]) - max(d - younger, 0), 0)
                 carried = int(nd[L - 1:].sum()) - int(dig[L - 2])   # minus the new arrival
                 assert stock == issued + wasted + carried
+
+
+def test_lifo_equals_fifo_with_one_life_class():
+    """m = 1: a single life class, so the issuing order cannot matter."""
+    for L in (1, 2):
+        fifo = Oracle(W.scenario_a(m=1, L=L, a_max=4, d_max=8))
+        lifo = Oracle(W.scenario_a(m=1, L=L, a_max=4, d_max=8, issuing="lifo"))
+        V = np.random.default_rng(3).normal(0.0, 20.0, fifo.n_states)
+        for x, y in zip(fifo.sweep(V), lifo.sweep(V)):
+            assert np.array_equal(x, y)
+
+
+def test_lifo_differs_from_fifo_when_ages_mix():
+    """m = 2 with both ages on hand and demand below the total: FIFO keeps the young
+    units, LIFO keeps the old ones (which then expire)."""
+    fifo = Oracle(W.scenario_a(m=2, L=1, a_max=5, d_max=9))
+    lifo = Oracle(W.scenario_a(m=2, L=1, a_max=5, d_max=9, issuing="lifo"))
+    s = fifo.encode([2, 3])                     # X_2 = 2 young, X_1 = 3 old
+    assert fifo.transition(s, 0, [2]) == (fifo.encode([0, 2]), -2.0 * 1.0 - 7.0 * 1.0)
+    assert lifo.transition(s, 0, [2]) == (lifo.encode([0, 0]), -7.0 * 3.0)
 
 
 # ------------------------------------------------------------------ Bellman operator
@@ -239,13 +269,14 @@ def _dense(sc):
 
 DENSE = [
     W.scenario_a(m=2, L=2, a_max=3, d_max=7),
+    W.scenario_a(m=3, L=1, a_max=3, d_max=8, issuing="lifo"),
     W.scenario_a(m=3, L=1, a_max=3, d_max=9, demand={"kind": "gamma", "mean": [2.0],
                                                       "cv": [0.8]}),
     W.scenario_b(m=3, a_max=(2, 2), d_max=(4, 3), means=(1.5, 1.2), rho=0.5),
     W.scenario_c(m=3, a_max=3, d_max=5, n_periods=3, n=[2.0, 5.0, 3.0],
                  means=[1.5, 2.5, 2.0], c0=[0.0, 0.5, 1.0], c1=[0.0, 0.1, -0.2]),
 ]
-DENSE_IDS = ["A-m2L2", "A-m3L1-gamma", "B-m3", "C-m3-endogenous"]
+DENSE_IDS = ["A-m2L2", "A-m3L1-lifo", "A-m3L1-gamma", "B-m3", "C-m3-endogenous"]
 
 
 @pytest.fixture(scope="module", params=list(range(len(DENSE))), ids=DENSE_IDS)
@@ -315,6 +346,22 @@ def test_vi_against_lp_and_policy_iteration(dense):
     Qs = np.sort(Q, axis=0)
     clear = (Qs[-1] - Qs[-2]) > 1e-6
     assert np.array_equal(res["pi"][clear], pi_star[clear])
+
+
+def test_supnorm_stop_bound(dense):
+    """The sup-norm rule (Appendix A): once max|V_i - V_{i-1}| < eps the iterate is
+    within gamma eps / (1 - gamma) of the optimum (LP), and it never stops earlier
+    than the first sweep meeting the rule."""
+    sc, o, P, r = dense
+    g = sc["gamma"]
+    V_lp = _lp_optimum(P, r, g)
+    for eps in (1e-2, 1e-5):
+        res = o.solve(thr=eps, stop_rule="supnorm")
+        assert res["converged"] and max(abs(res["dmax"]), abs(res["dmin"])) < eps
+        assert np.abs(res["V"] - V_lp).max() <= g * eps / (1.0 - g) + 1e-6
+        if res["sweeps"] > 1:
+            prev = o.solve(thr=eps, fixed_sweeps=res["sweeps"] - 1)
+            assert max(abs(prev["dmax"]), abs(prev["dmin"])) >= eps
 
 
 def test_policy_evaluation_fixed_point(dense):

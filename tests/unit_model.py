@@ -2,7 +2,8 @@
 
 The oracle writes each transition as the paper's digit formulas.  This module
 instead keeps an explicit list of units, each with its days of life left, issues
-the oldest first, throws away what reaches the end of its life, and counts the
+the oldest first (youngest first for LIFO scenario A), throws away what reaches the
+end of its life, and counts the
 costs by looking at the units.  Building dense P(s'|s,a) and r(s,a) from it gives
 a second, structurally different model of the same MDP, so the oracle's Bellman
 operator can be checked against it on tiny instances.
@@ -70,6 +71,12 @@ def _serve(units, demand):
     return n, units[n:]
 
 
+def _serve_youngest(units, demand):
+    """Issue `demand` units, youngest (most days left) first."""
+    n = min(demand, len(units))
+    return n, units[:len(units) - n]
+
+
 def step(sc, s, a, omega):
     """One day of the unit model.  Returns (next state index, reward)."""
     fam, m, L = sc["family"], sc["m"], sc["L"]
@@ -80,7 +87,8 @@ def step(sc, s, a, omega):
         stock = {life: dig[(L - 1) + (m - life)] for life in range(1, m + 1)}
         units = _units(stock)
         d = omega[0]
-        issued, left = _serve(units, d)
+        serve = _serve_youngest if sc.get("issuing", "fifo") == "lifo" else _serve
+        issued, left = serve(units, d)
         short = d - issued
         expired = sum(1 for u in left if u == 1)
         kept = [u - 1 for u in left if u > 1]

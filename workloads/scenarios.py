@@ -41,8 +41,9 @@ def _costs(var=(0.0, 0.0), fixed=0.0, hold=0.0, short=0.0, waste=0.0, rev=(0.0, 
 
 
 def scenario_a(m=2, L=1, a_max=10, d_max=20, demand=None, costs=None, gamma=0.99,
-               eps=1e-4):
-    """Scenario A (single product, lead time L >= 1, FIFO issuing)."""
+               eps=1e-4, issuing="fifo"):
+    """Scenario A (single product, lead time L >= 1, FIFO or LIFO issuing)."""
+    assert issuing in ("fifo", "lifo")
     if demand is None:
         demand = {"kind": "poisson", "mean": [4.0]}
     if costs is None:
@@ -51,7 +52,8 @@ def scenario_a(m=2, L=1, a_max=10, d_max=20, demand=None, costs=None, gamma=0.99
             "a_max": [int(a_max), 0], "d_max": [int(d_max), 0],
             "demand": [copy.deepcopy(demand), {"kind": "none", "mean": [0.0]}],
             "rul_c0": [0.0] * int(m), "rul_c1": [0.0] * int(m), "subst_rho": 0.0,
-            "costs": copy.deepcopy(costs), "gamma": float(gamma), "eps": float(eps)}
+            "costs": copy.deepcopy(costs), "gamma": float(gamma), "eps": float(eps),
+            "issuing": issuing}
 
 
 def scenario_b(m=3, a_max=(14, 14), d_max=(20, 20), means=(5.0, 4.0), rho=0.5,
