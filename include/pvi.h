@@ -88,6 +88,22 @@ typedef enum {
                           polish as PVI_FP32 */
 } pvi_precision;
 
+/* Scenario A issuing order (Appendix A): FIFO issues the oldest units first
+ * (FIFO issuing/ageing equation), LIFO the youngest (LIFO issuing/ageing
+ * equation).  The other families issue FIFO. */
+typedef enum {
+    PVI_FIFO = 0,
+    PVI_LIFO = 1
+} pvi_issuing;
+
+/* Stopping rule of vi_solve.  SPAN (Appendix B convergence test): stop when
+ * max(V_new - V) - min(V_new - V) < eps (1 - gamma) / gamma.  SUPNORM (Appendix A
+ * convergence test): stop when max |V_new - V| < eps. */
+typedef enum {
+    PVI_STOP_SPAN = 0,
+    PVI_STOP_SUPNORM = 1
+} pvi_stop_rule;
+
 #define PVI_MAX_PERIODS 7
 #define PVI_MAX_LIFE 8
 
@@ -96,7 +112,8 @@ typedef enum {
  * P(d_max) = P(D >= d_max) (Poisson, negative binomial) or 1 - F(d_max - 1/2)
  * (gamma). */
 typedef struct pvi_mdp_desc {
-    uint32_t struct_size;      /* sizeof(pvi_mdp_desc) */
+    uint32_t struct_size;      /* sizeof(pvi_mdp_desc); a smaller size that ends before
+                                  `issuing` is accepted, the missing fields read 0 */
     int32_t family;            /* pvi_family */
     int32_t m;                 /* maximum useful life, 1..PVI_MAX_LIFE */
     int32_t lead_time;         /* A: >= 1; B and C: 0 */
@@ -115,18 +132,21 @@ typedef struct pvi_mdp_desc {
     double c_hold, c_short, c_waste;
     double c_rev[2];           /* B: revenue per unit issued */
     double gamma;              /* discount factor, 0 < gamma < 1 */
+    int32_t issuing;           /* A: pvi_issuing (absent in older callers' struct_size: FIFO) */
 } pvi_mdp_desc;
 
 typedef struct pvi_solve_opts {
-    uint32_t struct_size;      /* sizeof(pvi_solve_opts) */
+    uint32_t struct_size;      /* sizeof(pvi_solve_opts); a smaller size that ends before
+                                  `stop_rule` is accepted, the missing field reads 0 */
     int32_t precision;         /* pvi_precision */
-    double eps;                /* stop when span(V_new - V) < eps (1-gamma)/gamma */
+    double eps;                /* tolerance of the stopping rule (see pvi_stop_rule) */
     int32_t max_sweeps;        /* cap on sweeps (> 0) */
     int32_t fixed_sweeps;      /* > 0: run exactly this many sweeps, no early stop */
     const double* v0;          /* optional host [N_S] initial values; NULL = zeros */
     void* stream;              /* optional hipStream_t; NULL = the handle's own */
     int32_t check_every;       /* sweeps launched between host checks; 0 = default */
     int32_t time_kernels;      /* 1: time every backup launch with HIP events */
+    int32_t stop_rule;         /* pvi_stop_rule (absent in older callers' struct_size: SPAN) */
 } pvi_solve_opts;
 
 typedef struct pvi_result {
@@ -136,7 +156,7 @@ typedef struct pvi_result {
     int32_t backup_launches[2];/* backup launches timed (time_kernels = 1); [0] FP64
                                   storage sweeps, [1] FP32 storage sweeps */
     double final_span;         /* span of the last V_new - V */
-    double threshold;          /* eps (1-gamma)/gamma */
+    double threshold;          /* span rule: eps (1-gamma)/gamma; sup-norm rule: eps */
     double dmax, dmin;         /* max and min of the last V_new - V */
     double wall_ms;            /* host wall time of the solve */
     double backup_ms[2];       /* summed backup kernel time of those launches */

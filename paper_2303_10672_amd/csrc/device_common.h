@@ -64,6 +64,8 @@ __device__ inline void span_update(Ctl* ctl, double a0, double a1, double a2, do
         ctl->mu += 0.5 * (a2 + a3);
     }
     const double span = dmax - dmin;
+    // stopping criterion: the span (rule 0) or max |V_new - V| (rule 1)
+    const double crit = ctl->rule == 1 ? fmax(fabs(dmax), fabs(dmin)) : span;
     ctl->dmax = dmax;
     ctl->dmin = dmin;
     ctl->span = span;
@@ -78,11 +80,13 @@ __device__ inline void span_update(Ctl* ctl, double a0, double a1, double a2, do
         } else {
             ctl->stall += 1;
         }
-        if (span < ctl->thr || span <= ctl->floor32 * vabs || ctl->stall >= 3) {
+        // the FP32 phase hands over to FP64 at the FP32 floor (span based for
+        // either rule) or when the rule itself is met
+        if (crit < ctl->thr || span <= ctl->floor32 * vabs || ctl->stall >= 3) {
             ctl->stop = 1;
             ctl->stop_sweep = ctl->sweeps;
         }
-    } else if (span < ctl->thr) {
+    } else if (crit < ctl->thr) {
         ctl->stop = 1;
         ctl->stop_sweep = ctl->sweeps;
     }

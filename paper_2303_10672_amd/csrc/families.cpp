@@ -22,6 +22,10 @@ ADev make_adev(const pvi_mdp* p) {
     a.nz = p->m >= 2 ? (int)ipow(R, p->m - 2) : 1;
     a.r2 = p->m >= 2 ? R : 1;
     a.tiles = (int)(ipow(R, p->L - 1) * a.nz);
+    // LIFO (m >= 2) has its own kernel over tiles (O, X_{m-1}..X_2); with one life
+    // class the two issuing orders coincide and the FIFO kernel runs
+    a.lifo = (p->d.issuing == PVI_LIFO && p->m >= 2) ? 1 : 0;
+    a.lmax = (p->m >= 2 ? (p->m - 2) * (R - 1) : 0) + a.r2;
     a.G = p->a_G;
     a.CH = p->a_CH;
     a.groups = p->dev.agroups;
@@ -136,8 +140,12 @@ std::string family_support_msg(const pvi_mdp* p) {
 bool family_supported(const pvi_mdp* p) { return family_support_msg(p) == "ok"; }
 
 int family_tiles(const pvi_mdp* p) {
-    if (p->family == PVI_FAMILY_LEADTIME)  // one span partial per tile group
-        return p->a_G > 0 ? (int)(p->a_groups.size() / p->a_G) : 1;
+    if (p->family == PVI_FAMILY_LEADTIME) {
+        const int R = p->rad[0];
+        if (p->d.issuing == PVI_LIFO && p->m >= 2)  // one partial per LIFO tile
+            return (int)(ipow(R, p->L - 1) * ipow(R, p->m - 2));
+        return p->a_G > 0 ? (int)(p->a_groups.size() / p->a_G) : 1;  // one per tile group
+    }
     if (p->family == PVI_FAMILY_SUBST2) return (int)ipow(p->rad[1], p->m - 1);
     if (p->family == PVI_FAMILY_RUL_WEEKDAY)
         return (int)(p->P * ((ipow(p->rad[0], p->m - 1) + 255) / 256));
@@ -228,6 +236,7 @@ hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, int fixed
         a.v_in = vin;
         a.v_out = vout;
         a.fixed = fixed;
+        if (a.lifo) return launch_backup_a_lifo(a, fp32, extract, s);
         return launch_backup_a(a, fp32, kahan, extract, s);
     }
     if (p->family == PVI_FAMILY_SUBST2) {

@@ -144,38 +144,48 @@ __global__ __launch_bounds__(1024) void c_merge2_kernel(CDev p, const void* in_,
 // LB consecutive values of the digits below j); the slab in[r'][z_j][lo] for every
 // remaining count r' is staged in LDS once, and each lane (x_j, lo) produces
 //   T_j(r) = sum_{y<=r} Bin(y; r, q_j) T_{j-1}(.., c(x_j + y), ..; r - y)
-// for every r.  Lanes with consecutive lo touch consecutive addresses.
+// for every r.  Lanes with consecutive lo touch consecutive addresses; each lane
+// stages one (z_j, lo) column over all r', so no index division runs per element.
+// The binomial weights Bin(y; r, q_j) are staged in LDS beside the slab.
+// The grid is one-dimensional and remapped so that each XCD takes a contiguous run
+// of blocks: neighbouring lo-blocks share cache lines, which then meet in one L2
+// instead of being fetched and written back in halves by two XCDs.
 template <typename VT, int LB>
-__global__ __launch_bounds__(512) void c_merge_kernel(CDev p, int j, const void* in_,
-                                                      void* out_) {
+__global__ __launch_bounds__(1024) void c_merge_kernel(CDev p, int j, const void* in_,
+                                                       void* out_) {
     extern __shared__ __align__(16) unsigned char smem[];
     if (!p.extract && p.ctl->stop) return;
     const int R = p.R, tid = threadIdx.x;
-    VT* slab = reinterpret_cast<VT*>(smem);                        // [r'][z][LB]
-    double* bq = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)R * R * LB);
-    const int tym = blockIdx.y, tau = tym / R, ym = tym - tau * R;
-    const int nr = R - ym;
-    const int64_t nlo = p.pow_r[j - 1];            // R^(j-1) values below digit j
+    VT* slab = reinterpret_cast<VT*>(smem);  // [r'][z][LB]
+    double* bq = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)R * R * LB);  // [r][y]
+    const int64_t nlo = p.pow_r[j - 1];  // R^(j-1) values below digit j
     const int64_t nlob = (nlo + LB - 1) / LB;
-    const int64_t hi = blockIdx.x / nlob;
-    const int64_t lo0 = (blockIdx.x - hi * nlob) * LB;
-    const int64_t base = hi * nlo * R + lo0;        // digits above j, digit j = 0, lo0
+    const int64_t nx = (p.nblk / (nlo * R)) * nlob;  // blocks per (tau, y_m)
+    const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int tym = (int)(lid / nx), tau = tym / R, ym = tym - tau * R;
+    const int64_t xb = lid - (int64_t)tym * nx;
+    const int nr = R - ym;
+    const int64_t hi = xb / nlob;
+    const int64_t lo0 = (xb - hi * nlob) * LB;
+    const int64_t base = hi * nlo * R + lo0;  // digits above j, digit j = 0, lo0
     const int64_t row0 = (int64_t)tau * p.npair + p.pair_base[ym];
+    const int l = tid % LB, xz = tid / LB;  // lane: lo offset, digit j value
+    const bool lane_ok = xz < R && lo0 + l < nlo;
     const VT* in = reinterpret_cast<const VT*>(in_);
-    for (int i = tid; i < nr * R * LB; i += blockDim.x) {
-        const int l = i % LB, z = (i / LB) % R, rr = i / (LB * R);
-        slab[i] = lo0 + l < nlo ? in[(row0 + rr) * p.nblk + base + (int64_t)z * nlo + l] : VT(0);
+    if (xz < R) {
+        const VT* src = in + row0 * p.nblk + base + (int64_t)xz * nlo + l;
+        for (int rr = 0; rr < nr; ++rr)
+            slab[(rr * R + xz) * LB + l] = lo0 + l < nlo ? src[(int64_t)rr * p.nblk] : VT(0);
     }
-    for (int i = tid; i < R * R; i += blockDim.x) bq[i] = p.binq[((size_t)j * R) * R + i];
+    for (int i = tid; i < R * R; i += blockDim.x) bq[i] = p.binq[(size_t)j * R * R + i];
     __syncthreads();
-    const int l = tid % LB, xj = tid / LB;
-    if (xj >= R || lo0 + l >= nlo) return;
-    VT* out = reinterpret_cast<VT*>(out_);
+    if (!lane_ok) return;
+    VT* out = reinterpret_cast<VT*>(out_) + row0 * p.nblk + base + (int64_t)xz * nlo + l;
     for (int r = 0; r < nr; ++r) {
         double acc = 0.0;
         for (int y = 0; y <= r; ++y)
-            acc = fma(bq[r * R + y], (double)slab[((r - y) * R + min(xj + y, R - 1)) * LB + l], acc);
-        out[(row0 + r) * p.nblk + base + (int64_t)xj * nlo + l] = (VT)acc;
+            acc = fma(bq[r * R + y], (double)slab[((r - y) * R + min(xz + y, R - 1)) * LB + l], acc);
+        out[(int64_t)r * p.nblk] = (VT)acc;
     }
 }
 
@@ -265,19 +275,25 @@ static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
             hipLaunchKernelGGL((c_merge2_kernel<VT>), dim3((unsigned)(p.nblk / (p.R * p.R)), p.P * p.R),
                                dim3(threads), 0, s, p, in, out);
         } else {
-            // widest block of low digits whose slab stays within 32 KB of LDS, so
-            // several workgroups share a CU and overlap their loads with compute
+            // the widest block of low digits (up to 64 bytes per slab row) whose slab
+            // stays within 32 KB of LDS, so several workgroups share a CU
             auto lds_for = [&](int lb) {
                 return sizeof(VT) * (size_t)p.R * p.R * lb + sizeof(double) * p.R * p.R;
             };
-            const int lb = lds_for(16) <= 32768 ? 16 : lds_for(8) <= 32768 ? 8 : 4;
-            if (lds_for(lb) > 65536) return hipErrorInvalidConfiguration;
+            int lb = (int)(64 / sizeof(VT));
+            while (lb > 4 && (lds_for(lb) > 32768 || p.R * lb > 1024)) lb /= 2;
+            if (lds_for(lb) > 65536 || p.R * lb > 1024) return hipErrorInvalidConfiguration;
             const int64_t nlo = p.pow_r[j - 1];
             const int64_t nlob = (nlo + lb - 1) / lb;
             const int64_t nhi = p.nblk / (nlo * p.R);
             const int threads = ((p.R * lb + 63) / 64) * 64;
-            const dim3 grid((unsigned)(nhi * nlob), p.P * p.R);
-            if (lb == 16)
+            const int64_t nwg = nhi * nlob * p.P * p.R;
+            if (nwg > 0x7fffffff) return hipErrorInvalidConfiguration;
+            const dim3 grid((unsigned)nwg);
+            if (lb == 32)
+                hipLaunchKernelGGL((c_merge_kernel<VT, 32>), grid, dim3(threads), lds_for(lb), s, p,
+                                   j, in, out);
+            else if (lb == 16)
                 hipLaunchKernelGGL((c_merge_kernel<VT, 16>), grid, dim3(threads), lds_for(lb), s, p,
                                    j, in, out);
             else if (lb == 8)

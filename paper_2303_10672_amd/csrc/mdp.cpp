@@ -1,7 +1,9 @@
 // Descriptor validation, host tables and the small accessors of the C ABI.
 #include "mdp.h"
 
+#include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
@@ -28,8 +30,9 @@ static int64_t ipow_i(int64_t b, int e) {
 }
 
 // Scenario A expected one-day reward without the order cost, as a table over
-// (X_1, total stock): sum_d P(d) (-C_h [X - d - W]^+ - C_s [d - X]^+ - C_w W),
-// W = [X_1 - d]^+ (Appendix A, reward equation).
+// (X_1, total stock) for FIFO or (X_1, X_2 + ... + X_m) for LIFO:
+// sum_d P(d) (-C_h [X - d - W]^+ - C_s [d - X]^+ - C_w W) with W from the FIFO or
+// LIFO issuing equation (Appendix A, reward equation).
 static void build_a_tables(pvi_mdp* p) {
     const int R = p->rad[0], dm = p->dmax[0];
     const auto& P = p->pmf[0];
@@ -55,15 +58,20 @@ static void build_a_tables(pvi_mdp* p) {
     p->xt = p->m * (R - 1) + 1;
     p->a_r0.assign((size_t)R * p->xt, 0.0);
     const double ch = p->d.c_hold, cs = p->d.c_short, cw = p->d.c_waste;
+    // with one life class LIFO and FIFO coincide and the FIFO kernel and table serve
+    const bool lifo = p->d.issuing == PVI_LIFO && p->m >= 2;
+    // FIFO: r0[X_1][X], X the total stock; LIFO: r0[X_1][K], K = X_2 + ... + X_m,
+    // whose waste is what the demand leaves of X_1 after the younger units
     for (int x1 = 0; x1 < R; ++x1)
-        for (int X = 0; X < p->xt; ++X) {
+        for (int k = 0; k < p->xt; ++k) {
+            const int X = lifo ? x1 + k : k;
             double e = 0.0;
             for (int d = 0; d <= dm; ++d) {
-                const int W = std::max(x1 - d, 0);
+                const int W = lifo ? std::max(x1 - std::max(d - k, 0), 0) : std::max(x1 - d, 0);
                 const double r = -ch * std::max(X - d - W, 0) - cs * std::max(d - X, 0) - cw * W;
                 e += P[d] * r;
             }
-            p->a_r0[(size_t)x1 * p->xt + X] = e;
+            p->a_r0[(size_t)x1 * p->xt + k] = e;
         }
     // multiply-adds that contribute to a result, per sweep, in the per-diagonal
     // prefix-sum scheme: for a tile of digit sum b (of X_m..X_3) and one action,
@@ -89,6 +97,13 @@ static void build_a_tables(pvi_mdp* p) {
         ex += cnt[b] * per;
     }
     p->executed_per_sweep = nh * ex * R;
+    if (lifo) {
+        // per tile and action: K + 1 terms for each X_m = t (K = b + t)
+        int64_t ex2 = 0;
+        for (size_t b = 0; b < cnt.size(); ++b)
+            for (int t = 0; t < R; ++t) ex2 += cnt[b] * ((int64_t)b + t + 1);
+        p->executed_per_sweep = nh * ex2 * R;
+    }
 
     // Work list of the backup kernel.  One wavefront takes G = floor(64 / R) tiles
     // of equal digit sum b (so their loops run in lockstep), R lanes each.  Tiles are
@@ -325,9 +340,18 @@ const char* pvi_last_error(void) { return pvi::g_err.c_str(); }
 
 pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out) {
     if (!desc || !out) return fail(PVI_E_INVALID, "mdp_create: NULL argument");
-    if (desc->struct_size < sizeof(pvi_mdp_desc))
+    // callers built against the layout that ended at `gamma` are accepted; fields
+    // past their struct_size read as zero
+    if (desc->struct_size < offsetof(pvi_mdp_desc, issuing))
         return fail(PVI_E_INVALID, "mdp_create: struct_size too small");
-    const pvi_mdp_desc& d = *desc;
+    pvi_mdp_desc dc{};
+    std::memcpy(&dc, desc, std::min<size_t>(desc->struct_size, sizeof(pvi_mdp_desc)));
+    dc.struct_size = sizeof(pvi_mdp_desc);
+    const pvi_mdp_desc& d = dc;
+    if (d.issuing != PVI_FIFO && d.issuing != PVI_LIFO)
+        return fail(PVI_E_INVALID, "mdp_create: issuing must be PVI_FIFO or PVI_LIFO");
+    if (d.issuing == PVI_LIFO && d.family != PVI_FAMILY_LEADTIME)
+        return fail(PVI_E_INVALID, "mdp_create: LIFO issuing is defined for scenario A only");
     if (d.family < 0 || d.family > 2) return fail(PVI_E_INVALID, "mdp_create: bad family");
     if (d.m < 1 || d.m > PVI_MAX_LIFE) return fail(PVI_E_INVALID, "mdp_create: m out of range");
     if (!(d.gamma > 0.0 && d.gamma < 1.0))

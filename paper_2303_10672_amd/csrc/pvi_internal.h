@@ -41,7 +41,8 @@ struct Ctl {
     int32_t stop_sweep;
     int32_t stall;    // sweeps without a new best span (FP32 phase)
     int32_t fp32_phase;
-    int32_t pad[3];
+    int32_t rule;     // 0: span rule, 1: sup-norm rule max|V_new - V| < thr
+    int32_t pad[2];
 };
 
 // ------------------------------------------------------------------ family A
@@ -66,6 +67,8 @@ struct ADev {
     int32_t G, CH, ngroups; // tiles per wavefront, path points per staged chunk
     int32_t pow_y[8];   // R^(i-1), weight of next-state digit i inside a block
     int32_t fixed;      // 1: fixed number of sweeps, the stopping rule is not applied
+    int32_t lifo;       // 1: LIFO issuing (tiles are (O, X_{m-1}..X_2) then)
+    int32_t lmax;       // LIFO: longest backwards depletion list, (m-2)(R-1) + R
     double gamma, cvar;
 };
 
@@ -130,6 +133,8 @@ hipError_t launch_batch(const BatchItem* d_items, int n, size_t lds_bytes, int r
                         hipStream_t s);
 
 // launchers (kernels_a.hip)
+// LIFO issuing (p.lifo = 1, m >= 2): tiles (O, X_{m-1}..X_2), FP64 accumulation.
+hipError_t launch_backup_a_lifo(const ADev& p, int storage_fp32, int extract, hipStream_t s);
 hipError_t launch_backup_a(const ADev& p, int storage_fp32, int acc_kahan, int extract,
                            hipStream_t s);
 hipError_t launch_span(Ctl* ctl, const double* partials, int tiles, int storage_fp32,

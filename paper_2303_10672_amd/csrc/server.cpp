@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstddef>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -49,8 +50,11 @@ size_t small_lds_bytes(const pvi_mdp* p) {
     return sizeof(double) * (2 * (size_t)p->ns + 3 * (size_t)p->tab + p->a_r0.size());
 }
 
+// The batched kernel runs FIFO scenario A under the span rule; everything else
+// takes the sweep loop.
 bool is_small(const pvi_mdp* p, const pvi_solve_opts& o) {
-    return p->family == PVI_FAMILY_LEADTIME && o.v0 == nullptr && p->rad[0] <= 24 &&
+    return p->family == PVI_FAMILY_LEADTIME && p->d.issuing == PVI_FIFO &&
+           o.stop_rule == PVI_STOP_SPAN && o.v0 == nullptr && p->rad[0] <= 24 &&
            small_lds_bytes(p) <= kSmallMaxLds;
 }
 
@@ -350,12 +354,19 @@ pvi_status pvi_server_destroy(pvi_server* S) {
     return PVI_OK;
 }
 
-pvi_status vi_batch_submit(pvi_server* S, pvi_mdp* const* mdps, const pvi_solve_opts* opts,
+pvi_status vi_batch_submit(pvi_server* S, pvi_mdp* const* mdps, const pvi_solve_opts* opts_in,
                            int32_t n, uint64_t* tickets) {
-    if (!S || !mdps || !opts || !tickets || n < 0)
+    if (!S || !mdps || !opts_in || !tickets || n < 0)
         return fail(PVI_E_INVALID, "vi_batch_submit: NULL argument");
-    if (opts->struct_size < sizeof(pvi_solve_opts))
+    // older callers' shorter options struct: missing fields read as zero
+    if (opts_in->struct_size < offsetof(pvi_solve_opts, stop_rule))
         return fail(PVI_E_INVALID, "vi_batch_submit: struct_size too small");
+    pvi_solve_opts oc{};
+    std::memcpy(&oc, opts_in, std::min<size_t>(opts_in->struct_size, sizeof(pvi_solve_opts)));
+    oc.struct_size = sizeof(pvi_solve_opts);
+    const pvi_solve_opts* opts = &oc;
+    if (opts->stop_rule != PVI_STOP_SPAN && opts->stop_rule != PVI_STOP_SUPNORM)
+        return fail(PVI_E_INVALID, "vi_batch_submit: bad stop_rule");
     for (int i = 0; i < n; ++i) {
         if (!mdps[i]) return fail(PVI_E_INVALID, "vi_batch_submit: NULL handle");
         if (!pvi::family_supported(mdps[i]))

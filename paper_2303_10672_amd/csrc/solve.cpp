@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -127,8 +128,9 @@ struct PhaseOut {
     bool stopped = false;
 };
 
-pvi_status init_ctl(pvi_mdp* p, hipStream_t s, double thr, double c0) {
+pvi_status init_ctl(pvi_mdp* p, hipStream_t s, double thr, double c0, int rule) {
     Ctl h{};
+    h.rule = rule;
     h.mu = 0.0;
     h.c = c0;
     h.best_span = INFINITY;
@@ -219,10 +221,17 @@ using namespace pvi;
 
 extern "C" {
 
-pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* o, pvi_result* res) {
-    if (!p || !o) return fail(PVI_E_INVALID, "vi_solve: NULL argument");
-    if (o->struct_size < sizeof(pvi_solve_opts))
+pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) {
+    if (!p || !opts_in) return fail(PVI_E_INVALID, "vi_solve: NULL argument");
+    // callers built against the layout that ended at `time_kernels` are accepted;
+    // fields past their struct_size read as zero
+    if (opts_in->struct_size < offsetof(pvi_solve_opts, stop_rule))
         return fail(PVI_E_INVALID, "vi_solve: struct_size too small");
+    pvi_solve_opts oc{};
+    std::memcpy(&oc, opts_in, std::min<size_t>(opts_in->struct_size, sizeof(pvi_solve_opts)));
+    const pvi_solve_opts* o = &oc;
+    if (o->stop_rule != PVI_STOP_SPAN && o->stop_rule != PVI_STOP_SUPNORM)
+        return fail(PVI_E_INVALID, "vi_solve: bad stop_rule");
     if (o->precision < PVI_FP64 || o->precision > PVI_FP32_WIDE)
         return fail(PVI_E_INVALID, "vi_solve: bad precision");
     if (!(o->eps > 0.0)) return fail(PVI_E_INVALID, "vi_solve: eps must be > 0");
@@ -237,7 +246,7 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* o, pvi_result* res) {
     auto& d = p->dev;
     hipStream_t s = o->stream ? (hipStream_t)o->stream : d.own;
     const double g = p->d.gamma;
-    const double thr = o->eps * (1.0 - g) / g;
+    const double thr = o->stop_rule == PVI_STOP_SUPNORM ? o->eps : o->eps * (1.0 - g) / g;
     const int max_sweeps = o->max_sweeps > 0 ? o->max_sweeps : o->fixed_sweeps;
     const int kmax = o->check_every > 0 ? o->check_every : 64;
     p->have_result = 0;
@@ -255,7 +264,7 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* o, pvi_result* res) {
     const int kahan = o->precision == PVI_FP32 ? 1 : 0;
     if (fp32) {
         PVI_HIP(launch_to_f32(d.v64[0], d.v32[0], c0, p->ns, s));
-        if ((st = init_ctl(p, s, thr, c0)) != PVI_OK) return st;
+        if ((st = init_ctl(p, s, thr, c0, o->stop_rule)) != PVI_OK) return st;
         Phase ph;
         ph.fp32 = true;
         ph.kahan = kahan;
@@ -268,7 +277,7 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* o, pvi_result* res) {
     }
     const bool fp64_phase = !fp32 || o->fixed_sweeps <= 0;
     if (fp64_phase) {
-        if ((st = init_ctl(p, s, thr, 0.0)) != PVI_OK) return st;
+        if ((st = init_ctl(p, s, thr, 0.0, o->stop_rule)) != PVI_OK) return st;
         Phase ph;
         ph.fixed = fp32 ? 0 : o->fixed_sweeps;
         ph.max_sweeps = max_sweeps;
@@ -323,14 +332,14 @@ pvi_status vi_backup(pvi_mdp* p, int32_t precision, const double* v_in, double* 
     p->have_result = 0;
     PVI_HIP(hipMemcpyAsync(d.v64[0], v_in, sizeof(double) * p->ns, hipMemcpyHostToDevice, s));
     if (precision == PVI_FP64) {
-        if ((st = init_ctl(p, s, -1.0, 0.0)) != PVI_OK) return st;
+        if ((st = init_ctl(p, s, -1.0, 0.0, PVI_STOP_SPAN)) != PVI_OK) return st;
         PVI_HIP(family_backup(p, 0, 0, 0, 1, d.v64[0], d.v64[1], s));
         if (!family_fused_span(p))
             PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, 0, 1, p->d.gamma, s));
     } else {
         const double c0 = midrange(v_in, p->ns);
         PVI_HIP(launch_to_f32(d.v64[0], d.v32[0], c0, p->ns, s));
-        if ((st = init_ctl(p, s, -1.0, c0)) != PVI_OK) return st;
+        if ((st = init_ctl(p, s, -1.0, c0, PVI_STOP_SPAN)) != PVI_OK) return st;
         PVI_HIP(family_backup(p, 1, precision == PVI_FP32, 0, 1, d.v32[0], d.v32[1], s));
         if (!family_fused_span(p))
             PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, 1, 1, p->d.gamma, s));

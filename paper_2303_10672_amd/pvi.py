@@ -22,6 +22,8 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGE
                 5: "NOT_READY", 6: "CANCELLED", 7: "BUSY"}
 FAMILY = {"A": 0, "B": 1, "C": 2}
 DEMAND = {"none": 0, "poisson": 1, "gamma": 2, "negbin": 3, "table": 4}
+ISSUING = {"fifo": 0, "lifo": 1}
+STOP_RULE = {"span": 0, "supnorm": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_wide": 2}
 MAX_PERIODS, MAX_LIFE = 7, 8
 
@@ -46,6 +48,7 @@ class Desc(ctypes.Structure):
         ("c_fixed", ctypes.c_double), ("c_hold", ctypes.c_double),
         ("c_short", ctypes.c_double), ("c_waste", ctypes.c_double),
         ("c_rev", ctypes.c_double * 2), ("gamma", ctypes.c_double),
+        ("issuing", ctypes.c_int32),
     ]
 
 
@@ -55,7 +58,7 @@ class Opts(ctypes.Structure):
         ("eps", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
         ("fixed_sweeps", ctypes.c_int32), ("v0", ctypes.POINTER(ctypes.c_double)),
         ("stream", ctypes.c_void_p), ("check_every", ctypes.c_int32),
-        ("time_kernels", ctypes.c_int32),
+        ("time_kernels", ctypes.c_int32), ("stop_rule", ctypes.c_int32),
     ]
 
 
@@ -168,6 +171,7 @@ def make_desc(sc):
     d.c_fixed, d.c_hold, d.c_short, d.c_waste = c["fixed"], c["hold"], c["short"], c["waste"]
     d.c_rev[0], d.c_rev[1] = c["rev"]
     d.gamma = sc["gamma"]
+    d.issuing = ISSUING[sc.get("issuing", "fifo")]
     return d, keep
 
 
@@ -245,8 +249,9 @@ def mdp_life_probs(m):
 
 
 def make_opts(precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0, v0=None,
-              stream=None, check_every=0, time_kernels=False, sc=None):
+              stream=None, check_every=0, time_kernels=False, sc=None, stop_rule="span"):
     o = Opts()
+    o.stop_rule = STOP_RULE[stop_rule]
     o.struct_size = ctypes.sizeof(Opts)
     o.precision = PRECISION[precision]
     o.eps = float(eps if eps is not None else (sc["eps"] if sc else 1e-4))
@@ -260,11 +265,12 @@ def make_opts(precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0, v0=
 
 
 def vi_solve(m, precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0, v0=None,
-             stream=None, check_every=0, time_kernels=False, allow_not_converged=False):
+             stream=None, check_every=0, time_kernels=False, allow_not_converged=False,
+             stop_rule="span"):
     """Blocking solve; returns the pvi_result fields as a dict."""
     v0a = None if v0 is None else np.ascontiguousarray(v0, dtype=np.float64)
     o = make_opts(precision, eps, max_sweeps, fixed_sweeps, v0a, stream, check_every,
-                  time_kernels, m.sc)
+                  time_kernels, m.sc, stop_rule)
     r = Result()
     st = _lib.vi_solve(m.handle, ctypes.byref(o), ctypes.byref(r))
     if not (allow_not_converged and st == PVI_E_NOT_CONVERGED):
@@ -329,12 +335,13 @@ class Server:
         except Exception:
             pass
 
-    def submit(self, mdps, precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0):
+    def submit(self, mdps, precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0,
+               stop_rule="span"):
         """vi_batch_submit: returns one ticket per MDP (same options for all)."""
         n = len(mdps)
         arr = (ctypes.c_void_p * n)(*[m.handle for m in mdps])
         o = make_opts(precision, eps, max_sweeps, fixed_sweeps, None, None, 0, False,
-                      mdps[0].sc if n else None)
+                      mdps[0].sc if n else None, stop_rule)
         t = (ctypes.c_uint64 * n)()
         _check(_lib.vi_batch_submit(self.handle, arr, ctypes.byref(o), n, t), "vi_batch_submit")
         tickets = list(t)

@@ -31,8 +31,40 @@ def test_library_exports_every_declared_function():
 def test_struct_sizes_match_header_layout():
     # pvi_mdp_desc: 5 int32 + 3x2 int32 + 2x7x2 doubles + 2 ptrs + 16 doubles + ...
     assert ctypes.sizeof(pvi.Desc) % 8 == 0
-    assert ctypes.sizeof(pvi.Opts) == 48
+    assert ctypes.sizeof(pvi.Opts) == 56
     assert ctypes.sizeof(pvi.Result) == 96
+
+
+def test_older_struct_sizes_are_accepted_and_new_fields_checked():
+    """A descriptor or options struct that ends before the newest field (issuing,
+    stop_rule) is accepted with that field read as 0; a full-size struct with a bad
+    value is rejected; anything shorter than the first layout is rejected."""
+    lib = ctypes.CDLL(pvi.LIB_PATH)
+    lib.mdp_create.argtypes = [ctypes.POINTER(pvi.Desc), ctypes.POINTER(ctypes.c_void_p)]
+    lib.mdp_destroy.argtypes = [ctypes.c_void_p]
+    d, keep = pvi.make_desc(W.config0())
+    h = ctypes.c_void_p()
+    d.issuing = 7
+    assert lib.mdp_create(ctypes.byref(d), ctypes.byref(h)) == pvi.PVI_E_INVALID
+    d.struct_size = pvi.Desc.issuing.offset        # the layout before `issuing`
+    assert lib.mdp_create(ctypes.byref(d), ctypes.byref(h)) == pvi.PVI_OK
+    lib.mdp_destroy(h)
+    d.struct_size = pvi.Desc.issuing.offset - 8
+    assert lib.mdp_create(ctypes.byref(d), ctypes.byref(h)) == pvi.PVI_E_INVALID
+    sc = W.scenario_b(m=2, a_max=(2, 2), d_max=(4, 4), means=(1.0, 1.0), rho=0.5)
+    d2, keep2 = pvi.make_desc(sc)
+    d2.issuing = pvi.ISSUING["lifo"]                  # LIFO is defined for scenario A only
+    assert lib.mdp_create(ctypes.byref(d2), ctypes.byref(h)) == pvi.PVI_E_INVALID
+
+    m = pvi.mdp_create(W.config0())
+    lib.vi_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(pvi.Opts), ctypes.c_void_p]
+    o = pvi.make_opts("fp64", sc=W.config0())
+    o.stop_rule = 5
+    assert lib.vi_solve(m.handle, ctypes.byref(o), None) == pvi.PVI_E_INVALID
+    o.struct_size = pvi.Opts.stop_rule.offset          # older callers: rule reads as span
+    assert lib.vi_solve(m.handle, ctypes.byref(o), None) == pvi.PVI_E_DEVICE
+    o.struct_size = pvi.Opts.stop_rule.offset - 4
+    assert lib.vi_solve(m.handle, ctypes.byref(o), None) == pvi.PVI_E_INVALID
 
 
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3])
