@@ -146,11 +146,12 @@ __global__ __launch_bounds__(1024) void c_merge2_kernel(CDev p, const void* in_,
 //   T_j(r) = sum_{y<=r} Bin(y; r, q_j) T_{j-1}(.., c(x_j + y), ..; r - y)
 // for every r.  Lanes with consecutive lo touch consecutive addresses; each lane
 // stages one (z_j, lo) column over all r', so no index division runs per element.
-// The binomial weights Bin(y; r, q_j) are staged in LDS beside the slab.
-// The grid is one-dimensional and remapped so that each XCD takes a contiguous run
-// of blocks: neighbouring lo-blocks share cache lines, which then meet in one L2
-// instead of being fetched and written back in halves by two XCDs.
-template <typename VT, int LB>
+// The sum over y is unrolled up to RC >= R, so each term is an LDS read at a
+// precomputed per-lane offset, a weight Bin(y; r, q_j) (staged in LDS, the same
+// for all lanes) and one multiply-add.  The grid
+// is one-dimensional and remapped so that each XCD takes a contiguous run of blocks:
+// neighbouring lo-blocks share cache lines, which then meet in one L2.
+template <typename VT, int LB, int RC>
 __global__ __launch_bounds__(1024) void c_merge_kernel(CDev p, int j, const void* in_,
                                                        void* out_) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -158,16 +159,17 @@ __global__ __launch_bounds__(1024) void c_merge_kernel(CDev p, int j, const void
     const int R = p.R, tid = threadIdx.x;
     VT* slab = reinterpret_cast<VT*>(smem);  // [r'][z][LB]
     double* bq = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)R * R * LB);  // [r][y]
-    const int64_t nlo = p.pow_r[j - 1];  // R^(j-1) values below digit j
-    const int64_t nlob = (nlo + LB - 1) / LB;
-    const int64_t nx = (p.nblk / (nlo * R)) * nlob;  // blocks per (tau, y_m)
-    const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
-    const int tym = (int)(lid / nx), tau = tym / R, ym = tym - tau * R;
-    const int64_t xb = lid - (int64_t)tym * nx;
+    // block decomposition in 32 bits (the launcher checks that the counts fit)
+    const int nlo = (int)p.pow_r[j - 1];  // R^(j-1) values below digit j
+    const int nlob = (nlo + LB - 1) / LB;
+    const int nx = (int)(p.nblk / ((int64_t)nlo * R)) * nlob;  // blocks per (tau, y_m)
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int tym = lid / nx, tau = tym / R, ym = tym - tau * R;
+    const int xb = lid - tym * nx;
     const int nr = R - ym;
-    const int64_t hi = xb / nlob;
-    const int64_t lo0 = (xb - hi * nlob) * LB;
-    const int64_t base = hi * nlo * R + lo0;  // digits above j, digit j = 0, lo0
+    const int hi = xb / nlob;
+    const int lo0 = (xb - hi * nlob) * LB;
+    const int64_t base = (int64_t)hi * nlo * R + lo0;  // digits above j, digit j = 0, lo0
     const int64_t row0 = (int64_t)tau * p.npair + p.pair_base[ym];
     const int l = tid % LB, xz = tid / LB;  // lane: lo offset, digit j value
     const bool lane_ok = xz < R && lo0 + l < nlo;
@@ -180,11 +182,19 @@ __global__ __launch_bounds__(1024) void c_merge_kernel(CDev p, int j, const void
     for (int i = tid; i < R * R; i += blockDim.x) bq[i] = p.binq[(size_t)j * R * R + i];
     __syncthreads();
     if (!lane_ok) return;
+    // term y of row r reads slab[r - y][c(x_j + y)][lo] at r * rstride + adj[y]
+    const int rstride = R * LB;
+    int adj[RC];
+#pragma unroll
+    for (int y = 0; y < RC; ++y) adj[y] = min(xz + y, R - 1) * LB + l - y * rstride;
     VT* out = reinterpret_cast<VT*>(out_) + row0 * p.nblk + base + (int64_t)xz * nlo + l;
     for (int r = 0; r < nr; ++r) {
+        const VT* sr = slab + r * rstride;
+        const double* w = bq + r * R;
         double acc = 0.0;
-        for (int y = 0; y <= r; ++y)
-            acc = fma(bq[r * R + y], (double)slab[((r - y) * R + min(xz + y, R - 1)) * LB + l], acc);
+#pragma unroll
+        for (int y = 0; y < RC; ++y)
+            if (y <= r) acc = fma(w[y], (double)sr[adj[y]], acc);
         out[(int64_t)r * p.nblk] = (VT)acc;
     }
 }
@@ -288,26 +298,41 @@ static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
             const int64_t nhi = p.nblk / (nlo * p.R);
             const int threads = ((p.R * lb + 63) / 64) * 64;
             const int64_t nwg = nhi * nlob * p.P * p.R;
-            if (nwg > 0x7fffffff) return hipErrorInvalidConfiguration;
+            // the kernel decomposes block ids and offsets in 32 bits
+            if (nwg > 0x7fffffff || nlo * p.R > 0x7fffffff || p.R > 32)
+                return hipErrorInvalidConfiguration;
             const dim3 grid((unsigned)nwg);
-            if (lb == 32)
-                hipLaunchKernelGGL((c_merge_kernel<VT, 32>), grid, dim3(threads), lds_for(lb), s, p,
-                                   j, in, out);
-            else if (lb == 16)
-                hipLaunchKernelGGL((c_merge_kernel<VT, 16>), grid, dim3(threads), lds_for(lb), s, p,
-                                   j, in, out);
-            else if (lb == 8)
-                hipLaunchKernelGGL((c_merge_kernel<VT, 8>), grid, dim3(threads), lds_for(lb), s, p,
-                                   j, in, out);
-            else
-                hipLaunchKernelGGL((c_merge_kernel<VT, 4>), grid, dim3(threads), lds_for(lb), s, p,
-                                   j, in, out);
+            const size_t lds = lds_for(lb);
+            if ((e = launch_merge_lb<VT>(p, j, in, out, lb, grid, threads, lds, s)) != hipSuccess)
+                return e;
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         in = out;
     }
     hipLaunchKernelGGL((c_final_kernel<VT, EXTRACT>), dim3(gx, p.P), dim3(256), 0, s, p, in);
     return hipGetLastError();
+}
+
+template <typename VT, int LB>
+static hipError_t launch_merge_rc(const CDev& p, int j, const void* in, void* out, dim3 grid,
+                                  int threads, size_t lds, hipStream_t s) {
+    if (p.R <= 8)
+        hipLaunchKernelGGL((c_merge_kernel<VT, LB, 8>), grid, dim3(threads), lds, s, p, j, in, out);
+    else if (p.R <= 16)
+        hipLaunchKernelGGL((c_merge_kernel<VT, LB, 16>), grid, dim3(threads), lds, s, p, j, in, out);
+    else if (p.R <= 24)
+        hipLaunchKernelGGL((c_merge_kernel<VT, LB, 24>), grid, dim3(threads), lds, s, p, j, in, out);
+    else
+        hipLaunchKernelGGL((c_merge_kernel<VT, LB, 32>), grid, dim3(threads), lds, s, p, j, in, out);
+    return hipGetLastError();
+}
+
+template <typename VT>
+static hipError_t launch_merge_lb(const CDev& p, int j, const void* in, void* out, int lb,
+                                  dim3 grid, int threads, size_t lds, hipStream_t s) {
+    if (lb == 16) return launch_merge_rc<VT, 16>(p, j, in, out, grid, threads, lds, s);
+    if (lb == 8) return launch_merge_rc<VT, 8>(p, j, in, out, grid, threads, lds, s);
+    return launch_merge_rc<VT, 4>(p, j, in, out, grid, threads, lds, s);
 }
 
 hipError_t launch_backup_c(const CDev& p, int storage_fp32, int extract, hipStream_t s) {
