@@ -226,14 +226,15 @@ class Oracle:
         """Value iteration.  Returns dict(V, pi, gap, sweeps, span, dmax, dmin, converged).
 
         stop_rule "span": max(V'-V) - min(V'-V) < thr (Appendix B); "supnorm":
-        max |V' - V| < thr (Appendix A).
+        max |V' - V| < thr (Appendix A); "periodic": Appendix C's test over the last
+        n_periods increments, with thr the relative tolerance.
         """
         thr = self.threshold if thr is None else float(thr)
         V = np.zeros(self.n_states) if v0 is None else np.array(v0, dtype=np.float64)
         pi = np.zeros(self.n_states, dtype=np.int32)
         gap = np.zeros(self.n_states)
         st = np.zeros(4)
-        rule = {"span": 0, "supnorm": 1}[stop_rule]
+        rule = {"span": 0, "supnorm": 1, "periodic": 2}[stop_rule]
         rc = self.lib.or_solve(self.ref, thr, int(max_sweeps), int(fixed_sweeps), rule, _dp(V),
                                _ip(pi), _dp(gap), _dp(st))
         return {"V": V, "pi": pi, "gap": gap, "sweeps": int(st[0]), "span": st[1],

@@ -393,12 +393,19 @@ int or_sweep(const or_mdp* p, const double* V, double* Vnew, int32_t* pi, double
  * one more backup of V_ret.  out_stats = {sweeps, final span, max dV, min dV}.
  */
 /* stop_rule 0: span rule, max(V'-V) - min(V'-V) < thr (Appendix B);
-   stop_rule 1: sup-norm rule, max |V' - V| < thr (Appendix A). */
+   stop_rule 1: sup-norm rule, max |V' - V| < thr (Appendix A);
+   stop_rule 2: periodic rule of Appendix C with period P = n_periods: with the
+   increments d_k = V_k - V_{k-1}, the paper sums gamma^-(i-j-1) d_{i-j} over the
+   last P sweeps j = 0..P-1; multiplying that sum by gamma^(i-1) gives
+   D(s) = sum_j gamma^j d_{i-j}(s) and the same test, which is: stop once i >= P
+   and max D - min D <= 2 thr min(|max D|, |min D|). */
 int or_solve(const or_mdp* p, double thr, int32_t max_sweeps, int32_t fixed_sweeps,
              int32_t stop_rule, double* V, int32_t* pi, double* gap, double* out_stats) {
     int64_t ns = or_num_states(p);
     double* Vn = (double*)malloc(sizeof(double) * ns);
     double* Vx = (double*)malloc(sizeof(double) * ns);
+    const int P = p->n_periods > 0 ? p->n_periods : 1;
+    double* hist = stop_rule == 2 ? (double*)malloc(sizeof(double) * ns * P) : NULL;
     int sweeps = 0, rc = 1;
     double span = INFINITY, dmax = 0.0, dmin = 0.0;
     int limit = fixed_sweeps > 0 ? fixed_sweeps : max_sweeps;
@@ -413,9 +420,28 @@ int or_solve(const or_mdp* p, double thr, int32_t max_sweeps, int32_t fixed_swee
             if (dv < dmin) dmin = dv;
         }
         span = dmax - dmin;
+        int periodic_met = 0;
+        if (stop_rule == 2) {
+            /* increment of sweep i = sweeps kept in slot i mod P */
+            double* di = hist + (size_t)(sweeps % P) * ns;
+            for (int64_t s = 0; s < ns; ++s) di[s] = Vn[s] - V[s];
+            if (sweeps >= P) {
+                double Dmax = -INFINITY, Dmin = INFINITY;
+                for (int64_t s = 0; s < ns; ++s) {
+                    double D = 0.0, w = 1.0;
+                    for (int j = 0; j < P; ++j) {
+                        D += w * hist[(size_t)((sweeps - j) % P) * ns + s];
+                        w *= p->gamma;
+                    }
+                    if (D > Dmax) Dmax = D;
+                    if (D < Dmin) Dmin = D;
+                }
+                periodic_met = Dmax - Dmin <= 2.0 * thr * fmin(fabs(Dmax), fabs(Dmin));
+            }
+        }
         memcpy(V, Vn, sizeof(double) * ns);
         const double crit = stop_rule == 1 ? fmax(fabs(dmax), fabs(dmin)) : span;
-        if (fixed_sweeps <= 0 && crit < thr) {
+        if (fixed_sweeps <= 0 && (stop_rule == 2 ? periodic_met : crit < thr)) {
             rc = 0;
             break;
         }
@@ -428,6 +454,7 @@ int or_solve(const or_mdp* p, double thr, int32_t max_sweeps, int32_t fixed_swee
     out_stats[3] = dmin;
     free(Vn);
     free(Vx);
+    free(hist);
     return rc;
 }
 

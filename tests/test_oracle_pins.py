@@ -364,6 +364,42 @@ def test_supnorm_stop_bound(dense):
             assert max(abs(prev["dmax"]), abs(prev["dmin"])) >= eps
 
 
+def _no_order_c(P):
+    """Scenario C with ordering priced out (fixed cost 1e6) and one-day stock: from
+    the second day on every state holds nothing and earns the weekday's shortage
+    reward, so after the first sweep every state's increments are the same cycle of
+    rewards."""
+    return W.scenario_c(m=2, a_max=2, d_max=6, n_periods=P, gamma=0.9,
+                        means=[1.0 + 0.5 * t for t in range(P)], n=[3.0] * P,
+                        costs=W.scenarios._costs(fixed=1e6, hold=1.0, short=20.0, waste=5.0))
+
+
+@pytest.mark.parametrize("P", [2, 3, 7])
+def test_periodic_rule_stops_after_one_full_cycle(P):
+    """Appendix C's periodic test on the instance above: the window of the last P
+    increments holds one whole weekly cycle for every state once it no longer
+    contains the first sweep (whose reward depends on the stock held), so the test
+    is met exactly at sweep P + 1 and not before."""
+    o = Oracle(_no_order_c(P))
+    res = o.solve(thr=1e-4, stop_rule="periodic")
+    assert res["converged"] and res["sweeps"] == P + 1
+    assert np.all(res["pi"] == 0)
+
+
+def test_periodic_rule_keeps_the_converged_policy():
+    """The point of the periodic test (Appendix C): once every state gains the same
+    amount per cycle the greedy policy no longer changes.  It stops far earlier than
+    the span rule and its policy equals the tightly converged one."""
+    sc = W.scenario_c(m=3, a_max=6, d_max=12, n_periods=3, means=[2.0, 3.5, 2.5],
+                      n=[5.0] * 3, c0=[0.0, 1.0, 2.0])
+    o = Oracle(sc)
+    per = o.solve(thr=1e-4, stop_rule="periodic")
+    tight = o.solve(thr=1e-11)
+    assert per["converged"] and per["sweeps"] < tight["sweeps"] // 2
+    clear = tight["gap"] > 1e-3
+    assert np.array_equal(per["pi"][clear], tight["pi"][clear])
+
+
 def test_policy_evaluation_fixed_point(dense):
     sc, o, P, r = dense
     g = sc["gamma"]
