@@ -231,17 +231,25 @@ def bench_serving(args, pvi, W):
 
 
 def bench_single(args, pvi, W, cfg):
-    """One full solve of config 2 or 3, FP64 and FP32 schedules."""
+    """One full solve of config 2 or 3, FP64 and FP32 schedules (span rule); for
+    config 3 also under the periodic rule of Appendix C (its own stopping test)."""
     sc = W.config_by_index(cfg)
     m = pvi.mdp_create(sc)
     out = {}
-    for prec in ("fp64", "fp32"):
-        pvi.vi_solve(m, precision=prec, max_sweeps=20000, allow_not_converged=True)
+    runs = [("fp64", "span"), ("fp32", "span")]
+    if cfg == 3:
+        runs += [("fp64", "periodic"), ("fp32", "periodic")]
+    for prec, rule in runs:
+        key = prec if rule == "span" else f"{prec}_{rule}"
+        pvi.vi_solve(m, precision=prec, max_sweeps=20000, allow_not_converged=True,
+                     stop_rule=rule)
         t0 = time.perf_counter()
         r = pvi.vi_solve(m, precision=prec, max_sweeps=20000, time_kernels=True,
-                         allow_not_converged=True)
+                         allow_not_converged=True, stop_rule=rule)
         dt = time.perf_counter() - t0
-        out[prec] = {"backups_per_s": r["logical_backups"] / dt, "solve_ms": dt * 1e3,
+        print(f"{key}: {dt:.2f} s, {r['sweeps_fp32']} + {r['sweeps_fp64']} sweeps",
+              file=sys.stderr, flush=True)
+        out[key] = {"backups_per_s": r["logical_backups"] / dt, "solve_ms": dt * 1e3,
                      "sweeps_fp32": r["sweeps_fp32"], "sweeps_fp64": r["sweeps_fp64"],
                      "status": r["status"], "executed_terms": r["executed_terms"],
                      "backup_ms": list(r["backup_ms"]),

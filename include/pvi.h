@@ -98,10 +98,17 @@ typedef enum {
 
 /* Stopping rule of vi_solve.  SPAN (Appendix B convergence test): stop when
  * max(V_new - V) - min(V_new - V) < eps (1 - gamma) / gamma.  SUPNORM (Appendix A
- * convergence test): stop when max |V_new - V| < eps. */
+ * convergence test): stop when max |V_new - V| < eps.  PERIODIC (Appendix C
+ * convergence test, period P = n_periods): with the increments d_k = V_k - V_{k-1}
+ * and D(s) = sum_{j=0}^{P-1} gamma^j d_{i-j}(s) (the paper's gamma^-(i-j-1)-weighted
+ * sum times gamma^(i-1), the same test), stop at sweep i >= P once
+ * max D - min D <= 2 eps min(|max D|, |min D|); eps is relative here.  The test
+ * runs on FP64 sweeps, which keep the last P + 1 value tables; with the FP32
+ * schedules the FP32 phase is a warm start of at most 2P sweeps. */
 typedef enum {
     PVI_STOP_SPAN = 0,
-    PVI_STOP_SUPNORM = 1
+    PVI_STOP_SUPNORM = 1,
+    PVI_STOP_PERIODIC = 2
 } pvi_stop_rule;
 
 #define PVI_MAX_PERIODS 7
@@ -156,7 +163,7 @@ typedef struct pvi_result {
     int32_t backup_launches[2];/* backup launches timed (time_kernels = 1); [0] FP64
                                   storage sweeps, [1] FP32 storage sweeps */
     double final_span;         /* span of the last V_new - V */
-    double threshold;          /* span rule: eps (1-gamma)/gamma; sup-norm rule: eps */
+    double threshold;          /* span rule: eps (1-gamma)/gamma; sup-norm and periodic: eps */
     double dmax, dmin;         /* max and min of the last V_new - V */
     double wall_ms;            /* host wall time of the solve */
     double backup_ms[2];       /* summed backup kernel time of those launches */

@@ -65,7 +65,10 @@ __device__ inline void span_update(Ctl* ctl, double a0, double a1, double a2, do
     }
     const double span = dmax - dmin;
     // stopping criterion: the span (rule 0) or max |V_new - V| (rule 1)
-    const double crit = ctl->rule == 1 ? fmax(fabs(dmax), fabs(dmin)) : span;
+    // (the periodic rule, 2, is decided by its own kernels after this one)
+    const double crit = ctl->rule == 1   ? fmax(fabs(dmax), fabs(dmin))
+                        : ctl->rule == 2 ? INFINITY
+                                         : span;
     ctl->dmax = dmax;
     ctl->dmin = dmin;
     ctl->span = span;

@@ -49,6 +49,10 @@ struct pvi_mdp {
         int device = -1;
         hipStream_t own = nullptr;
         double* v64[2] = {nullptr, nullptr};
+        // extra FP64 value tables of the periodic rule's ring (slots 2 .. period),
+        // taken at the first solve that needs them
+        double* vring[8] = {};
+        double* pparts = nullptr;  // periodic test partials
         float* v32[2] = {nullptr, nullptr};
         int32_t* pi = nullptr;
         double* gap = nullptr;
@@ -73,7 +77,7 @@ struct pvi_mdp {
     std::vector<double> h_v, h_gap;
     std::vector<int32_t> h_pi;
     int have_result = 0;
-    int ret_buf = 0;  // v64 buffer holding V
+    int ret_buf = 0;  // value-table slot holding V (0, 1: v64; 2..: dev.vring)
     std::mutex mu;
 };
 

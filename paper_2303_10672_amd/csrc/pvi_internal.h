@@ -41,7 +41,8 @@ struct Ctl {
     int32_t stop_sweep;
     int32_t stall;    // sweeps without a new best span (FP32 phase)
     int32_t fp32_phase;
-    int32_t rule;     // 0: span rule, 1: sup-norm rule max|V_new - V| < thr
+    int32_t rule;     // 0: span rule, 1: sup-norm rule max|V_new - V| < thr,
+                      // 2: periodic rule (decided by the periodic check kernels)
     int32_t pad[2];
 };
 
@@ -137,6 +138,17 @@ hipError_t launch_batch(const BatchItem* d_items, int n, size_t lds_bytes, int r
 hipError_t launch_backup_a_lifo(const ADev& p, int storage_fp32, int extract, hipStream_t s);
 hipError_t launch_backup_a(const ADev& p, int storage_fp32, int acc_kahan, int extract,
                            hipStream_t s);
+// Periodic stopping test after sweep i: v[j] = V_{i-j} for j = 0..P (P <= 7);
+// partials holds 2 doubles per block of the first kernel.
+struct PeriodicArgs {
+    const double* v[8];
+    int32_t P;
+    double gamma, thr;
+    int64_t n;
+};
+constexpr int kPeriodicBlocks = 1024;
+hipError_t launch_periodic_check(Ctl* ctl, const PeriodicArgs& a, double* partials,
+                                 hipStream_t s);
 hipError_t launch_span(Ctl* ctl, const double* partials, int tiles, int storage_fp32,
                        int fixed, double gamma, hipStream_t s);
 hipError_t launch_to_f64(const float* v32, double* v64, const Ctl* ctl, int64_t n,

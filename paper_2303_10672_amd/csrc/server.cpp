@@ -365,7 +365,8 @@ pvi_status vi_batch_submit(pvi_server* S, pvi_mdp* const* mdps, const pvi_solve_
     std::memcpy(&oc, opts_in, std::min<size_t>(opts_in->struct_size, sizeof(pvi_solve_opts)));
     oc.struct_size = sizeof(pvi_solve_opts);
     const pvi_solve_opts* opts = &oc;
-    if (opts->stop_rule != PVI_STOP_SPAN && opts->stop_rule != PVI_STOP_SUPNORM)
+    if (opts->stop_rule != PVI_STOP_SPAN && opts->stop_rule != PVI_STOP_SUPNORM &&
+        opts->stop_rule != PVI_STOP_PERIODIC)
         return fail(PVI_E_INVALID, "vi_batch_submit: bad stop_rule");
     for (int i = 0; i < n; ++i) {
         if (!mdps[i]) return fail(PVI_E_INVALID, "vi_batch_submit: NULL handle");

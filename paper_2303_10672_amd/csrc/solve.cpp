@@ -19,6 +19,8 @@ size_t device_bytes(const pvi_mdp* p) {
     size_t b = ns * (2 * sizeof(double) + 2 * sizeof(float) + sizeof(int32_t) + sizeof(double));
     b += family_extra_bytes(p);
     b += 4 * sizeof(double) * (size_t)family_tiles(p) + sizeof(Ctl) + 4096;
+    // value tables the periodic stopping rule keeps beyond the two ping-pong ones
+    if (p->P > 1) b += sizeof(double) * ((size_t)(p->P - 1) * ns + 2 * kPeriodicBlocks);
     return b;
 }
 
@@ -33,6 +35,13 @@ void free_device(pvi_mdp* p) {
                     d.partials, d.ctl, d.pmf,   d.cdf,   d.tail, d.r0};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    for (double*& b : d.vring)
+        if (b) {
+            (void)hipFree(b);
+            b = nullptr;
+        }
+    if (d.pparts) (void)hipFree(d.pparts);
+    d.pparts = nullptr;
     family_free(p);
     if (d.h_ctl) (void)hipHostFree(d.h_ctl);
     for (auto e : d.ev) (void)hipEventDestroy(e);
@@ -119,6 +128,9 @@ struct Phase {
     int k0 = 4;          // sweeps in the first batch
     int kmax = 64;       // cap on sweeps per batch
     bool time = false;
+    int ring = 2;        // FP64 value tables cycled through (period + 1 for the periodic rule)
+    int period = 0;      // > 0: run the periodic test after every sweep from this many on
+    double gamma = 0.0, thr = 0.0;
 };
 
 struct PhaseOut {
@@ -127,6 +139,21 @@ struct PhaseOut {
     int timed = 0;
     bool stopped = false;
 };
+
+// FP64 value table of slot k: the two ping-pong tables, then the ring's extras.
+double* v64_slot(pvi_mdp* p, int k) { return k < 2 ? p->dev.v64[k] : p->dev.vring[k]; }
+
+pvi_status ensure_ring(pvi_mdp* p, int ring) {
+    auto& d = p->dev;
+    for (int k = 2; k < ring; ++k)
+        if (!d.vring[k] && hipMalloc((void**)&d.vring[k], sizeof(double) * (size_t)p->ns) !=
+                               hipSuccess)
+            return fail(PVI_E_NOMEM, "vi_solve: periodic-rule value tables do not fit");
+    if (!d.pparts &&
+        hipMalloc((void**)&d.pparts, sizeof(double) * 2 * kPeriodicBlocks) != hipSuccess)
+        return fail(PVI_E_NOMEM, "vi_solve: periodic-rule partials do not fit");
+    return PVI_OK;
+}
 
 pvi_status init_ctl(pvi_mdp* p, hipStream_t s, double thr, double c0, int rule) {
     Ctl h{};
@@ -158,8 +185,10 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
         const int n = std::min(k, limit - launched);
         const int before = d.h_ctl->sweeps;
         for (int i = 0; i < n; ++i) {
-            const void* vin = ph.fp32 ? (const void*)d.v32[launched & 1] : d.v64[launched & 1];
-            void* vout = ph.fp32 ? (void*)d.v32[(launched + 1) & 1] : d.v64[(launched + 1) & 1];
+            const void* vin = ph.fp32 ? (const void*)d.v32[launched & 1]
+                                      : v64_slot(p, launched % ph.ring);
+            void* vout = ph.fp32 ? (void*)d.v32[(launched + 1) & 1]
+                                 : v64_slot(p, (launched + 1) % ph.ring);
             if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i], s));
             PVI_HIP(family_backup(p, ph.fp32, ph.kahan, 0, ph.fixed > 0, vin, vout, s));
             if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i + 1], s));
@@ -167,6 +196,18 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
                 PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, ph.fp32 ? 1 : 0, ph.fixed > 0,
                                     p->d.gamma, s));
             ++launched;
+            if (ph.period > 0 && launched >= ph.period) {
+                // V_{i-j} for j = 0..P, i = launched (a sweep that was skipped after the
+                // stop flag leaves its table untouched, and so does this check)
+                PeriodicArgs a{};
+                for (int j = 0; j <= ph.period; ++j)
+                    a.v[j] = v64_slot(p, (launched - j) % ph.ring);
+                a.P = ph.period;
+                a.gamma = ph.gamma;
+                a.thr = ph.thr;
+                a.n = p->ns;
+                PVI_HIP(launch_periodic_check(d.ctl, a, d.pparts, s));
+            }
         }
         PVI_HIP(hipMemcpyAsync(d.h_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         PVI_HIP(hipStreamSynchronize(s));
@@ -230,7 +271,8 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
     pvi_solve_opts oc{};
     std::memcpy(&oc, opts_in, std::min<size_t>(opts_in->struct_size, sizeof(pvi_solve_opts)));
     const pvi_solve_opts* o = &oc;
-    if (o->stop_rule != PVI_STOP_SPAN && o->stop_rule != PVI_STOP_SUPNORM)
+    if (o->stop_rule != PVI_STOP_SPAN && o->stop_rule != PVI_STOP_SUPNORM &&
+        o->stop_rule != PVI_STOP_PERIODIC)
         return fail(PVI_E_INVALID, "vi_solve: bad stop_rule");
     if (o->precision < PVI_FP64 || o->precision > PVI_FP32_WIDE)
         return fail(PVI_E_INVALID, "vi_solve: bad precision");
@@ -246,7 +288,10 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
     auto& d = p->dev;
     hipStream_t s = o->stream ? (hipStream_t)o->stream : d.own;
     const double g = p->d.gamma;
-    const double thr = o->stop_rule == PVI_STOP_SUPNORM ? o->eps : o->eps * (1.0 - g) / g;
+    const double thr = o->stop_rule == PVI_STOP_SPAN ? o->eps * (1.0 - g) / g : o->eps;
+    const bool periodic = o->stop_rule == PVI_STOP_PERIODIC && o->fixed_sweeps <= 0;
+    const int period = p->P > 0 ? p->P : 1;
+    if (periodic && (st = ensure_ring(p, period + 1)) != PVI_OK) return st;
     const int max_sweeps = o->max_sweeps > 0 ? o->max_sweeps : o->fixed_sweeps;
     const int kmax = o->check_every > 0 ? o->check_every : 64;
     p->have_result = 0;
@@ -269,7 +314,9 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
         ph.fp32 = true;
         ph.kahan = kahan;
         ph.fixed = o->fixed_sweeps;
-        ph.max_sweeps = max_sweeps;
+        // under the periodic rule the test itself runs on FP64 sweeps and needs only
+        // about a cycle or two of them: the FP32 phase is a short warm start
+        ph.max_sweeps = periodic ? std::min(max_sweeps, 2 * period) : max_sweeps;
         ph.kmax = kmax;
         ph.time = o->time_kernels != 0;
         if ((st = run_phase(p, ph, s, o32)) != PVI_OK) return st;
@@ -284,13 +331,19 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
         ph.kmax = kmax;
         ph.k0 = fp32 ? 1 : 4;
         ph.time = o->time_kernels != 0;
+        if (periodic) {
+            ph.ring = period + 1;
+            ph.period = period;
+            ph.gamma = g;
+            ph.thr = thr;
+        }
         if ((st = run_phase(p, ph, s, o64)) != PVI_OK) return st;
-        p->ret_buf = o64.sweeps & 1;
+        p->ret_buf = o64.sweeps % ph.ring;
     } else {
         p->ret_buf = 0;
     }
     // policy and Q gap from one more FP64 backup of the returned V
-    PVI_HIP(family_backup(p, 0, 0, 1, 0, d.v64[p->ret_buf], nullptr, s));
+    PVI_HIP(family_backup(p, 0, 0, 1, 0, v64_slot(p, p->ret_buf), nullptr, s));
     PVI_HIP(hipStreamSynchronize(s));
     p->have_result = 1;
     const bool converged = o->fixed_sweeps > 0 || o64.stopped;
@@ -382,7 +435,7 @@ pvi_status value_get(const pvi_mdp* cp, double* v) {
         return PVI_OK;
     }
     PVI_HIP(hipSetDevice(p->dev.device));
-    PVI_HIP(hipMemcpy(v, p->dev.v64[p->ret_buf], sizeof(double) * p->ns, hipMemcpyDeviceToHost));
+    PVI_HIP(hipMemcpy(v, v64_slot(p, p->ret_buf), sizeof(double) * p->ns, hipMemcpyDeviceToHost));
     return PVI_OK;
 }
 

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGE
 FAMILY = {"A": 0, "B": 1, "C": 2}
 DEMAND = {"none": 0, "poisson": 1, "gamma": 2, "negbin": 3, "table": 4}
 ISSUING = {"fifo": 0, "lifo": 1}
-STOP_RULE = {"span": 0, "supnorm": 1}
+STOP_RULE = {"span": 0, "supnorm": 1, "periodic": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_wide": 2}
 MAX_PERIODS, MAX_LIFE = 7, 8
 
