@@ -77,6 +77,13 @@ def _load():
                                  P(ctypes.c_double), P(ctypes.c_double)]
         lib.or_transition.argtypes = [P(_OrMdp), ctypes.c_int64, ctypes.c_int32,
                                       P(ctypes.c_int32), P(ctypes.c_int64), P(ctypes.c_double)]
+        lib.or_philox4x64_10.argtypes = [P(ctypes.c_uint64), P(ctypes.c_uint64),
+                                         P(ctypes.c_uint64)]
+        lib.or_simulate.argtypes = [P(_OrMdp), ctypes.c_int32, P(ctypes.c_int32),
+                                    P(ctypes.c_int32), P(ctypes.c_double), ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_uint64, ctypes.c_int64, P(ctypes.c_double),
+                                    P(ctypes.c_double)]
         lib.or_arrival_prob.restype = ctypes.c_double
         lib.or_arrival_prob.argtypes = [P(_OrMdp), ctypes.c_int32, P(ctypes.c_int32)]
         _lib = lib
@@ -239,3 +246,44 @@ class Oracle:
                                _ip(pi), _dp(gap), _dp(st))
         return {"V": V, "pi": pi, "gap": gap, "sweeps": int(st[0]), "span": st[1],
                 "dmax": st[2], "dmin": st[3], "converged": rc == 0}
+
+    # rollouts --------------------------------------------------------------
+    def simulate(self, policy="table", table=None, params=None, n_rollouts=1000, warmup=100,
+                 horizon=365, seed=0, start=0):
+        """Rollouts of one tabulated policy or of several heuristic parameter vectors.
+
+        policy: "table" (table = action per state), "base_stock" (params rows [S]),
+        "mod_base_stock" ([S_0, S_1]) or "s_S" ([s_0, S_0, ..., s_6, S_6]).
+        Returns (ret [n_pol, n_rollouts], kpi [n_pol, n_rollouts, 3]) with the KPIs
+        service level %, wastage % and mean holding."""
+        kind = {"table": 0, "base_stock": 1, "mod_base_stock": 2, "s_S": 3}[policy]
+        if kind == 0:
+            tab = np.ascontiguousarray(table, dtype=np.int32)
+            assert tab.shape == (self.n_states,)
+            prm = None
+            n_pol = 1
+        else:
+            tab = None
+            rows = np.atleast_2d(np.asarray(params, dtype=np.int32))
+            prm = np.zeros((rows.shape[0], 16), dtype=np.int32)
+            prm[:, :rows.shape[1]] = rows
+            n_pol = rows.shape[0]
+        mu = np.array([float(self.sc["demand"][k]["mean"][0]) for k in range(2)])
+        ret = np.zeros((n_pol, n_rollouts))
+        kpi = np.zeros((n_pol, n_rollouts, 3))
+        null_i = ctypes.POINTER(ctypes.c_int32)()
+        self.lib.or_simulate(self.ref, kind, _ip(tab) if tab is not None else null_i,
+                             _ip(prm) if prm is not None else null_i, _dp(mu), n_pol,
+                             int(n_rollouts), int(warmup), int(horizon),
+                             ctypes.c_uint64(int(seed)), int(start), _dp(ret), _dp(kpi))
+        return ret, kpi
+
+
+def philox4x64_10(counter, key):
+    """Philox4x64-10 of one counter block (the oracle's generator, for its pins)."""
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    P = ctypes.POINTER(ctypes.c_uint64)
+    _load().or_philox4x64_10(c.ctypes.data_as(P), k.ctypes.data_as(P), out.ctypes.data_as(P))
+    return out

@@ -484,3 +484,235 @@ double or_arrival_prob(const or_mdp* p, int32_t a, const int32_t* y_desc) {
     for (int k = 1; k <= p->m; ++k) y[k] = y_desc[p->m - k];
     return multinom_pmf(p, a, y);
 }
+
+/* -------------------------------------------------------------- simulation */
+/*
+ * Rollouts of a policy (Simulation section: rollouts of warmup + horizon days from
+ * a start state; the return is the discounted sum of rewards from the end of the
+ * warm-up; KPIs are the service level, the wastage and the holding).
+ *
+ * Random numbers: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC 2011).  Draw w of block b on day t of rollout r
+ * is word w of Philox(counter = {r, t, b, 0}, key = {seed, 0}), mapped to
+ * u = (x >> 11) * 2^-53 in [0, 1).  Block 0 word 0 is the demand (product 0),
+ * word 1 the demand of product 1 (B).  Unit i of the day (C: remaining life of
+ * the i-th unit ordered; B: whether the i-th unmet customer of product 0 accepts
+ * product 1) uses block 1 + i/4, word i%4.  Rollouts of different policies see the
+ * same numbers.
+ *
+ * Sampling: the demand is the smallest d with u < CDF(d), CDF summed left to right
+ * over the PMF, and d_max when there is none; a unit's remaining life is the
+ * smallest k with u < p_1 + ... + p_k, and m when there is none; a customer
+ * accepts substitution when u < rho.
+ */
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+    unsigned __int128 p = (unsigned __int128)a * b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void or_philox4x64_10(const uint64_t* ctr, const uint64_t* key, uint64_t* out) {
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { /* Weyl sequence bump of the key between rounds */
+            k0 += 0x9E3779B97F4A7C15ULL;
+            k1 += 0xBB67AE8584CAA73BULL;
+        }
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(0xD2E7470EE14C6C93ULL, x0, &hi0, &lo0);
+        mulhilo64(0xCA5A826395121157ULL, x2, &hi1, &lo1);
+        uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static double unif(uint64_t x) { return (double)(x >> 11) * (1.0 / 9007199254740992.0); }
+
+/* word w of block b of day t of rollout r */
+static double draw(uint64_t seed, int64_t r, int t, int b, int w) {
+    uint64_t ctr[4] = {(uint64_t)r, (uint64_t)t, (uint64_t)b, 0};
+    uint64_t key[2] = {seed, 0};
+    uint64_t out[4];
+    or_philox4x64_10(ctr, key, out);
+    return unif(out[w]);
+}
+
+static int sample_pmf(const double* pmf, int dmax, double u) {
+    double cdf = 0.0;
+    for (int d = 0; d < dmax; ++d) {
+        cdf += pmf[d];
+        if (u < cdf) return d;
+    }
+    return dmax;
+}
+
+/* Heuristic and tabulated policies (Simulation optimization, per scenario):
+ *  kind 0: table[s];
+ *  kind 1: base stock (Scenario A): [S - I]^+, I = stock on hand and in transit;
+ *  kind 2: modified base stock (Scenario B), per product k with on-hand stock I_k,
+ *          oldest stock X1_k and mean demand mu_k: floor([S_k - I_k + [X1_k - mu_k]^+]^+);
+ *  kind 3: (s, S) per weekday (Scenario C): [S_tau - I]^+ when I <= s_tau and
+ *          s_tau < S_tau, else 0.
+ * Every order is capped at the maximum order quantity. */
+static int policy_action(const or_mdp* p, int kind, const int32_t* table,
+                         const int32_t* prm, const double* mu, int64_t s, const int32_t* dig) {
+    int nd = n_digits(p);
+    if (kind == 0) return table[s];
+    if (kind == 1) {
+        int I = 0;
+        for (int i = 0; i < nd; ++i) I += dig[i];
+        int a = ipos(prm[0] - I);
+        return a < p->a_max[0] ? a : p->a_max[0];
+    }
+    if (kind == 2) {
+        int m = p->m, q[2];
+        for (int k = 0; k < 2; ++k) {
+            int I = 0;
+            for (int j = 0; j < m - 1; ++j) I += dig[k * (m - 1) + j];
+            int x1 = dig[k * (m - 1) + (m - 2)]; /* life 1: last digit of the product */
+            double v = pos((double)prm[k] - I + pos((double)x1 - mu[k]));
+            int a = (int)floor(v);
+            q[k] = a < p->a_max[k] ? a : p->a_max[k];
+        }
+        return q[0] * (p->a_max[1] + 1) + q[1];
+    }
+    {
+        int tau = dig[0], I = 0;
+        for (int i = 1; i < nd; ++i) I += dig[i];
+        int s_lo = prm[2 * tau], S_hi = prm[2 * tau + 1];
+        if (!(s_lo < S_hi) || I > s_lo) return 0;
+        int a = ipos(S_hi - I);
+        return a < p->a_max[0] ? a : p->a_max[0];
+    }
+}
+
+typedef struct {
+    int64_t demand, met, expired, received, held;
+} or_counts;
+
+/* one day: sample the outcome, apply T, count the KPI quantities */
+static double sim_day(const or_mdp* p, uint64_t seed, int64_t r, int t, const int32_t* dig,
+                      int a, int32_t* nd, or_counts* c) {
+    double rew;
+    int m = p->m;
+    if (p->family == 0) {
+        int d = sample_pmf(p->pmf0, p->d_max[0], draw(seed, r, t, 0, 0));
+        trans_a(p, dig, a, d, nd, &rew);
+        int L = p->L, X[OR_MAXD + 1], tot = 0;
+        for (int j = 1; j <= m; ++j) tot += (X[j] = dig[(L - 1) + (m - j)]);
+        int met = d < tot ? d : tot, W;
+        if (p->issuing == 1) {
+            int above = tot - X[1];
+            W = ipos(X[1] - ipos(d - above));
+        } else {
+            W = ipos(X[1] - d);
+        }
+        c->demand += d;
+        c->met += met;
+        c->expired += W;
+        c->held += tot - met - W;
+        c->received += nd[L - 1]; /* X_m of the next state: the units that arrived */
+    } else if (p->family == 1) {
+        int nb = p->a_max[1] + 1, aA = a / nb, aB = a % nb;
+        int dA = sample_pmf(p->pmf0, p->d_max[0], draw(seed, r, t, 0, 0));
+        int dB = sample_pmf(p->pmf1, p->d_max[1], draw(seed, r, t, 0, 1));
+        int sA = aA, sB = aB;
+        for (int j = 0; j < m - 1; ++j) {
+            sA += dig[j];
+            sB += dig[(m - 1) + j];
+        }
+        int hA = dA < sA ? dA : sA, uA = dA - hA;
+        int k = 0;
+        for (int i = 0; i < uA; ++i)
+            if (draw(seed, r, t, 1 + i / 4, i % 4) < p->rho) ++k;
+        trans_b(p, dig, aA, aB, dA, dB, k, nd, &rew);
+        int hB = dB < sB ? dB : sB, hS = k < sB - hB ? k : sB - hB;
+        int keptA = 0, keptB = 0;
+        for (int j = 0; j < m - 1; ++j) {
+            keptA += nd[j];
+            keptB += nd[(m - 1) + j];
+        }
+        c->demand += dA + dB;
+        c->met += hA + hB + hS;
+        c->received += aA + aB;
+        c->held += keptA + keptB;
+        c->expired += (sA - hA - keptA) + (sB - hB - hS - keptB);
+    } else {
+        int d = sample_pmf(p->pmf0 + (size_t)dig[0] * (p->d_max[0] + 1), p->d_max[0],
+                           draw(seed, r, t, 0, 0));
+        int y[OR_MAXD + 1];
+        for (int k = 1; k <= m; ++k) y[k] = 0;
+        const double* pk = p->rul_p + (size_t)a * m;
+        for (int i = 0; i < a; ++i) {
+            double u = draw(seed, r, t, 1 + i / 4, i % 4), cum = 0.0;
+            int life = m;
+            for (int k = 1; k < m; ++k) {
+                cum += pk[k - 1];
+                if (u < cum) {
+                    life = k;
+                    break;
+                }
+            }
+            y[life]++;
+        }
+        trans_c(p, dig, a, y, d, nd, &rew);
+        int cap = p->a_max[0], tot = 0, before = 0, z1 = 0;
+        for (int j = 1; j <= m - 1; ++j) {
+            int x = dig[m - j], z = x + y[j] < cap ? x + y[j] : cap;
+            if (j == 1) z1 = z;
+            tot += z;
+            before += x;
+        }
+        tot += y[m];
+        c->demand += d;
+        c->met += d < tot ? d : tot;
+        c->expired += ipos(z1 - d);
+        c->held += ipos(tot - d); /* includes the units that expire tonight */
+        c->received += tot - before;
+    }
+    return rew;
+}
+
+/* n_pol policies (params: [n_pol][16]) x n_roll rollouts each.
+ * ret[p*n_roll + r] = sum_{t=warmup}^{warmup+horizon-1} gamma^(t-warmup) R_t;
+ * kpi[(p*n_roll + r)*3 + 0..2] = service level % (met/demand, 100 when no demand),
+ * wastage % (expired/received, 0 when nothing arrived), mean holding per day; all
+ * counted over the horizon days only. */
+int or_simulate(const or_mdp* p, int32_t kind, const int32_t* table, const int32_t* params,
+                const double* mu, int32_t n_pol, int32_t n_roll, int32_t warmup,
+                int32_t horizon, uint64_t seed, int64_t start, double* ret, double* kpi) {
+    int64_t total = (int64_t)n_pol * n_roll;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < total; ++i) {
+        int pol = (int)(i / n_roll);
+        int64_t r = i % n_roll;
+        const int32_t* prm = params ? params + (size_t)pol * 16 : NULL;
+        int32_t dig[OR_MAXD], nd[OR_MAXD];
+        int64_t s = start;
+        double g = 1.0, acc = 0.0;
+        or_counts c = {0, 0, 0, 0, 0};
+        for (int t = 0; t < warmup + horizon; ++t) {
+            or_decode(p, s, dig);
+            int a = policy_action(p, kind, table, prm, mu, s, dig);
+            or_counts day = {0, 0, 0, 0, 0};
+            double rew = sim_day(p, seed, r, t, dig, a, nd, &day);
+            if (t >= warmup) {
+                acc += g * rew;
+                g *= p->gamma;
+                c.demand += day.demand;
+                c.met += day.met;
+                c.expired += day.expired;
+                c.received += day.received;
+                c.held += day.held;
+            }
+            s = or_encode(p, nd);
+        }
+        ret[i] = acc;
+        kpi[3 * i + 0] = c.demand > 0 ? 100.0 * (double)c.met / (double)c.demand : 100.0;
+        kpi[3 * i + 1] = c.received > 0 ? 100.0 * (double)c.expired / (double)c.received : 0.0;
+        kpi[3 * i + 2] = horizon > 0 ? (double)c.held / (double)horizon : 0.0;
+    }
+    return 0;
+}

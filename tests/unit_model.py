@@ -79,6 +79,14 @@ def _serve_youngest(units, demand):
 
 def step(sc, s, a, omega):
     """One day of the unit model.  Returns (next state index, reward)."""
+    sn, rw, _ = day(sc, s, a, omega)
+    return sn, rw
+
+
+def day(sc, s, a, omega):
+    """One day of the unit model: (next state index, reward, counts), where counts
+    holds the day's demand, demand met, units expired, units received into stock and
+    units held at the end of the day (scenario C: including tonight's expiries)."""
     fam, m, L = sc["family"], sc["m"], sc["L"]
     c = sc["costs"]
     dig = decode(sc, s)
@@ -98,9 +106,12 @@ def step(sc, s, a, omega):
             arriving, new_pipeline = a, []
         else:
             arriving, new_pipeline = pipeline[-1], [a] + pipeline[:-1]
+        held = len(kept)
         kept += [m] * arriving
         counts = [sum(1 for u in kept if u == life) for life in range(m, 0, -1)]
-        return encode(sc, new_pipeline + counts), float(reward)
+        tally = {"demand": d, "met": issued, "expired": expired, "received": arriving,
+                 "held": held}
+        return encode(sc, new_pipeline + counts), float(reward), tally
     if fam == "B":
         nb = sc["a_max"][1] + 1
         aA, aB = a // nb, a % nb
@@ -117,7 +128,9 @@ def step(sc, s, a, omega):
         nB = [u - 1 for u in leftB if u > 1]
         dA_ = [sum(1 for u in nA if u == life) for life in range(m - 1, 0, -1)]
         dB_ = [sum(1 for u in nB if u == life) for life in range(m - 1, 0, -1)]
-        return encode(sc, dA_ + dB_), float(reward)
+        tally = {"demand": dA + dB, "met": hA + hB + hS, "received": aA + aB,
+                 "expired": sum(1 for u in leftA + leftB if u == 1), "held": len(nA) + len(nB)}
+        return encode(sc, dA_ + dB_), float(reward), tally
     # C
     cap = sc["a_max"][0]
     tau = dig[0]
@@ -136,7 +149,9 @@ def step(sc, s, a, omega):
               - c["short"] * short - c["waste"] * expired)
     kept = [u - 1 for u in left if u > 1]
     counts = [sum(1 for u in kept if u == life) for life in range(m - 1, 0, -1)]
-    return encode(sc, [(tau + 1) % sc["n_periods"]] + counts), float(reward)
+    tally = {"demand": d, "met": issued, "expired": expired, "held": len(left),
+             "received": sum(held.values()) - sum(stock.values())}
+    return encode(sc, [(tau + 1) % sc["n_periods"]] + counts), float(reward), tally
 
 
 def compositions(total, parts):
@@ -215,6 +230,6 @@ def c_omegas(sc, a):
             for y in compositions(a, sc["m"])]
 
 
-__all__ = ["radices", "encode", "decode", "n_states", "n_actions", "step", "outcomes",
+__all__ = ["radices", "encode", "decode", "n_states", "n_actions", "step", "day", "outcomes",
            "dense_model", "bellman", "compositions", "all_omegas", "c_omegas",
            "itertools"]

@@ -9,6 +9,10 @@ from .scenarios import (  # noqa: F401
     scenario_a,
     scenario_b,
     scenario_c,
+    scenario_a_paper,
+    PAPER_A_EXPERIMENTS,
+    scenario_c_paper,
+    PAPER_C_EXPERIMENTS,
     config0,
     config1,
     config2,

@@ -29,7 +29,9 @@ import copy
 import numpy as np
 
 __all__ = [
-    "scenario_a", "scenario_b", "scenario_c", "config0", "config1", "config2",
+    "scenario_a", "scenario_b", "scenario_c", "scenario_a_paper", "PAPER_A_EXPERIMENTS",
+    "scenario_c_paper", "PAPER_C_EXPERIMENTS",
+    "config0", "config1", "config2",
     "config3", "config_by_index", "serving_mix", "random_values", "sample_indices",
 ]
 
@@ -90,6 +92,55 @@ def scenario_c(m=3, a_max=4, d_max=8, n=None, means=None, c0=None, c1=None,
             "rul_c0": [float(x) for x in c0], "rul_c1": [float(x) for x in c1],
             "subst_rho": 0.0, "costs": copy.deepcopy(costs), "gamma": float(gamma),
             "eps": float(eps)}
+
+
+# Scenario A experiments of the paper's results table: (m, experiment, L, C_w, issuing).
+# Sizes follow from m and L: (A_max + 1)^(m + L - 1) states, 11 actions, 101 outcomes.
+PAPER_A_EXPERIMENTS = [
+    (m, e + 1, L, cw, iss)
+    for m in (2, 3, 4, 5)
+    for e, (L, cw, iss) in enumerate(
+        [(L, cw, iss) for L in (1, 2) for cw in (7.0, 10.0) for iss in ("lifo", "fifo")])
+]
+
+
+def scenario_a_paper(m, L, waste, issuing):
+    """Scenario A with the settings the paper fixes for all its experiments (Appendix A,
+    common-settings table): gamma demand with mean 4 and coefficient of variation 0.5,
+    truncated at 100; orders up to 10; C_v 3, C_s 5, C_h 1; gamma 0.99, eps 1e-4.  The
+    paper stops these solves with the sup-norm test."""
+    return scenario_a(m=m, L=L, a_max=10, d_max=100,
+                      demand={"kind": "gamma", "mean": [4.0], "cv": [0.5]},
+                      costs=_costs(var=(3.0, 0.0), hold=1.0, short=5.0, waste=waste),
+                      gamma=0.99, eps=1e-4, issuing=issuing)
+
+
+# Scenario C experiments of the paper's results table that fit in memory: m in {3, 5},
+# experiment 1 with remaining life on arrival independent of the order (exogenous),
+# experiment 2 with it depending on the order quantity (endogenous).  Logit
+# coefficients c_0^k, c_1^k for k = 2..m from the paper's useful-life table.
+PAPER_C_RUL = {
+    (3, 1): ([1.0, 0.5], [0.0, 0.0]),
+    (3, 2): ([1.0, 0.5], [0.4, 0.8]),
+    (5, 1): ([1.6, 2.6, 2.8, 1.6], [0.0, 0.0, 0.0, 0.0]),
+    (5, 2): ([1.9, 3.1, 3.1, 2.5], [-0.03, -0.06, -0.03, -0.09]),
+}
+PAPER_C_EXPERIMENTS = sorted(PAPER_C_RUL)
+# weekday negative-binomial demand, Monday (tau = 0) to Sunday: successes n, mean delta
+PAPER_C_DEMAND_N = [3.5, 11.0, 7.2, 11.1, 5.9, 5.5, 2.2]
+PAPER_C_DEMAND_MEAN = [5.7, 6.9, 6.5, 6.2, 5.8, 3.3, 3.4]
+
+
+def scenario_c_paper(m, exp):
+    """Scenario C with the settings the paper fixes for all its experiments (Appendix C
+    common-settings, weekday-demand and useful-life tables): demand truncated at 20,
+    orders and stock of each remaining life up to 20, C_f 10, C_h 1, C_s 20, C_w 5,
+    gamma 0.95, eps 1e-4.  The paper stops these solves with its periodic test."""
+    c0, c1 = PAPER_C_RUL[(m, exp)]
+    return scenario_c(m=m, a_max=20, d_max=20, n=PAPER_C_DEMAND_N,
+                      means=PAPER_C_DEMAND_MEAN, c0=[0.0] + list(c0), c1=[0.0] + list(c1),
+                      costs=_costs(fixed=10.0, hold=1.0, short=20.0, waste=5.0),
+                      gamma=0.95, eps=1e-4)
 
 
 def _jitter(rng, x, frac=0.2):
