@@ -40,11 +40,18 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="config1", choices=["config1", "batch", "serving",
-                                                               "config2", "config3"],
+                                                               "config2", "config3",
+                                                               "paper-a", "paper-c"],
                     help="config1 (default, the headline), batch (many small solves: "
                          "batched FP32 kernel vs one FP64 solve per call), serving (the "
-                         "request mix through the server), config2/config3 (one solve)")
+                         "request mix through the server), config2/config3 (one solve), paper-a / paper-c "
+                         "(the paper's scenario-A and scenario-C experiments, one solve "
+                         "each)")
     ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--paper-rules", action="store_true",
+                    help="serving: scenario-C requests stop by the periodic rule of "
+                         "Appendix C (the paper's test for C); otherwise every request "
+                         "uses the span rule")
     ap.add_argument("--prerun", type=int, default=200,
                     help="requests in the closed-loop pre-run that sets the saturated rate")
     ap.add_argument("--rate", type=float, default=0.0,
@@ -169,8 +176,13 @@ def bench_serving(args, pvi, W):
     # closed-loop pre-run on a prefix gives the saturated rate
     srv = pvi.Server(small_batch=args.batch)
     pre = scs[:min(args.prerun, len(scs))]
+
+    def rule(sc):
+        return "periodic" if args.paper_rules and sc["family"] == "C" else "span"
+
     t0 = time.perf_counter()
-    ts = [srv.submit([pvi.mdp_create(sc)], precision="fp32")[0] for sc in pre]
+    ts = [srv.submit([pvi.mdp_create(sc)], precision="fp32", stop_rule=rule(sc))[0]
+          for sc in pre]
     for i, t in enumerate(ts):
         srv.wait(t)
         if (i + 1) % 10 == 0 or i + 1 == len(ts):
@@ -191,7 +203,7 @@ def bench_serving(args, pvi, W):
             d = t_next - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            tickets[i] = srv.submit([m], precision="fp32")[0]
+            tickets[i] = srv.submit([m], precision="fp32", stop_rule=rule(scs[i]))[0]
             if (i + 1) % 20 == 0:
                 print(f"submitted: {i + 1}/{len(mdps)} requests", file=sys.stderr, flush=True)
 
@@ -223,7 +235,9 @@ def bench_serving(args, pvi, W):
         "config": {"workload": f"{len(mdps)} requests, exponential arrivals at {rate:.1f}/s "
                                "(0.7 x closed-loop rate unless given); 70% small A, 25% C "
                                "with order cap 10..20, 5% the m=4 L=2 A instance; FP32 "
-                               "schedule with FP64 check and polish"},
+                               "schedule with FP64 check and polish; stopping rule: "
+                               + ("periodic for C, span otherwise" if args.paper_rules
+                                  else "span")},
         "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"]},
         "per_class": per, "closed_loop_rate": sat, "completed_ok": ok,
     }
@@ -257,6 +271,81 @@ def bench_single(args, pvi, W, cfg):
     line = {"metric": METRIC, "value": max(o["backups_per_s"] for o in out.values()),
             "unit": "backups/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
             "config": {"workload": f"config {cfg} one solve"}, "detail": out}
+    print(json.dumps(line), flush=True)
+
+
+def bench_paper_a(args, pvi, W):
+    """The paper's 32 scenario-A experiments (Appendix A settings, sup-norm stop with
+    eps 1e-4): wall time of one full solve each, FP64 and the FP32 schedule, after one
+    untimed solve; mdp_create (host tables and upload) timed apart."""
+    out = []
+    for (mm, exp, L, cw, iss) in W.PAPER_A_EXPERIMENTS:
+        sc = W.scenario_a_paper(mm, L, cw, iss)
+        t0 = time.perf_counter()
+        m = pvi.mdp_create(sc)
+        create_ms = (time.perf_counter() - t0) * 1e3
+        row = {"m": mm, "exp": exp, "L": L, "c_waste": cw, "issuing": iss,
+               "states": m.n_states, "create_ms": create_ms}
+        for prec in ("fp64", "fp32_wide"):
+            pvi.vi_solve(m, precision=prec, eps=1e-4, stop_rule="supnorm")
+            t0 = time.perf_counter()
+            r = pvi.vi_solve(m, precision=prec, eps=1e-4, stop_rule="supnorm")
+            dt = time.perf_counter() - t0
+            row[prec] = {"solve_ms": dt * 1e3, "sweeps_fp32": r["sweeps_fp32"],
+                         "sweeps_fp64": r["sweeps_fp64"],
+                         "backups_per_s": r["logical_backups"] / dt}
+        pol, _ = pvi.policy_get(m)
+        row["V_empty"] = float(pvi.value_get(m)[0])
+        row["order_when_empty"] = int(pol[0])
+        print(f"m={mm} exp {exp}: {row['states']} states, fp64 "
+              f"{row['fp64']['solve_ms']:.1f} ms ({row['fp64']['sweeps_fp64']} sweeps), "
+              f"fp32_wide {row['fp32_wide']['solve_ms']:.1f} ms", file=sys.stderr, flush=True)
+        out.append(row)
+        del m
+    big = [r for r in out if r["states"] == max(x["states"] for x in out)]
+    line = {"metric": METRIC, "value": max(r["fp64"]["backups_per_s"] for r in big),
+            "unit": "backups/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "dtype": "f64",
+            "config": {"workload": "paper scenario-A experiments, sup-norm stop; value: "
+                                   "FP64 at 1,771,561 states"},
+            "total_solve_s_fp64": sum(r["fp64"]["solve_ms"] for r in out) / 1e3,
+            "total_solve_s_fp32_wide": sum(r["fp32_wide"]["solve_ms"] for r in out) / 1e3,
+            "detail": out}
+    print(json.dumps(line), flush=True)
+
+
+def bench_paper_c(args, pvi, W):
+    """The paper's scenario-C experiments that fit in memory (m = 3 and 5, remaining
+    life independent of or depending on the order), periodic stop of Appendix C:
+    wall time of one full solve each, FP64 and the FP32 schedule, after one untimed
+    solve."""
+    out = []
+    for (mm, exp) in W.PAPER_C_EXPERIMENTS:
+        sc = W.scenario_c_paper(mm, exp)
+        t0 = time.perf_counter()
+        m = pvi.mdp_create(sc)
+        row = {"m": mm, "exp": exp, "states": m.n_states,
+               "create_ms": (time.perf_counter() - t0) * 1e3}
+        for prec in ("fp64", "fp32"):
+            pvi.vi_solve(m, precision=prec, eps=1e-4, stop_rule="periodic")
+            t0 = time.perf_counter()
+            r = pvi.vi_solve(m, precision=prec, eps=1e-4, stop_rule="periodic",
+                             time_kernels=True)
+            dt = time.perf_counter() - t0
+            row[prec] = {"solve_ms": dt * 1e3, "sweeps_fp32": r["sweeps_fp32"],
+                         "sweeps_fp64": r["sweeps_fp64"],
+                         "backups_per_s": r["logical_backups"] / dt,
+                         "backup_ms": list(r["backup_ms"])}
+        print(f"C m={mm} exp {exp}: {row['states']} states, fp64 "
+              f"{row['fp64']['solve_ms']:.1f} ms ({row['fp64']['sweeps_fp64']} sweeps), fp32 "
+              f"{row['fp32']['solve_ms']:.1f} ms", file=sys.stderr, flush=True)
+        out.append(row)
+        del m
+    line = {"metric": METRIC, "value": max(r["fp64"]["backups_per_s"] for r in out),
+            "unit": "backups/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "dtype": "f64",
+            "config": {"workload": "paper scenario-C experiments (m 3 and 5), periodic stop"},
+            "detail": out}
     print(json.dumps(line), flush=True)
 
 
@@ -303,6 +392,10 @@ def main():
         return bench_serving(args, pvi, W)
     if args.workload in ("config2", "config3"):
         return bench_single(args, pvi, W, int(args.workload[-1]))
+    if args.workload == "paper-a":
+        return bench_paper_a(args, pvi, W)
+    if args.workload == "paper-c":
+        return bench_paper_c(args, pvi, W)
     if args.copy_calibration_mb > 0:
         n = args.copy_calibration_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

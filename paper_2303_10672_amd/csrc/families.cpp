@@ -96,6 +96,10 @@ static CDev make_cdev(const pvi_mdp* p) {
     c.u = d.cu;
     c.t0 = d.ct0;
     c.t1 = d.ct1;
+    c.tf = d.ctf;
+    c.exogenous = p->c_exogenous ? 1 : 0;
+    c.alim = R - 1;
+    c.top_only = 0;
     c.pmf = d.cpmf;
     c.cdf = d.ccdf;
     c.tail = d.ctail;
@@ -126,9 +130,6 @@ std::string family_support_msg(const pvi_mdp* p) {
         return "ok";
     }
     if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
-        if (!p->c_exogenous)
-            return "scenario C with order-dependent remaining life (rul_c1 != 0) has no GPU "
-                   "kernel";
         if (p->m > 9) return "scenario C needs m <= 9 on the GPU";
         const size_t lds = sizeof(double) * ((size_t)p->c_lpmax + 3 * (size_t)p->c_tab);
         if (lds > 65536) return "scenario C demand table exceeds LDS";
@@ -162,7 +163,8 @@ size_t family_extra_bytes(const pvi_mdp* p) {
     if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
         const size_t ut = (size_t)p->ns * p->rad[0];
         const size_t tt = p->m >= 3 ? c_table_entries(p) : 0;
-        return sizeof(double) * (ut + 2 * tt + 3 * p->c_pmf.size() + p->c_r0.size() +
+        const size_t ntab = p->c_exogenous ? 2 : 3;
+        return sizeof(double) * (ut + ntab * tt + 3 * p->c_pmf.size() + p->c_r0.size() +
                                  p->c_binq.size() + p->c_binm.size());
     }
     return 0;
@@ -196,6 +198,7 @@ pvi_status family_init(pvi_mdp* p) {
         if (hipMalloc(&d.cu, sizeof(double) * ut) != hipSuccess ||
             hipMalloc(&d.ct0, sizeof(double) * tt) != hipSuccess ||
             hipMalloc(&d.ct1, sizeof(double) * tt) != hipSuccess ||
+            (!p->c_exogenous && hipMalloc(&d.ctf, sizeof(double) * tt) != hipSuccess) ||
             upload_vec(&d.cpmf, p->c_pmf) != hipSuccess ||
             upload_vec(&d.ccdf, p->c_cdf) != hipSuccess ||
             upload_vec(&d.ctail, p->c_tail) != hipSuccess ||
@@ -214,11 +217,11 @@ void family_free(pvi_mdp* p) {
     auto& d = p->dev;
     void* bufs[] = {d.z,    d.rexp0, d.epmf,  d.ecdf,  d.etail, d.rexp1, d.cu,  d.ct0,
                     d.ct1,  d.cpmf,  d.ccdf,  d.ctail, d.cr0,   d.cbinq,  d.cbinm, d.cpy,
-                    d.cpr,  d.cpb, d.agroups};
+                    d.cpr,  d.cpb, d.agroups, d.ctf};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     d.z = d.rexp0 = d.epmf = d.ecdf = d.etail = d.rexp1 = nullptr;
-    d.cu = d.ct0 = d.ct1 = nullptr;
+    d.cu = d.ct0 = d.ct1 = d.ctf = nullptr;
     d.cpmf = d.ccdf = d.ctail = d.cr0 = d.cbinq = d.cbinm = nullptr;
     d.cpy = d.cpr = d.cpb = nullptr;
     d.agroups = nullptr;

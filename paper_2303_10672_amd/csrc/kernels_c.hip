@@ -20,9 +20,12 @@
 //              T_j(.., x_j, ..; r)   = sum_y Bin(y; r, q_j) T_{j-1}(.., c(x_j+y), ..; r-y)
 //              Q(tau, x, a) = -C_f[a>0] + sum_y Bin(y; a, p_m) T_{m-1}(tau, y, x; a-y)
 //            where c(.) caps at a_max and r counts units still to place.
-// The remaining-life probabilities must not depend on the order size here
-// (exogenous case).  T tables are laid out [tau][(y_m, r) pair][x digits] so
-// consecutive lanes touch consecutive addresses.
+// When the remaining-life probabilities depend on the order size (the endogenous
+// case, c_1 != 0), every q_j and p_m depends on a, so the merge chain runs once per
+// order a with that a's factors, over the rows y_m + r <= a only; its top level
+// keeps just the row r = a - y_m that the final sum for a reads, in a table of
+// its own.  T tables are laid out [tau][(y_m, r) pair][x digits] so consecutive
+// lanes touch consecutive addresses.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -121,7 +124,8 @@ __global__ __launch_bounds__(1024) void c_merge2_kernel(CDev p, const void* in_,
     const int R = p.R, tid = threadIdx.x;
     const int tym = blockIdx.y, tau = tym / R, ym = tym - tau * R;
     const int64_t hi = blockIdx.x;  // digits 3..m-1
-    const int nr = R - ym;          // r = 0 .. a_max - y_m
+    const int nr = min(R - ym, p.alim - ym + 1);  // r = 0 .. min(a_max, alim) - y_m
+    if (nr <= 0) return;
     const VT* U = reinterpret_cast<const VT*>(in_) + ((int64_t)tau * R + ym) * p.nblk + hi * R * R;
     for (int i = tid; i < R * R; i += blockDim.x) {
         slab[i] = (double)U[i];
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(1024) void c_merge2_kernel(CDev p, const void* in_,
     const int x2 = tid / R, x1 = tid - x2 * R;
     VT* T = reinterpret_cast<VT*>(out_);
     const int64_t row0 = (int64_t)tau * p.npair + p.pair_base[ym];
-    for (int r = 0; r < nr; ++r) {
+    for (int r = p.top_only ? nr - 1 : 0; r < nr; ++r) {
         double acc = 0.0;
         for (int y = 0; y <= r; ++y)
             acc = fma(bq[r * R + y], slab[min(x2 + y, R - 1) * R + min(x1 + r - y, R - 1)], acc);
@@ -166,7 +170,8 @@ __global__ __launch_bounds__(1024) void c_merge_kernel(CDev p, int j, const void
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
     const int tym = lid / nx, tau = tym / R, ym = tym - tau * R;
     const int xb = lid - tym * nx;
-    const int nr = R - ym;
+    const int nr = min(R - ym, p.alim - ym + 1);
+    if (nr <= 0) return;
     const int hi = xb / nlob;
     const int lo0 = (xb - hi * nlob) * LB;
     const int64_t base = (int64_t)hi * nlo * R + lo0;  // digits above j, digit j = 0, lo0
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(1024) void c_merge_kernel(CDev p, int j, const void
 #pragma unroll
     for (int y = 0; y < RC; ++y) adj[y] = min(xz + y, R - 1) * LB + l - y * rstride;
     VT* out = reinterpret_cast<VT*>(out_) + row0 * p.nblk + base + (int64_t)xz * nlo + l;
-    for (int r = 0; r < nr; ++r) {
+    for (int r = p.top_only ? nr - 1 : 0; r < nr; ++r) {
         const VT* sr = slab + r * rstride;
         const double* w = bq + r * R;
         double acc = 0.0;
@@ -264,6 +269,12 @@ __global__ __launch_bounds__(256) void c_final_kernel(CDev p, const void* tin) {
     }
 }
 
+template <typename VT>
+static hipError_t launch_c_chain(const CDev& p, void* top, hipStream_t s);
+template <typename VT>
+static hipError_t launch_merge_lb(const CDev& p, int j, const void* in, void* out, int lb,
+                                  dim3 grid, int threads, size_t lds, hipStream_t s);
+
 template <typename VT, bool EXTRACT>
 static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
     const size_t ubytes = sizeof(double) * ((size_t)p.lpmax + 3 * (size_t)p.tab);
@@ -276,14 +287,42 @@ static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned gx = (unsigned)((p.nblk + 255) / 256);
+    const void* tin = p.u;
+    if (p.m >= 3 && p.exogenous) {
+        if ((e = launch_c_chain<VT>(p, p.t1 /* level m-1 output */, s)) != hipSuccess) return e;
+        tin = ((p.m - 1) & 1) ? p.t1 : p.t0;
+    } else if (p.m >= 3) {
+        for (int a = 0; a < p.R; ++a) {
+            CDev q = p;
+            q.binq = p.binq + (size_t)a * p.m * p.R * p.R;
+            q.alim = a;
+            if ((e = launch_c_chain<VT>(q, p.tf, s)) != hipSuccess) return e;
+        }
+        tin = p.tf;
+    }
+    hipLaunchKernelGGL((c_final_kernel<VT, EXTRACT>), dim3(gx, p.P), dim3(256), 0, s, p, tin);
+    return hipGetLastError();
+}
+
+// The merges of life classes 2 .. m-1 from U.  Levels alternate between the two
+// ping-pong tables; in the order-dependent case (alim < a_max possible) the top
+// level writes only its row r = alim - y_m, into `top`.
+template <typename VT>
+static hipError_t launch_c_chain(const CDev& p, void* top, hipStream_t s) {
+    hipError_t e = hipSuccess;
     const void* in = p.u;
     void* bufs[2] = {p.t0, p.t1};
     for (int j = 2; j <= p.m - 1; ++j) {
+        CDev q = p;
         void* out = bufs[j & 1];
+        if (!p.exogenous && j == p.m - 1) {
+            q.top_only = 1;
+            out = top;
+        }
         if (j == 2) {
             const int threads = ((p.R * p.R + 63) / 64) * 64;
             hipLaunchKernelGGL((c_merge2_kernel<VT>), dim3((unsigned)(p.nblk / (p.R * p.R)), p.P * p.R),
-                               dim3(threads), 0, s, p, in, out);
+                               dim3(threads), 0, s, q, in, out);
         } else {
             // the widest block of low digits (up to 64 bytes per slab row) whose slab
             // stays within 32 KB of LDS, so several workgroups share a CU
@@ -303,14 +342,14 @@ static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
                 return hipErrorInvalidConfiguration;
             const dim3 grid((unsigned)nwg);
             const size_t lds = lds_for(lb);
-            if ((e = launch_merge_lb<VT>(p, j, in, out, lb, grid, threads, lds, s)) != hipSuccess)
+            if ((e = launch_merge_lb<VT>(q, j, in, out, lb, grid, threads, lds, s)) != hipSuccess)
                 return e;
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         in = out;
     }
-    hipLaunchKernelGGL((c_final_kernel<VT, EXTRACT>), dim3(gx, p.P), dim3(256), 0, s, p, in);
-    return hipGetLastError();
+    (void)top;
+    return hipSuccess;
 }
 
 template <typename VT, int LB>

@@ -274,19 +274,27 @@ static void build_c_tables(pvi_mdp* p) {
                 p->c_r0[((size_t)t * R + z1) * p->c_xt + Z] = e;
             }
     }
-    // life probabilities (order-size independent in the exogenous case: row a = 0)
-    const double* pk = p->life.data();
-    p->c_binq.assign((size_t)m * R * R, 0.0);
-    double cum = pk[0];
-    for (int j = 2; j <= m - 1; ++j) {
-        cum += pk[j - 1];
-        const double q = cum > 0.0 ? pk[j - 1] / cum : 0.0;
-        for (int r = 0; r < R; ++r)
-            for (int y = 0; y <= r; ++y) p->c_binq[((size_t)j * R + r) * R + y] = binom_pmf(y, r, q);
+    // Binomial factors of the remaining-life multinomial.  Exogenous: one set
+    // [m][R][R] from p_k(0).  Order-dependent: one set per order a, [a][m][R][R],
+    // from p_k(a).  Row a of binm always uses p_m(a).
+    const int nsets = p->c_exogenous ? 1 : R;
+    p->c_binq.assign((size_t)nsets * m * R * R, 0.0);
+    for (int a = 0; a < nsets; ++a) {
+        const double* pk = p->life.data() + (size_t)a * m;
+        double* bq = p->c_binq.data() + (size_t)a * m * R * R;
+        double cum = pk[0];
+        for (int j = 2; j <= m - 1; ++j) {
+            cum += pk[j - 1];
+            const double q = cum > 0.0 ? pk[j - 1] / cum : 0.0;
+            for (int r = 0; r < R; ++r)
+                for (int y = 0; y <= r; ++y) bq[((size_t)j * R + r) * R + y] = binom_pmf(y, r, q);
+        }
     }
     p->c_binm.assign((size_t)R * R, 0.0);
-    for (int a = 0; a < R; ++a)
-        for (int y = 0; y <= a; ++y) p->c_binm[(size_t)a * R + y] = binom_pmf(y, a, pk[m - 1]);
+    for (int a = 0; a < R; ++a) {
+        const double pm = p->life[(size_t)(p->c_exogenous ? 0 : a) * m + (m - 1)];
+        for (int y = 0; y <= a; ++y) p->c_binm[(size_t)a * R + y] = binom_pmf(y, a, pm);
+    }
     p->c_pair_y.clear();
     p->c_pair_r.clear();
     p->c_pair_base.assign(R, 0);
@@ -316,10 +324,19 @@ static void build_c_tables(pvi_mdp* p) {
                 const int N = (int)b + z2;
                 exu += cnt[b] * ((N == 0 ? 0 : std::max(0, std::min(N, dm - z1))) + 1);
             }
-    int64_t pair_terms = 0;
-    for (int i = 0; i < p->c_npair; ++i) pair_terms += p->c_pair_r[i] + 1;
+    int64_t merge_terms = 0;  // over all merge levels, per state block
+    if (p->c_exogenous) {
+        for (int i = 0; i < p->c_npair; ++i) merge_terms += (int64_t)(m - 2) * (p->c_pair_r[i] + 1);
+    } else if (m >= 3) {
+        // per order a: rows y_m + r <= a at the lower levels, r = a - y_m at the top
+        for (int a = 0; a < R; ++a)
+            for (int ym = 0; ym <= a; ++ym) {
+                for (int r = 0; r <= a - ym; ++r) merge_terms += (int64_t)(m - 3) * (r + 1);
+                merge_terms += a - ym + 1;
+            }
+    }
     const int64_t final_terms = (int64_t)R * (R + 1) / 2;
-    p->executed_per_sweep = P * (exu + (int64_t)(m - 2) * pair_terms * nblk + final_terms * nblk);
+    p->executed_per_sweep = P * (exu + merge_terms * nblk + final_terms * nblk);
     // logical: every (d, y) outcome of every (state, order): (d_max+1) C(a+m-1, m-1)
     int64_t comps = 0;
     for (int a = 0; a < R; ++a) {

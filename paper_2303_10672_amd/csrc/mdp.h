@@ -63,7 +63,7 @@ struct pvi_mdp {
         int32_t* agroups = nullptr;
         double *z = nullptr, *rexp0 = nullptr, *epmf = nullptr, *ecdf = nullptr,
                *etail = nullptr, *rexp1 = nullptr;
-        void *cu = nullptr, *ct0 = nullptr, *ct1 = nullptr;
+        void *cu = nullptr, *ct0 = nullptr, *ct1 = nullptr, *ctf = nullptr;
         double *cpmf = nullptr, *ccdf = nullptr, *ctail = nullptr, *cr0 = nullptr,
                *cbinq = nullptr, *cbinm = nullptr;
         int32_t *cpy = nullptr, *cpr = nullptr, *cpb = nullptr;

@@ -69,12 +69,53 @@ def test_converged(sc):
     assert np.array_equal(pol[clear], tight["pi"][clear])
 
 
-def test_endogenous_life_is_rejected_loudly():
-    sc = W.scenario_c(m=3, a_max=4, d_max=8, c1=[0.0, 0.1, -0.1])
+# remaining life on arrival that depends on the order size (c_1 != 0): one merge
+# chain per order size on the GPU
+ENDO = [
+    W.scenario_c(m=3, a_max=4, d_max=8, c1=[0.0, 0.1, -0.1]),
+    W.scenario_c(m=2, a_max=5, d_max=7, n_periods=2, means=[3.0, 4.0], n=[5.0, 5.0],
+                 c0=[0.0, 1.0], c1=[0.0, -0.3]),
+    W.scenario_c(m=4, a_max=3, d_max=6, n_periods=3, means=[2.0, 3.0, 2.5], n=[4.0, 5.0, 3.0],
+                 c0=[0.0, 0.5, 1.0, 2.0], c1=[0.0, 0.4, -0.2, 0.3]),
+    W.scenario_c(m=5, a_max=3, d_max=5, n_periods=2, means=[2.0, 2.5], n=[5.0, 4.0],
+                 c0=[0.0, 1.9, 3.1, 3.1, 2.5], c1=[0.0, -0.03, -0.06, -0.03, -0.09]),
+    W.scenario_c(m=3, a_max=9, d_max=12, n_periods=7, c0=[0.0, 1.0, 0.5], c1=[0.0, 0.4, 0.8]),
+]
+ENDO_IDS = ["m3", "m2-P2", "m4-P3", "m5-P2", "m3-R10"]
+
+
+@pytest.mark.parametrize("sc", ENDO, ids=ENDO_IDS)
+def test_endogenous_one_backup(sc):
+    o = Oracle(sc)
     m = pvi.mdp_create(sc)
-    with pytest.raises(pvi.PviError) as e:
-        pvi.vi_solve(m)
-    assert e.value.status == pvi.PVI_E_INVALID
+    for seed in (31, 32):
+        V = W.random_values(o.n_states, seed=seed, scale=20.0, offset=-300.0)
+        Vo, pio, gapo = o.sweep(V)
+        Vg, pig, gapg = pvi.vi_backup(m, V, "fp64")
+        assert relerr(Vg, Vo) < 1e-12
+        clear = gapo > 1e-9
+        assert np.array_equal(pig[clear], pio[clear])
+        assert np.allclose(gapg[clear], gapo[clear], rtol=1e-8, atol=1e-9)
+        V32, _, _ = pvi.vi_backup(m, V, "fp32")
+        assert relerr(V32, Vo) < 1e-6
+
+
+@pytest.mark.parametrize("sc", ENDO, ids=ENDO_IDS)
+def test_endogenous_converged(sc):
+    o = Oracle(sc)
+    ref = o.solve()
+    tight = o.solve(thr=1e-11)
+    m = pvi.mdp_create(sc)
+    res = pvi.vi_solve(m, precision="fp64")
+    assert res["sweeps_fp64"] == ref["sweeps"]
+    assert relerr(pvi.value_get(m), ref["V"]) < 1e-12
+    pol, _ = pvi.policy_get(m)
+    clear = tight["gap"] > 1e-6
+    assert np.array_equal(pol[clear], tight["pi"][clear])
+    g = sc["gamma"]
+    res = pvi.vi_solve(m, precision="fp32")
+    assert res["final_span"] < res["threshold"]
+    assert relerr(vhat(pvi.value_get(m), res, g), vhat(ref["V"], ref, g)) < 1e-5
 
 
 @pytest.fixture(scope="module")
