@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="config1", choices=["config1", "batch", "serving",
                                                                "config2", "config3",
-                                                               "paper-a", "paper-c"],
+                                                               "paper-a", "paper-c", "rollouts"],
                     help="config1 (default, the headline), batch (many small solves: "
                          "batched FP32 kernel vs one FP64 solve per call), serving (the "
                          "request mix through the server), config2/config3 (one solve), paper-a / paper-c "
@@ -349,6 +349,49 @@ def bench_paper_c(args, pvi, W):
     print(json.dumps(line), flush=True)
 
 
+def bench_rollouts(args, pvi, W):
+    """Policy evaluation and simulation optimization on the GPU (Simulation section):
+    10,000 rollouts of 100 + 365 days of the solved policy of the paper's largest
+    scenario-A and scenario-C runs, and heuristic grids over the same rollouts."""
+    import numpy as np
+    import torch
+    runs = []
+    cases = [
+        ("A m=5 L=2 FIFO C_w=7 (1,771,561 states)", W.scenario_a_paper(5, 2, 7.0, "fifo"),
+         "supnorm", "base_stock", [[S] for S in range(11)]),
+        ("C m=5 exp 1 (1,361,367 states)", W.scenario_c_paper(5, 1), "periodic", "s_S",
+         [[lo, hi] * 7 for lo in range(0, 21, 2) for hi in range(lo + 1, 21, 2)]),
+        ("B two products (config 2 shape, 50,625 states)", W.config2(), "span",
+         "mod_base_stock", [[a, b] for a in range(0, 29) for b in range(0, 29)]),
+    ]
+    for label, sc, rule, kind, grid in cases:
+        m = pvi.mdp_create(sc)
+        pvi.vi_solve(m, precision="fp64", eps=sc["eps"], stop_rule=rule)
+        row = {"workload": label}
+        for what, kw in (("vi_policy", {}), (kind + "_grid", {"policy": kind, "params": grid})):
+            pvi.policy_rollouts(m, n_rollouts=1000, per_rollout=False, **kw)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = pvi.policy_rollouts(m, n_rollouts=10000, per_rollout=False, **kw)
+            dt = time.perf_counter() - t0
+            npol = r["stats"].shape[0]
+            best = int(np.argmax(r["stats"][:, 0]))
+            row[what] = {"policies": npol, "ms": dt * 1e3,
+                         "rollout_days_per_s": npol * 10000 * 465 / dt,
+                         "best_policy": best, "best_mean_return": float(r["stats"][best, 0]),
+                         "best_return_sd": float(r["stats"][best, 1])}
+            print(f"{label} {what}: {npol} x 10000 rollouts in {dt * 1e3:.1f} ms",
+                  file=sys.stderr, flush=True)
+        runs.append(row)
+        del m
+    line = {"metric": "rollout days per second (10,000 rollouts of 465 days per policy)",
+            "value": max(r[k]["rollout_days_per_s"] for r in runs for k in r if k != "workload"),
+            "unit": "rollout-days/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "policy rollouts and heuristic grids"},
+            "detail": runs}
+    print(json.dumps(line), flush=True)
+
+
 TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                "backup_a_kernel_m4L2_hbm_traffic.md")
 KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2303_10672_amd",
@@ -396,6 +439,8 @@ def main():
         return bench_paper_a(args, pvi, W)
     if args.workload == "paper-c":
         return bench_paper_c(args, pvi, W)
+    if args.workload == "rollouts":
+        return bench_rollouts(args, pvi, W)
     if args.copy_calibration_mb > 0:
         n = args.copy_calibration_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -226,7 +226,9 @@ pvi_status policy_get_device(const pvi_mdp* mdp, int32_t* d_policy, void* stream
  * within hbm_budget_bytes (0 = 80% of free device memory).  Small scenario-A
  * instances are batched, up to small_batch per persistent launch.  Each ticket's
  * results stay in its pvi_mdp handle, which the caller keeps alive until the
- * ticket completes. */
+ * ticket completes.  A handle that had no device state when its request started
+ * gets its results in host memory and its device buffers freed once the solve
+ * ends (policy_get, value_get and policy_get_device read them from there). */
 pvi_status pvi_server_create(int64_t hbm_budget_bytes, int32_t small_batch,
                              pvi_server** out);
 pvi_status pvi_server_destroy(pvi_server* server);
@@ -238,6 +240,80 @@ pvi_status vi_wait(pvi_server* server, uint64_t ticket, int64_t timeout_us,
 /* Latency statistics over completed tickets (milliseconds, submit to done). */
 pvi_status pvi_server_stats(pvi_server* server, double* p50_ms, double* p99_ms,
                             int64_t* completed);
+
+/* ------------------------------------------------------------------ rollouts
+ * Policy evaluation by simulation (Simulation section): n_rollouts rollouts of
+ * warmup_days + horizon_days days from start_state under each policy; the return
+ * of a rollout is sum_{t < horizon} gamma^t R_{warmup + t}, and its KPIs, counted
+ * over the horizon days, are the service level (100 x demand met / demand, 100
+ * with no demand; scenario B counts demand of product 0 met by product 1 as met),
+ * the wastage (100 x units expired / units received into stock, 0 with none
+ * received) and the holding (units in stock at the end of the day, per day; the
+ * units that expire that night count in scenario C and not in A or B).
+ *
+ * Randomness: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC 2011), key (seed, 0), counter (rollout, day,
+ * block, 0); word w maps to u = (x >> 11) 2^-53.  Block 0 word 0 draws the demand
+ * of product 0 (the smallest d with u < CDF(d), else d_max), word 1 that of
+ * product 1; unit i of the day uses word i%4 of block 1 + i/4: in scenario C the
+ * remaining life of the i-th unit ordered (the smallest k with u < p_1(a) + ... +
+ * p_k(a), else m), in scenario B whether the i-th unmet customer of product 0
+ * accepts product 1 (u < subst_rho).  Every policy of a call sees the same
+ * numbers.
+ *
+ * Policies (Simulation optimization of each scenario):
+ *   TABLE           action per state: `table` (host, n_states entries in
+ *                   [0, n_actions)), or NULL for the policy of the handle's last
+ *                   solve; n_policies = 1.
+ *   BASE_STOCK      scenario A: order [S - I]^+, I = stock on hand and in transit;
+ *                   params[0] = S.
+ *   MOD_BASE_STOCK  scenario B: per product k, floor([S_k - I_k + [X1_k - mu_k]^+]^+)
+ *                   with I_k its stock, X1_k its oldest stock and mu_k its mean
+ *                   demand; params[0..1] = S_0, S_1.
+ *   S_S             scenario C: [S_tau - I]^+ when I <= s_tau and s_tau < S_tau,
+ *                   else 0, for weekday tau; params[2 tau] = s_tau,
+ *                   params[2 tau + 1] = S_tau.
+ * Every order is capped at a_max. */
+typedef enum {
+    PVI_POLICY_TABLE = 0,
+    PVI_POLICY_BASE_STOCK = 1,
+    PVI_POLICY_MOD_BASE_STOCK = 2,
+    PVI_POLICY_S_S = 3
+} pvi_policy_kind;
+
+#define PVI_POLICY_PARAMS 16
+
+typedef struct pvi_rollout_opts {
+    uint32_t struct_size;      /* sizeof(pvi_rollout_opts) */
+    int32_t kind;              /* pvi_policy_kind; must suit the handle's family */
+    const int32_t* table;      /* TABLE: host [n_states], or NULL (last solved policy) */
+    const int32_t* params;     /* heuristics: host [n_policies][PVI_POLICY_PARAMS] */
+    int32_t n_policies;        /* >= 1 (TABLE: 1) */
+    int32_t n_rollouts;        /* >= 1; n_policies x n_rollouts < 2^31 */
+    int32_t warmup_days;       /* >= 0 */
+    int32_t horizon_days;      /* >= 1 */
+    uint64_t seed;
+    int64_t start_state;       /* state index at day 0, 0 = empty */
+    void* stream;              /* optional hipStream_t; NULL = a stream of the call */
+} pvi_rollout_opts;
+
+/* Run the rollouts on the device and return, per policy, stats[8 p .. 8 p + 7] =
+ * mean and sample standard deviation (n - 1) of the return, the service level,
+ * the wastage and the holding.  returns ([n_policies][n_rollouts]) and kpis
+ * ([n_policies][n_rollouts][3]: service, wastage, holding) are optional host
+ * outputs (NULL to skip).  Blocks until done.  Errors: PVI_E_INVALID (options,
+ * a kind that does not suit the family, table entries out of range),
+ * PVI_E_NOT_READY (TABLE with NULL table before any solve), PVI_E_NOMEM,
+ * PVI_E_DEVICE.  Device buffers are taken and released within the call. */
+pvi_status policy_rollouts(pvi_mdp* mdp, const pvi_rollout_opts* opts, double* stats,
+                           double* returns, double* kpis);
+
+/* Simulation optimization over a grid of heuristic parameter vectors (a
+ * heuristic kind, n_policies candidates, common random numbers): the rollouts of
+ * policy_rollouts, then *best = the candidate with the highest mean return, ties
+ * to the lowest index.  stats as for policy_rollouts (may be NULL). */
+pvi_status heuristic_search(pvi_mdp* mdp, const pvi_rollout_opts* opts, double* stats,
+                            int32_t* best);
 
 /* Thread-local message of the last failing call on this thread. */
 const char* pvi_last_error(void);

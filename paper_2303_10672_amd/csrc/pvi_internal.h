@@ -104,21 +104,49 @@ struct CDev {
     void* u;              // U[tau][z_m][z_{m-1}..z_1]
     void* t0;             // merge ping-pong tables [tau][(y_m, r)][digits]
     void* t1;
+    void* tf;             // order-dependent life: top-level rows r = a - y_m of every a
     const double* pmf;    // [P][tab] per-weekday demand, zero past d_max
     const double* cdf;    // [P][tab], one past d_max
     const double* tail;   // [P][tab], zero past d_max
     const double* r0;     // [P][R][xt] expected one-day reward of post-arrival stock
-    const double* binq;   // [m][R][R] Bin(y; r, q_j)
-    const double* binm;   // [R][R] Bin(y; a, p_m)
+    const double* binq;   // [m][R][R] Bin(y; r, q_j) (for one order size a when the
+                          // life distribution depends on it)
+    const double* binm;   // [R][R] Bin(y; a, p_m(a))
     const int32_t* pair_y;
     const int32_t* pair_r;
     const int32_t* pair_base;
     Ctl* ctl;
     int64_t nblk;         // R^(m-1) states per weekday
     int32_t R, m, P, nzu, npair, tab, xt, lpmax, dmax, extract;
+    int32_t exogenous;    // 0: one merge chain per order size a
+    int32_t alim;         // merges compute rows with y_m + r <= alim
+    int32_t top_only;     // and, when set, only the row r = alim - y_m
     int32_t pow_r[10];
     double gamma, cfixed;
 };
+
+// ------------------------------------------------------------------ rollouts
+struct SimDev {
+    int32_t family, m, L, P, kind, issuing;
+    int32_t R0, R1;            // a_max + 1 of product 0 and 1
+    int32_t dmax0, dmax1;
+    int32_t n_pol, n_roll, warmup, horizon;
+    int32_t n_cdf0, n_cdf1, n_lcum;  // entries of the three staged tables
+    int64_t start;             // start state index
+    uint64_t seed;
+    double gamma, rho, mu0, mu1;
+    double cvar0, cvar1, cfixed, chold, cshort, cwaste, rev0, rev1;
+    const int32_t* table;      // TABLE: action per state
+    const int32_t* params;     // heuristics: [n_pol][PVI_POLICY_PARAMS]
+    const double* cdf0;        // [P][dmax0 + 1] demand CDF of product 0, summed left to right
+    const double* cdf1;        // [dmax1 + 1] demand CDF of product 1 (B)
+    const double* lifecum;     // C: [a_max + 1][m], p_1(a) + ... + p_k(a) at a*m + k-1
+    double* ret;               // [n_pol * n_roll]
+    double* kpi;               // [n_pol * n_roll][3]
+};
+hipError_t launch_rollouts(const SimDev& s, hipStream_t st);
+hipError_t launch_rollout_stats(const double* ret, const double* kpi, int n_pol, int n_roll,
+                                double* stats, hipStream_t st);
 
 // ------------------------------------------------------------------ batched small instances
 struct BatchItem {

@@ -80,6 +80,21 @@ class Result(ctypes.Structure):
         return out
 
 
+POLICY_KIND = {"table": 0, "base_stock": 1, "mod_base_stock": 2, "s_S": 3}
+POLICY_PARAMS = 16
+
+
+class RolloutOpts(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("kind", ctypes.c_int32),
+        ("table", ctypes.POINTER(ctypes.c_int32)), ("params", ctypes.POINTER(ctypes.c_int32)),
+        ("n_policies", ctypes.c_int32), ("n_rollouts", ctypes.c_int32),
+        ("warmup_days", ctypes.c_int32), ("horizon_days", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("start_state", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 _P = ctypes.POINTER
 
@@ -114,6 +129,8 @@ def load():
         "vi_poll": (i32, [vp, ctypes.c_uint64, _P(Result)]),
         "vi_wait": (i32, [vp, ctypes.c_uint64, i64, _P(Result)]),
         "pvi_server_stats": (i32, [vp, dp, dp, _P(i64)]),
+        "policy_rollouts": (i32, [vp, _P(RolloutOpts), dp, dp, dp]),
+        "heuristic_search": (i32, [vp, _P(RolloutOpts), dp, _P(i32)]),
         "pvi_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -389,3 +406,62 @@ def vi_wait(server, ticket, timeout_us=-1):
 
 def pvi_server_stats(server):
     return server.stats()
+
+
+def _rollout_opts(m, policy, table, params, n_rollouts, warmup, horizon, seed, start, stream):
+    o = RolloutOpts()
+    o.struct_size = ctypes.sizeof(RolloutOpts)
+    o.kind = POLICY_KIND[policy]
+    keep = []
+    if policy == "table":
+        o.n_policies = 1
+        if table is not None:
+            tab = np.ascontiguousarray(table, dtype=np.int32)
+            if tab.shape != (m.n_states,):
+                raise ValueError("table needs one action per state")
+            keep.append(tab)
+            o.table = _iptr(tab)
+    else:
+        rows = np.atleast_2d(np.asarray(params, dtype=np.int32))
+        prm = np.zeros((rows.shape[0], POLICY_PARAMS), dtype=np.int32)
+        prm[:, :rows.shape[1]] = rows
+        keep.append(prm)
+        o.params = _iptr(prm)
+        o.n_policies = rows.shape[0]
+    o.n_rollouts, o.warmup_days, o.horizon_days = int(n_rollouts), int(warmup), int(horizon)
+    o.seed, o.start_state = int(seed), int(start)
+    o.stream = stream
+    return o, keep
+
+
+def policy_rollouts(m, policy="table", table=None, params=None, n_rollouts=10000, warmup=100,
+                    horizon=365, seed=0, start=0, stream=None, per_rollout=True):
+    """Rollouts of a policy (table: the given one, or the handle's solved policy when
+    table is None) or of heuristic parameter rows.  Returns dict(stats [n_pol, 8],
+    ret [n_pol, n_rollouts], kpi [n_pol, n_rollouts, 3]) (ret, kpi None unless
+    per_rollout)."""
+    o, keep = _rollout_opts(m, policy, table, params, n_rollouts, warmup, horizon, seed, start,
+                            stream)
+    n = o.n_policies
+    stats = np.zeros((n, 8))
+    ret = np.zeros((n, int(n_rollouts))) if per_rollout else None
+    kpi = np.zeros((n, int(n_rollouts), 3)) if per_rollout else None
+    null = _P(ctypes.c_double)()
+    _check(_lib.policy_rollouts(m.handle, ctypes.byref(o), _dptr(stats),
+                                _dptr(ret) if per_rollout else null,
+                                _dptr(kpi) if per_rollout else null), "policy_rollouts")
+    del keep
+    return {"stats": stats, "ret": ret, "kpi": kpi}
+
+
+def heuristic_search(m, policy, params, n_rollouts=10000, warmup=100, horizon=365, seed=0,
+                     start=0, stream=None):
+    """Simulation optimization over heuristic parameter rows: (best row index, stats)."""
+    o, keep = _rollout_opts(m, policy, None, params, n_rollouts, warmup, horizon, seed, start,
+                            stream)
+    stats = np.zeros((o.n_policies, 8))
+    best = ctypes.c_int32()
+    _check(_lib.heuristic_search(m.handle, ctypes.byref(o), _dptr(stats), ctypes.byref(best)),
+           "heuristic_search")
+    del keep
+    return int(best.value), stats

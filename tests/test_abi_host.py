@@ -33,6 +33,46 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(pvi.Desc) % 8 == 0
     assert ctypes.sizeof(pvi.Opts) == 56
     assert ctypes.sizeof(pvi.Result) == 96
+    assert ctypes.sizeof(pvi.RolloutOpts) == 64
+
+
+def test_rollout_options_are_validated_before_the_device():
+    lib = ctypes.CDLL(pvi.LIB_PATH)
+    P = ctypes.POINTER
+    lib.policy_rollouts.argtypes = [ctypes.c_void_p, P(pvi.RolloutOpts), P(ctypes.c_double),
+                                    P(ctypes.c_double), P(ctypes.c_double)]
+    lib.heuristic_search.argtypes = [ctypes.c_void_p, P(pvi.RolloutOpts), P(ctypes.c_double),
+                                     P(ctypes.c_int32)]
+    m = pvi.mdp_create(W.config0())
+    st = np.zeros(8 * 11)
+    null = P(ctypes.c_double)()
+
+    def run(policy="base_stock", table=None, params=[[5]], **kw):
+        o, keep = pvi._rollout_opts(m, policy, table, params, kw.get("n", 10), kw.get("w", 5),
+                                    kw.get("h", 20), 0, kw.get("start", 0), None)
+        for k, v in kw.get("set", {}).items():
+            setattr(o, k, v)
+        return lib.policy_rollouts(m.handle, ctypes.byref(o), pvi._dptr(st), null, null)
+
+    assert run(policy="mod_base_stock", params=[[3, 3]]) == pvi.PVI_E_INVALID  # A has no B rule
+    assert run(policy="s_S", params=[[1, 2] * 7]) == pvi.PVI_E_INVALID
+    assert run(n=0) == pvi.PVI_E_INVALID
+    assert run(h=0) == pvi.PVI_E_INVALID
+    assert run(w=-1) == pvi.PVI_E_INVALID
+    assert run(start=121) == pvi.PVI_E_INVALID
+    assert run(set={"struct_size": 60}) == pvi.PVI_E_INVALID
+    assert run(set={"kind": 9}) == pvi.PVI_E_INVALID
+    bad = np.zeros(121, np.int32)
+    bad[7] = 11                                       # 11 actions: 0..10
+    assert run(policy="table", table=bad) == pvi.PVI_E_INVALID
+    assert run(policy="table", table=None) == pvi.PVI_E_NOT_READY   # nothing solved yet
+    assert run(set={"n_rollouts": 1 << 30, "n_policies": 4}) == pvi.PVI_E_INVALID
+    # a valid request reaches the device, which this machine lacks
+    assert run(params=[[S] for S in range(11)]) == pvi.PVI_E_DEVICE
+    o, keep = pvi._rollout_opts(m, "table", np.zeros(121, np.int32), None, 5, 1, 5, 0, 0, None)
+    best = ctypes.c_int32()
+    assert lib.heuristic_search(m.handle, ctypes.byref(o), pvi._dptr(st),
+                                ctypes.byref(best)) == pvi.PVI_E_INVALID
 
 
 def test_older_struct_sizes_are_accepted_and_new_fields_checked():
