@@ -84,6 +84,7 @@ struct pvi_mdp {
 namespace pvi {
 pvi_status ensure_device(pvi_mdp* p);
 void free_device(pvi_mdp* p);
+pvi_status park_results(pvi_mdp* p);
 size_t device_bytes(const pvi_mdp* p);
 pvi::ADev make_adev(const pvi_mdp* p);
 }  // namespace pvi

@@ -10,7 +10,10 @@
 //    (vi_solve) on their own streams, so large solves overlap with the batches.
 // Admission: a large request is started only when its device bytes fit both the
 // server budget and the free device memory; one that can never fit completes with
-// PVI_E_BUSY.  The V tables of large requests stay resident in their handles.
+// PVI_E_BUSY.  The V table of a large request stays resident in HBM until its
+// solve converges; if the request made the handle resident, its results then move
+// to the handle's host memory and its device buffers are freed, so finished
+// handles that the caller keeps never hold memory that waiting requests need.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -119,7 +122,14 @@ void large_worker(pvi_server* S) {
         o.stream = stream;
         o.v0 = r->v0.empty() ? nullptr : r->v0.data();
         pvi_result res{};
+        const bool fresh = !r->mdp->dev.ready;
         pvi_status st = vi_solve(r->mdp, &o, &res);
+        // a handle this request made resident returns its HBM with the results in
+        // host memory, so finished requests never block the admission of new ones
+        if (fresh && (st == PVI_OK || st == PVI_E_NOT_CONVERGED)) {
+            const pvi_status ps = pvi::park_results(r->mdp);
+            if (ps != PVI_OK) st = ps;
+        }
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->used -= r->bytes;

@@ -256,6 +256,27 @@ double midrange(const double* v, int64_t n) {
 }
 
 }  // namespace
+// Move the results of the last solve (V, policy, Q gap) into the handle's host
+// vectors and give its device buffers back.  The request server calls this for
+// handles whose device state its own request created, so completed requests do
+// not pin HBM that waiting requests need.
+pvi_status park_results(pvi_mdp* p) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (!p->dev.ready || p->have_result != 1) return PVI_OK;
+    PVI_HIP(hipSetDevice(p->dev.device));
+    p->h_v.resize(p->ns);
+    p->h_pi.resize(p->ns);
+    p->h_gap.resize(p->ns);
+    PVI_HIP(hipMemcpy(p->h_v.data(), v64_slot(p, p->ret_buf), sizeof(double) * p->ns,
+                      hipMemcpyDeviceToHost));
+    PVI_HIP(hipMemcpy(p->h_pi.data(), p->dev.pi, sizeof(int32_t) * p->ns, hipMemcpyDeviceToHost));
+    PVI_HIP(hipMemcpy(p->h_gap.data(), p->dev.gap, sizeof(double) * p->ns,
+                      hipMemcpyDeviceToHost));
+    p->have_result = 2;
+    free_device(p);
+    return PVI_OK;
+}
+
 }  // namespace pvi
 
 using namespace pvi;
