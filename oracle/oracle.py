@@ -28,7 +28,7 @@ from scipy import stats
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pvi_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_FAMILY = {"A": 0, "B": 1, "C": 2}
+_FAMILY = {"A": 0, "B": 1, "C": 2, "B1": 3}
 
 
 def build(force=True):
@@ -48,6 +48,7 @@ class _OrMdp(ctypes.Structure):
         ("rho", ctypes.c_double), ("c_var", ctypes.c_double * 2), ("c_fixed", ctypes.c_double),
         ("c_hold", ctypes.c_double), ("c_short", ctypes.c_double), ("c_waste", ctypes.c_double),
         ("c_rev", ctypes.c_double * 2), ("gamma", ctypes.c_double), ("issuing", ctypes.c_int32),
+        ("issue_p", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -149,6 +150,38 @@ def life_probabilities(sc):
     return out
 
 
+def issue_probabilities(sc, pmf_a, pmf_b):
+    """Scenario B as the paper runs it (Scenario B description, Appendix B outcome
+    probabilities): P(h_a, h_b | I_a, I_b) for the units issued of each product.
+
+    Product b issues h_b = min(D_b, I_b); its c = D_b - h_b unmet customers each
+    accept product a with probability rho, so D_u ~ Bin(c, rho); product a issues
+    h_a = min(D_a + D_u, I_a).  Summed here over D_a, D_b and D_u from their PMFs.
+    (The paper's conditional P(D_u | I_b, D_b >= I_b) is read as the joint with
+    {D_b >= I_b}, so that the five cases sum to one.)  Returns [I_a][I_b][h_a][h_b]."""
+    m, rho = sc["m"], float(sc["subst_rho"])
+    HA, HB = m * sc["a_max"][0] + 1, m * sc["a_max"][1] + 1
+    da, db = len(pmf_a) - 1, len(pmf_b) - 1
+    # distribution of D_a + Bin(c, rho) for every excess c
+    tot = []
+    for c in range(db + 1):
+        bn = stats.binom.pmf(np.arange(c + 1), c, rho) if c > 0 else np.ones(1)
+        tot.append(np.convolve(pmf_a, bn))
+    P = np.zeros((HA, HB, HA, HB))
+    for Ia in range(HA):
+        for Ib in range(HB):
+            for d in range(db + 1):
+                if d < Ib:
+                    dist, hb = pmf_a, d
+                else:
+                    dist, hb = tot[d - Ib], Ib
+                capped = np.zeros(Ia + 1)
+                capped[:min(Ia, len(dist))] = dist[:Ia]
+                capped[Ia] += dist[Ia:].sum()
+                P[Ia, Ib, :Ia + 1, hb] += pmf_b[d] * capped
+    return P
+
+
 class Oracle:
     """One scenario, ready for oracle sweeps and solves."""
 
@@ -159,10 +192,14 @@ class Oracle:
         P = int(sc["n_periods"])
         self.pmf0 = np.ascontiguousarray(np.stack(
             [demand_pmf(sc["demand"][0], sc["d_max"][0], t) for t in range(P)]))
-        if fam == "B":
+        if fam in ("B", "B1"):
             self.pmf1 = np.ascontiguousarray(demand_pmf(sc["demand"][1], sc["d_max"][1]))
         else:
             self.pmf1 = np.zeros(1)
+        if fam == "B1":
+            self.issue_p = np.ascontiguousarray(issue_probabilities(sc, self.pmf0[0], self.pmf1))
+        else:
+            self.issue_p = np.zeros(1)
         if fam == "C":
             self.rul = np.ascontiguousarray(life_probabilities(sc))
         else:
@@ -181,15 +218,19 @@ class Oracle:
         self.s.c_rev[0], self.s.c_rev[1] = c["rev"]
         self.s.gamma = sc["gamma"]
         self.s.issuing = {"fifo": 0, "lifo": 1}[sc.get("issuing", "fifo")]
+        self.s.issue_p = _dp(self.issue_p)
         self.ref = ctypes.byref(self.s)
         self.n_states = int(self.lib.or_num_states(self.ref))
         self.n_actions = int(self.lib.or_num_actions(self.ref))
-        self.threshold = sc["eps"] * (1.0 - sc["gamma"]) / sc["gamma"]
+        # span rule: eps (1 - gamma)/gamma; with gamma = 1 (Scenario B) the test of
+        # Appendix B as written, span < eps
+        g = sc["gamma"]
+        self.threshold = sc["eps"] if g == 1.0 else sc["eps"] * (1.0 - g) / g
 
     # encoding --------------------------------------------------------------
     def n_digits(self):
         fam, m, L = self.sc["family"], self.sc["m"], self.sc["L"]
-        return {"A": m + L - 1, "B": 2 * (m - 1), "C": m}[fam]
+        return {"A": m + L - 1, "B": 2 * (m - 1), "C": m, "B1": 2 * m}[fam]
 
     def decode(self, idx):
         out = np.zeros(self.n_digits(), dtype=np.int32)
@@ -221,6 +262,26 @@ class Oracle:
         self.lib.or_q_states(self.ref, _dp(V), _lp(st), len(st), _dp(q))
         return q
 
+    def initial_values(self):
+        """V0: zero, except for the paper's Scenario B, whose V0(s) is the expected
+        one-day sales revenue (Appendix B, initial value equation)."""
+        if self.sc["family"] != "B1":
+            return np.zeros(self.n_states)
+        m = self.sc["m"]
+        HA, HB = self.issue_p.shape[0], self.issue_p.shape[1]
+        ra, rb = self.sc["costs"]["rev"]
+        rev = np.zeros((HA, HB))
+        for Ia in range(HA):
+            for Ib in range(HB):
+                P = self.issue_p[Ia, Ib]
+                rev[Ia, Ib] = sum(P[ha, hb] * (ra * ha + rb * hb)
+                                  for ha in range(Ia + 1) for hb in range(Ib + 1))
+        V = np.zeros(self.n_states)
+        for s in range(self.n_states):
+            d = self.decode(s)
+            V[s] = rev[int(d[:m].sum()), int(d[m:].sum())]
+        return V
+
     def sweep(self, V):
         V = np.ascontiguousarray(V, dtype=np.float64)
         Vn = np.zeros(self.n_states)
@@ -237,7 +298,10 @@ class Oracle:
         n_periods increments, with thr the relative tolerance.
         """
         thr = self.threshold if thr is None else float(thr)
-        V = np.zeros(self.n_states) if v0 is None else np.array(v0, dtype=np.float64)
+        if v0 is None:
+            V = self.initial_values()
+        else:
+            V = np.array(v0, dtype=np.float64)
         pi = np.zeros(self.n_states, dtype=np.int32)
         gap = np.zeros(self.n_states)
         st = np.zeros(4)

@@ -21,6 +21,10 @@
  *   [A_{m-1}..A_1, B_{m-1}..B_1], outcome = (dA, dB, k) where k ~ Binomial(uA, rho)
  *   of product 0's unmet demand uA accept product 1, served from product 1's stock
  *   left after its own demand, oldest first.
+ * Scenario B as the paper runs it (family 3; Appendix B): lead time 1, state
+ *   [Xa_m..Xa_1, Xb_m..Xb_1], outcome = units issued (h_a, h_b), probabilities
+ *   P(h_a, h_b | I_a, I_b) supplied as a table built from the demand and
+ *   substitution definitions (oracle.py).
  * Scenario C (Appendix C, state-transition and reward equations): state
  *   [tau, X_{m-1}, ..., X_1], outcome = (d, y) with y a multinomial split of the
  *   order over remaining lives m..1 and stock of each life capped at a_max.
@@ -46,6 +50,9 @@ typedef struct {
     double c_var[2], c_fixed, c_hold, c_short, c_waste, c_rev[2];
     double gamma;
     int32_t issuing;     /* A: 0 = FIFO (eq:demoor:fifo), 1 = LIFO (eq:demoor:lifo) */
+    /* family 3 (Scenario B as the paper runs it): P(h_a, h_b | I_a, I_b), flattened
+     * [I_a][I_b][h_a][h_b] with I_a, h_a in 0..m a_max[0], I_b, h_b in 0..m a_max[1] */
+    const double* issue_p;
 } or_mdp;
 
 static double pos(double x) { return x > 0.0 ? x : 0.0; }
@@ -56,6 +63,7 @@ static int ipos(int x) { return x > 0 ? x : 0; }
 static int n_digits(const or_mdp* p) {
     if (p->family == 0) return p->m + p->L - 1;
     if (p->family == 1) return 2 * (p->m - 1);
+    if (p->family == 3) return 2 * p->m;
     return p->m; /* tau + (m-1) stock digits */
 }
 
@@ -66,6 +74,9 @@ static void radices(const or_mdp* p, int* rad) {
     } else if (p->family == 1) {
         for (int i = 0; i < p->m - 1; ++i) rad[i] = p->a_max[0] + 1;
         for (int i = 0; i < p->m - 1; ++i) rad[p->m - 1 + i] = p->a_max[1] + 1;
+    } else if (p->family == 3) {
+        for (int i = 0; i < p->m; ++i) rad[i] = p->a_max[0] + 1;
+        for (int i = 0; i < p->m; ++i) rad[p->m + i] = p->a_max[1] + 1;
     } else {
         rad[0] = p->n_periods;
         for (int i = 1; i < n; ++i) rad[i] = p->a_max[0] + 1;
@@ -81,7 +92,7 @@ int64_t or_num_states(const or_mdp* p) {
 }
 
 int32_t or_num_actions(const or_mdp* p) {
-    if (p->family == 1) return (p->a_max[0] + 1) * (p->a_max[1] + 1);
+    if (p->family == 1 || p->family == 3) return (p->a_max[0] + 1) * (p->a_max[1] + 1);
     return p->a_max[0] + 1;
 }
 
@@ -233,6 +244,55 @@ static double q_b(const or_mdp* p, const double* V, const int32_t* dig, int aA, 
     return q;
 }
 
+/* ------------------------------------------- scenario B as the paper runs it */
+/* Family 3 (Scenario B description and Appendix B): lead time 1, so the state
+ * [Xa_m..Xa_1, Xb_m..Xb_1] includes yesterday's orders as X_m; the outcome is the
+ * units issued (h_a, h_b); issuing is FIFO per product (FIFO equation of Appendix
+ * B), today's order becomes tomorrow's X_m; reward -(C_v^a A^a + C_v^b A^b) +
+ * C_r^a h_a + C_r^b h_b (reward equation, with the garbled C^a_v A^b read as
+ * C^b_v A^b). */
+static void trans_b1(const or_mdp* p, const int32_t* dig, int aA, int aB, int hA, int hB,
+                     int32_t* nd, double* r) {
+    int m = p->m;
+    int xa[OR_MAXD + 1], xb[OR_MAXD + 1];
+    for (int j = 1; j <= m; ++j) {
+        xa[j] = dig[m - j];
+        xb[j] = dig[m + (m - j)];
+    }
+    int ca = 0, cb = 0;
+    for (int j = 1; j <= m - 1; ++j) {
+        ca += xa[j];
+        cb += xb[j];
+        nd[m - j] = ipos(xa[j + 1] - ipos(hA - ca));
+        nd[m + (m - j)] = ipos(xb[j + 1] - ipos(hB - cb));
+    }
+    nd[0] = aA;
+    nd[m] = aB;
+    *r = -(p->c_var[0] * aA + p->c_var[1] * aB) + p->c_rev[0] * hA + p->c_rev[1] * hB;
+}
+
+static double q_b1(const or_mdp* p, const double* V, const int32_t* dig, int aA, int aB) {
+    int m = p->m;
+    int Ia = 0, Ib = 0;
+    for (int j = 0; j < m; ++j) {
+        Ia += dig[j];
+        Ib += dig[m + j];
+    }
+    int HA = m * p->a_max[0] + 1, HB = m * p->a_max[1] + 1;
+    const double* P = p->issue_p + ((size_t)Ia * HB + Ib) * (size_t)HA * HB;
+    int32_t nd[OR_MAXD];
+    double q = 0.0;
+    for (int hA = 0; hA <= Ia; ++hA)
+        for (int hB = 0; hB <= Ib; ++hB) {
+            double pr = P[(size_t)hA * HB + hB];
+            if (pr == 0.0) continue;
+            double r;
+            trans_b1(p, dig, aA, aB, hA, hB, nd, &r);
+            q += pr * (r + p->gamma * V[or_encode(p, nd)]);
+        }
+    return q;
+}
+
 /* -------------------------------------------------------------- scenario C */
 /* dig = [tau, X_{m-1}..X_1]; y[1..m] arrivals by remaining life; demand d. */
 static void trans_c(const or_mdp* p, const int32_t* dig, int a, const int* y, int d,
@@ -327,6 +387,10 @@ static double q_sa(const or_mdp* p, const double* V, const int32_t* dig, int a) 
     if (p->family == 1) {
         int nb = p->a_max[1] + 1;
         return q_b(p, V, dig, a / nb, a % nb);
+    }
+    if (p->family == 3) {
+        int nb = p->a_max[1] + 1;
+        return q_b1(p, V, dig, a / nb, a % nb);
     }
     return q_c(p, V, dig, a);
 }
@@ -469,6 +533,9 @@ int or_transition(const or_mdp* p, int64_t s, int32_t a, const int32_t* omega,
     } else if (p->family == 1) {
         int nb = p->a_max[1] + 1;
         trans_b(p, dig, a / nb, a % nb, omega[0], omega[1], omega[2], nd, r);
+    } else if (p->family == 3) {
+        int nb = p->a_max[1] + 1;
+        trans_b1(p, dig, a / nb, a % nb, omega[0], omega[1], nd, r);
     } else {
         int y[OR_MAXD + 1];
         for (int k = 1; k <= p->m; ++k) y[k] = omega[1 + (p->m - k)];
@@ -568,10 +635,11 @@ static int policy_action(const or_mdp* p, int kind, const int32_t* table,
     }
     if (kind == 2) {
         int m = p->m, q[2];
+        int w = p->family == 3 ? m : m - 1; /* digits per product */
         for (int k = 0; k < 2; ++k) {
             int I = 0;
-            for (int j = 0; j < m - 1; ++j) I += dig[k * (m - 1) + j];
-            int x1 = dig[k * (m - 1) + (m - 2)]; /* life 1: last digit of the product */
+            for (int j = 0; j < w; ++j) I += dig[k * w + j];
+            int x1 = dig[k * w + (w - 1)]; /* life 1: last digit of the product */
             double v = pos((double)prm[k] - I + pos((double)x1 - mu[k]));
             int a = (int)floor(v);
             q[k] = a < p->a_max[k] ? a : p->a_max[k];
@@ -639,6 +707,30 @@ static double sim_day(const or_mdp* p, uint64_t seed, int64_t r, int t, const in
         c->received += aA + aB;
         c->held += keptA + keptB;
         c->expired += (sA - hA - keptA) + (sB - hB - hS - keptB);
+    } else if (p->family == 3) {
+        int nb = p->a_max[1] + 1, aA = a / nb, aB = a % nb;
+        int dA = sample_pmf(p->pmf0, p->d_max[0], draw(seed, r, t, 0, 0));
+        int dB = sample_pmf(p->pmf1, p->d_max[1], draw(seed, r, t, 0, 1));
+        int Ia = 0, Ib = 0;
+        for (int j = 0; j < m; ++j) {
+            Ia += dig[j];
+            Ib += dig[m + j];
+        }
+        int hB = dB < Ib ? dB : Ib, excess = dB - hB, du = 0;
+        for (int i = 0; i < excess; ++i)
+            if (draw(seed, r, t, 1 + i / 4, i % 4) < p->rho) ++du;
+        int hA = dA + du < Ia ? dA + du : Ia;
+        trans_b1(p, dig, aA, aB, hA, hB, nd, &rew);
+        int keptA = 0, keptB = 0;
+        for (int j = 1; j < m; ++j) {
+            keptA += nd[j];
+            keptB += nd[m + j];
+        }
+        c->demand += dA + dB;
+        c->met += hA + hB; /* product b's demand met by product a counts as met */
+        c->received += aA + aB;
+        c->held += keptA + keptB;
+        c->expired += (Ia - hA - keptA) + (Ib - hB - keptB);
     } else {
         int d = sample_pmf(p->pmf0 + (size_t)dig[0] * (p->d_max[0] + 1), p->d_max[0],
                            draw(seed, r, t, 0, 0));

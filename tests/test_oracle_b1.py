@@ -1,0 +1,109 @@
+"""Pins of the oracle's Scenario B as the paper runs it (Scenario B description and
+Appendix B: two products, lead time 1, outcome = units issued, substitution of
+product b's unmet customers by product a, gamma = 1, V0 = expected revenue, span
+stop).
+
+* The issue probabilities P(h_a, h_b | I_a, I_b) sum to one and, with rho = 0,
+  factor into the two products' capped demands.
+* The oracle's Bellman operator equals a dense model built from the unit-by-unit
+  model over every (D_a, D_b, D_u) outcome with scipy probabilities.
+* V0 is the expected one-day sales revenue of the unit model.
+* 10,000 rollouts of the oracle's policy reproduce the paper's printed returns of the
+  m = 2 experiments, and the modified base-stock levels it prints are the best of
+  their neighbourhood, with the printed returns.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import unit_model as U
+import workloads as W
+from oracle.oracle import Oracle, demand_pmf
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_rollouts.json")))
+
+TINY = [
+    W.scenario_b1(m=2, a_max=(2, 3), means=(1.5, 2.0), rho=0.5, d_max=7, gamma=0.9),
+    W.scenario_b1(m=3, a_max=(2, 1), means=(2.0, 1.0), rho=0.3, d_max=6, gamma=1.0),
+]
+
+
+@pytest.mark.parametrize("sc", TINY + [W.scenario_b_paper(2, 1)], ids=["m2", "m3", "paper-m2"])
+def test_issue_probabilities_sum_to_one(sc):
+    P = Oracle(sc).issue_p
+    assert np.abs(P.sum(axis=(2, 3)) - 1.0).max() < 1e-13
+    HA, HB = P.shape[:2]
+    for Ia in range(HA):                      # no more issued than in stock
+        assert np.all(P[Ia, :, Ia + 1:, :] == 0.0)
+
+
+def test_no_substitution_factorises():
+    sc = W.scenario_b1(m=2, a_max=(3, 2), means=(2.0, 1.5), rho=0.0, d_max=9)
+    o = Oracle(sc)
+    pa = demand_pmf(sc["demand"][0], sc["d_max"][0])
+    pb = demand_pmf(sc["demand"][1], sc["d_max"][1])
+
+    def capped(p, I):
+        out = np.zeros(I + 1)
+        out[:I] = p[:I]
+        out[I] = p[I:].sum()
+        return out
+
+    for Ia in range(o.issue_p.shape[0]):
+        for Ib in range(o.issue_p.shape[1]):
+            want = np.outer(capped(pa, Ia), capped(pb, Ib))
+            assert np.abs(o.issue_p[Ia, Ib, :Ia + 1, :Ib + 1] - want).max() < 1e-15
+
+
+@pytest.mark.parametrize("sc", TINY, ids=["m2", "m3"])
+def test_bellman_operator_matches_unit_model(sc):
+    o = Oracle(sc)
+    pa = [demand_pmf(sc["demand"][0], sc["d_max"][0])]
+    pb = demand_pmf(sc["demand"][1], sc["d_max"][1])
+    P, r = U.dense_model(sc, pa, pb)
+    assert np.abs(P.sum(axis=2) - 1.0).max() < 1e-12
+    V = W.random_values(o.n_states, seed=4, scale=5.0, offset=10.0)
+    Vu, piu, Q = U.bellman(P, r, sc["gamma"], V)
+    Vo, pio, gapo = o.sweep(V)
+    assert np.abs(Vo - Vu).max() < 1e-12 * np.abs(Vu).max()
+    clear = gapo > 1e-9
+    assert np.array_equal(pio[clear], piu[clear])
+
+
+def test_initial_values_are_expected_revenue():
+    sc = TINY[0]
+    o = Oracle(sc)
+    pa = [demand_pmf(sc["demand"][0], sc["d_max"][0])]
+    pb = demand_pmf(sc["demand"][1], sc["d_max"][1])
+    V0 = o.initial_values()
+    ra, rb = sc["costs"]["rev"]
+    for s in range(o.n_states):
+        want = 0.0
+        for om, pr in U.outcomes(sc, s, 0, pa, pb, None):
+            _, _, tally = U.day(sc, s, 0, om)
+            want += pr * tally["met"]            # unit revenue 1 for both products
+        assert abs(V0[s] - want) < 1e-12
+    assert ra == rb == 1.0
+
+
+def _close(ours, printed, sd, digits=0):
+    return abs(ours - printed) <= 4.0 * sd * np.sqrt(2.0 / 10000) + 0.5 * 10.0 ** -digits
+
+
+@pytest.mark.parametrize("row", GOLD["scenario_b"], ids=lambda r: f"m{r['m']}e{r['exp']}")
+def test_scenario_b_rollouts_match_the_paper(row):
+    sc = W.scenario_b_paper(row["m"], row["exp"])
+    o = Oracle(sc)
+    vi = o.solve()
+    ret, _ = o.simulate("table", table=vi["pi"], n_rollouts=10000, seed=1)
+    assert _close(ret[0].mean(), row["vi_return"][0], ret[0].std(ddof=1))
+    assert abs(ret[0].std(ddof=1) - row["vi_return"][1]) <= 2.0
+    Sa, Sb = row["s_best"]
+    grid = [[a, b] for a in range(Sa - 2, Sa + 3) for b in range(Sb - 2, Sb + 3)]
+    g, _ = o.simulate("mod_base_stock", params=grid, n_rollouts=10000, seed=1)
+    best = int(np.argmax(g.mean(axis=1)))
+    assert grid[best] == [Sa, Sb]
+    assert _close(g[best].mean(), row["so_return"][0], g[best].std(ddof=1))

@@ -57,7 +57,7 @@ def _replay(sc, table, n_roll, warmup, horizon, seed):
     """Rollouts in the unit model; returns (ret, kpi) like Oracle.simulate."""
     fam, m = sc["family"], sc["m"]
     pmfs = [demand_pmf(sc["demand"][0], sc["d_max"][0], t) for t in range(sc["n_periods"])]
-    pmf1 = demand_pmf(sc["demand"][1], sc["d_max"][1]) if fam == "B" else None
+    pmf1 = demand_pmf(sc["demand"][1], sc["d_max"][1]) if fam in ("B", "B1") else None
     life = life_probabilities(sc) if fam == "C" else None
     ret = np.zeros(n_roll)
     kpi = np.zeros((n_roll, 3))
@@ -78,6 +78,13 @@ def _replay(sc, table, n_roll, warmup, horizon, seed):
                 k = sum(1 for i in range(unmet) if _u(seed, r, t, 1 + i // 4, i % 4)
                         < sc["subst_rho"])
                 om = (dA, dB, k)
+            elif fam == "B1":
+                dA = _inverse_cdf(pmfs[0], _u(seed, r, t, 0, 0))
+                dB = _inverse_cdf(pmf1, _u(seed, r, t, 0, 1))
+                excess = max(dB - sum(dig[m:]), 0)
+                du = sum(1 for i in range(excess) if _u(seed, r, t, 1 + i // 4, i % 4)
+                         < sc["subst_rho"])
+                om = (dA, dB, du)
             else:
                 d = _inverse_cdf(pmfs[dig[0]], _u(seed, r, t, 0, 0))
                 y = [0] * (m + 1)                       # y[life]
@@ -109,10 +116,11 @@ REPLAY = [
                  demand={"kind": "gamma", "mean": [3.0], "cv": [0.8]}),
     W.scenario_b(m=3, a_max=(3, 4), d_max=(6, 5), means=(3.0, 2.0), rho=0.6),
     W.scenario_c(m=3, a_max=5, d_max=8, c0=[0.0, 1.0, 0.5], c1=[0.0, 0.2, -0.1]),
+    W.scenario_b1(m=2, a_max=(4, 3), means=(3.0, 2.5), rho=0.5, d_max=10),
 ]
 
 
-@pytest.mark.parametrize("sc", REPLAY, ids=["A-fifo", "A-lifo", "B", "C-endogenous"])
+@pytest.mark.parametrize("sc", REPLAY, ids=["A-fifo", "A-lifo", "B", "C-endogenous", "B1"])
 def test_rollouts_match_unit_model_replay(sc):
     o = Oracle(sc)
     rng = np.random.default_rng(5)

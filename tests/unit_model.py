@@ -27,6 +27,8 @@ def radices(sc):
         return [sc["a_max"][0] + 1] * (m + L - 1)
     if fam == "B":
         return [sc["a_max"][0] + 1] * (m - 1) + [sc["a_max"][1] + 1] * (m - 1)
+    if fam == "B1":
+        return [sc["a_max"][0] + 1] * m + [sc["a_max"][1] + 1] * m
     return [sc["n_periods"]] + [sc["a_max"][0] + 1] * (m - 1)
 
 
@@ -52,7 +54,7 @@ def n_states(sc):
 
 
 def n_actions(sc):
-    if sc["family"] == "B":
+    if sc["family"] in ("B", "B1"):
         return (sc["a_max"][0] + 1) * (sc["a_max"][1] + 1)
     return sc["a_max"][0] + 1
 
@@ -112,6 +114,27 @@ def day(sc, s, a, omega):
         tally = {"demand": d, "met": issued, "expired": expired, "received": arriving,
                  "held": held}
         return encode(sc, new_pipeline + counts), float(reward), tally
+    if fam == "B1":
+        # lead time 1: stock of life m is yesterday's order; product b's unmet
+        # customers (omega[2] of them accept) take product a's leftovers
+        nb = sc["a_max"][1] + 1
+        aA, aB = a // nb, a % nb
+        stA = {life: dig[m - life] for life in range(1, m + 1)}
+        stB = {life: dig[m + (m - life)] for life in range(1, m + 1)}
+        dA, dB, du = omega
+        hA, leftA = _serve(_units(stA), dA)
+        hB, leftB = _serve(_units(stB), dB)
+        assert du <= dB - hB
+        hS, leftA = _serve(leftA, du)
+        reward = (-(c["var"][0] * aA + c["var"][1] * aB) + c["rev"][0] * (hA + hS)
+                  + c["rev"][1] * hB)
+        nA = [u - 1 for u in leftA if u > 1]
+        nB = [u - 1 for u in leftB if u > 1]
+        dA_ = [aA] + [sum(1 for u in nA if u == life) for life in range(m - 1, 0, -1)]
+        dB_ = [aB] + [sum(1 for u in nB if u == life) for life in range(m - 1, 0, -1)]
+        tally = {"demand": dA + dB, "met": hA + hS + hB, "received": aA + aB,
+                 "expired": sum(1 for u in leftA + leftB if u == 1), "held": len(nA) + len(nB)}
+        return encode(sc, dA_ + dB_), float(reward), tally
     if fam == "B":
         nb = sc["a_max"][1] + 1
         aA, aB = a // nb, a % nb
@@ -181,6 +204,17 @@ def outcomes(sc, s, a, pmf0, pmf1, life_p):
                 for k in range(u + 1):
                     pk = stats.binom.pmf(k, u, sc["subst_rho"]) if u > 0 else 1.0
                     out.append(((dA, dB, k), float(pmf0[0][dA] * pmf1[dB] * pk)))
+        return out
+    if fam == "B1":
+        dig = decode(sc, s)
+        stockB = sum(dig[m:])
+        out = []
+        for dA in range(len(pmf0[0])):
+            for dB in range(len(pmf1)):
+                c = max(dB - stockB, 0)
+                for du in range(c + 1):
+                    pu = stats.binom.pmf(du, c, sc["subst_rho"]) if c > 0 else 1.0
+                    out.append(((dA, dB, du), float(pmf0[0][dA] * pmf1[dB] * pu)))
         return out
     tau = decode(sc, s)[0]
     out = []

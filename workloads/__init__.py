@@ -13,6 +13,9 @@ from .scenarios import (  # noqa: F401
     PAPER_A_EXPERIMENTS,
     scenario_c_paper,
     PAPER_C_EXPERIMENTS,
+    scenario_b1,
+    scenario_b_paper,
+    PAPER_B_EXPERIMENTS,
     config0,
     config1,
     config2,

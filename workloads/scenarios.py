@@ -2,7 +2,8 @@
 
 Every dictionary has the same keys, whatever the family:
 
-  family      "A" (lead time, FIFO), "B" (two products, one-way substitution),
+  family      "A" (lead time, FIFO), "B" (two products, one-way substitution, L = 0),
+              "B1" (the paper's two-product runs: L = 1, outcome = units issued),
               "C" (weekday demand, random remaining life on arrival)
   m           maximum useful life
   L           lead time (A: >= 1; B and C: 0, the order arrives before demand)
@@ -30,7 +31,8 @@ import numpy as np
 
 __all__ = [
     "scenario_a", "scenario_b", "scenario_c", "scenario_a_paper", "PAPER_A_EXPERIMENTS",
-    "scenario_c_paper", "PAPER_C_EXPERIMENTS",
+    "scenario_c_paper", "PAPER_C_EXPERIMENTS", "scenario_b1", "scenario_b_paper",
+    "PAPER_B_EXPERIMENTS",
     "config0", "config1", "config2",
     "config3", "config_by_index", "serving_mix", "random_values", "sample_indices",
 ]
@@ -70,6 +72,44 @@ def scenario_b(m=3, a_max=(14, 14), d_max=(20, 20), means=(5.0, 4.0), rho=0.5,
                        {"kind": "poisson", "mean": [float(means[1])]}],
             "rul_c0": [0.0] * int(m), "rul_c1": [0.0] * int(m), "subst_rho": float(rho),
             "costs": copy.deepcopy(costs), "gamma": float(gamma), "eps": float(eps)}
+
+
+def scenario_b1(m=2, a_max=(10, 10), means=(5.0, 5.0), rho=0.5, d_max=None, costs=None,
+                gamma=1.0, eps=1e-4):
+    """Scenario B as the paper runs it: two products, lead time 1 (yesterday's orders
+    are in stock as X_m), outcome = units issued, product b's unmet customers accept
+    product a with probability rho.  Poisson demand folded at d_max (default
+    m * max(a_max) + 2, the paper's table bound)."""
+    if costs is None:
+        costs = _costs(var=(0.5, 0.5), rev=(1.0, 1.0))
+    if d_max is None:
+        d_max = m * max(a_max) + 2
+    return {"family": "B1", "m": int(m), "L": 1, "n_periods": 1,
+            "a_max": [int(a_max[0]), int(a_max[1])], "d_max": [int(d_max), int(d_max)],
+            "demand": [{"kind": "poisson", "mean": [float(means[0])]},
+                       {"kind": "poisson", "mean": [float(means[1])]}],
+            "rul_c0": [0.0] * int(m), "rul_c1": [0.0] * int(m), "subst_rho": float(rho),
+            "costs": copy.deepcopy(costs), "gamma": float(gamma), "eps": float(eps)}
+
+
+# Scenario B experiments of the paper's results tables: (m, experiment) ->
+# (mean demand a, b; maximum order a, b).  "P1".."P4" are the settings of the
+# comparison with an earlier CUDA implementation, run for exactly 100 sweeps.
+PAPER_B_EXPERIMENTS = {
+    (2, "1"): ((5.0, 5.0), (10, 10)), (2, "2"): ((7.0, 3.0), (14, 6)),
+    (3, "1"): ((5.0, 5.0), (15, 15)), (3, "2"): ((7.0, 3.0), (21, 9)),
+    (3, "3"): ((5.0, 5.0), (13, 13)), (3, "4"): ((7.0, 3.0), (20, 4)),
+    (2, "P1"): ((5.0, 5.0), (10, 10)), (2, "P2"): ((5.0, 6.0), (10, 12)),
+    (2, "P3"): ((6.0, 6.0), (12, 12)), (2, "P4"): ((7.0, 7.0), (13, 13)),
+}
+
+
+def scenario_b_paper(m, exp):
+    """Scenario B with the settings the paper fixes for all its experiments (Appendix B
+    common-settings table): C_v 0.5 and C_r 1 for both products, rho 0.5, gamma 1,
+    eps 1e-4, span stop (the P experiments: 100 sweeps)."""
+    means, amax = PAPER_B_EXPERIMENTS[(m, str(exp))]
+    return scenario_b1(m=m, a_max=amax, means=means, rho=0.5)
 
 
 def scenario_c(m=3, a_max=4, d_max=8, n=None, means=None, c0=None, c1=None,
