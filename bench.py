@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="config1", choices=["config1", "batch", "serving",
                                                                "config2", "config3",
-                                                               "paper-a", "paper-c", "rollouts"],
+                                                               "paper-a", "paper-b", "paper-c", "rollouts"],
                     help="config1 (default, the headline), batch (many small solves: "
                          "batched FP32 kernel vs one FP64 solve per call), serving (the "
                          "request mix through the server), config2/config3 (one solve), paper-a / paper-c "
@@ -349,6 +349,41 @@ def bench_paper_c(args, pvi, W):
     print(json.dumps(line), flush=True)
 
 
+def bench_paper_b(args, pvi, W):
+    """The paper's scenario-B experiments (lead time 1, gamma = 1, V0 = expected revenue,
+    span stop; P1-P4: exactly 100 sweeps): one solve each after one untimed solve."""
+    out = []
+    for (mm, exp) in W.PAPER_B_EXPERIMENTS:
+        sc = W.scenario_b_paper(mm, exp)
+        t0 = time.perf_counter()
+        m = pvi.mdp_create(sc)
+        row = {"m": mm, "exp": exp, "states": m.n_states, "actions": m.n_actions,
+               "create_ms": (time.perf_counter() - t0) * 1e3}
+        fixed = 100 if exp.startswith("P") else 0
+        for prec in ("fp64", "fp32"):
+            kw = {"fixed_sweeps": fixed} if fixed else {}
+            pvi.vi_solve(m, precision=prec, **kw)
+            t0 = time.perf_counter()
+            r = pvi.vi_solve(m, precision=prec, time_kernels=True, **kw)
+            dt = time.perf_counter() - t0
+            row[prec] = {"solve_ms": dt * 1e3, "sweeps_fp32": r["sweeps_fp32"],
+                         "sweeps_fp64": r["sweeps_fp64"],
+                         "backups_per_s": r["logical_backups"] / dt,
+                         "backup_ms": list(r["backup_ms"]),
+                         "backup_launches": list(r["backup_launches"])}
+        print(f"B m={mm} exp {exp}: {row['states']} states, fp64 "
+              f"{row['fp64']['solve_ms']:.1f} ms ({row['fp64']['sweeps_fp64']} sweeps), fp32 "
+              f"{row['fp32']['solve_ms']:.1f} ms", file=sys.stderr, flush=True)
+        out.append(row)
+        del m
+    line = {"metric": METRIC, "value": max(r["fp64"]["backups_per_s"] for r in out),
+            "unit": "backups/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "dtype": "f64",
+            "config": {"workload": "paper scenario-B experiments (lead time 1, gamma 1)"},
+            "detail": out}
+    print(json.dumps(line), flush=True)
+
+
 def bench_rollouts(args, pvi, W):
     """Policy evaluation and simulation optimization on the GPU (Simulation section):
     10,000 rollouts of 100 + 365 days of the solved policy of the paper's largest
@@ -439,6 +474,8 @@ def main():
         return bench_paper_a(args, pvi, W)
     if args.workload == "paper-c":
         return bench_paper_c(args, pvi, W)
+    if args.workload == "paper-b":
+        return bench_paper_b(args, pvi, W)
     if args.workload == "rollouts":
         return bench_rollouts(args, pvi, W)
     if args.copy_calibration_mb > 0:

@@ -30,6 +30,17 @@
  *                          life on arrival ~ Multinomial(a; p_m(a)..p_1(a)), stock
  *                          of each life capped at a_max (excess refused at delivery).
  *                          State digits [tau, X_{m-1}, ..., X_1].
+ *   PVI_FAMILY_SUBST2_L1   Scenario B as the paper runs it (Scenario B description,
+ *                          Appendix B): two products a (0) and b (1), lead time 1
+ *                          (yesterday's orders are in stock with m days of life), FIFO;
+ *                          product b issues h_b = min(D_b, I_b) and its D_b - h_b unmet
+ *                          customers each accept product a with probability subst_rho;
+ *                          product a issues h_a = min(D_a + accepted, I_a).  State
+ *                          digits [Xa_m..Xa_1, Xb_m..Xb_1]; action a = a0*(a_max[1]+1)+a1;
+ *                          outcome (h_a, h_b); reward -c_var.a + c_rev.h.  gamma = 1 is
+ *                          allowed (the span rule then stops at span < eps), and the
+ *                          solve starts from the expected one-day sales revenue when
+ *                          no v0 is given (Appendix B, initial value equation).
  *
  * Conventions
  *  - Every function returns pvi_status and never throws across the ABI.  On error
@@ -66,7 +77,8 @@ typedef enum {
 typedef enum {
     PVI_FAMILY_LEADTIME = 0,
     PVI_FAMILY_SUBST2 = 1,
-    PVI_FAMILY_RUL_WEEKDAY = 2
+    PVI_FAMILY_RUL_WEEKDAY = 2,
+    PVI_FAMILY_SUBST2_L1 = 3
 } pvi_family;
 
 typedef enum {
@@ -123,7 +135,7 @@ typedef struct pvi_mdp_desc {
                                   `issuing` is accepted, the missing fields read 0 */
     int32_t family;            /* pvi_family */
     int32_t m;                 /* maximum useful life, 1..PVI_MAX_LIFE */
-    int32_t lead_time;         /* A: >= 1; B and C: 0 */
+    int32_t lead_time;         /* A: >= 1; B and C: 0; SUBST2_L1: 1 */
     int32_t n_periods;         /* C: 1..7 demand periods (weekdays); else 1 */
     int32_t a_max[2];          /* max order per product; B uses both */
     int32_t d_max[2];          /* demand truncation per product */
@@ -138,7 +150,7 @@ typedef struct pvi_mdp_desc {
     double c_fixed;            /* C: fixed cost when a > 0 */
     double c_hold, c_short, c_waste;
     double c_rev[2];           /* B: revenue per unit issued */
-    double gamma;              /* discount factor, 0 < gamma < 1 */
+    double gamma;              /* discount factor, 0 < gamma < 1 (SUBST2_L1: <= 1) */
     int32_t issuing;           /* A: pvi_issuing (absent in older callers' struct_size: FIFO) */
 } pvi_mdp_desc;
 

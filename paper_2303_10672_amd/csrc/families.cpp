@@ -76,6 +76,45 @@ static BDev make_bdev(const pvi_mdp* p) {
     return b;
 }
 
+static B1Dev make_b1dev(const pvi_mdp* p) {
+    B1Dev b{};
+    const int m = p->m;
+    b.m = m;
+    b.Ra = p->rad[0];
+    b.Rb = p->rad[1];
+    b.HA = p->b1_ha;
+    b.HB = p->b1_hb;
+    b.na1 = (int)ipow(b.Ra, m - 1);
+    b.nb1 = (int)ipow(b.Rb, m - 1);
+    b.NA = (int)ipow(b.Ra, m);
+    b.NB = (int)ipow(b.Rb, m);
+    b.gw = std::max(1, std::min(b.na1, 4096 / std::max(1, b.nb1)));
+    b.cb = std::max(1, std::min({16, b.Rb, 8192 / std::max(1, b.na1)}));
+    b.gamma = p->d.gamma;
+    b.cva = p->d.c_var[0];
+    b.cvb = p->d.c_var[1];
+    const auto& d = p->dev;
+    b.w = d.b1w;
+    b.y = d.b1y;
+    b.pa = d.b1pa;
+    b.pc = d.b1pc;
+    b.pb = d.b1pb;
+    b.fb = d.b1fb;
+    b.j = d.b1j;
+    b.jc = d.b1jc;
+    b.rev = d.b1rev;
+    b.ctl = d.ctl;
+    b.partials = d.partials;
+    b.pi = d.pi;
+    b.gap = d.gap;
+    return b;
+}
+
+hipError_t family_initial_values(pvi_mdp* p, double* v, hipStream_t s) {
+    if (p->family != PVI_FAMILY_SUBST2_L1) return hipErrorInvalidValue;
+    return launch_b1_initial(make_b1dev(p), v, s);
+}
+
 static CDev make_cdev(const pvi_mdp* p) {
     CDev c{};
     const int R = p->rad[0];
@@ -135,6 +174,14 @@ std::string family_support_msg(const pvi_mdp* p) {
         if (lds > 65536) return "scenario C demand table exceeds LDS";
         return "ok";
     }
+    if (p->family == PVI_FAMILY_SUBST2_L1) {
+        const int64_t na1 = ipow(p->rad[0], p->m - 1), nb1 = ipow(p->rad[1], p->m - 1);
+        if (ipow(p->rad[1], p->m) > 65535)
+            return "the lead-time-1 two-product family needs (a_max[1]+1)^m <= 65535 on the GPU";
+        if (na1 > 8192 || nb1 > 4096)
+            return "the lead-time-1 two-product family: aged stock of one product exceeds LDS";
+        return "ok";
+    }
     return "this family has no GPU kernel yet";
 }
 
@@ -150,7 +197,17 @@ int family_tiles(const pvi_mdp* p) {
     if (p->family == PVI_FAMILY_SUBST2) return (int)ipow(p->rad[1], p->m - 1);
     if (p->family == PVI_FAMILY_RUL_WEEKDAY)
         return (int)(p->P * ((ipow(p->rad[0], p->m - 1) + 255) / 256));
+    if (p->family == PVI_FAMILY_SUBST2_L1)
+        return (int)(ipow(p->rad[1], p->m) * ((ipow(p->rad[0], p->m) + 255) / 256));
     return 1;
+}
+
+static size_t b1_w_entries(const pvi_mdp* p) {
+    return (size_t)p->na * ipow(p->rad[1], p->m) * ipow(p->rad[0], p->m - 1);
+}
+
+static size_t b1_y_entries(const pvi_mdp* p) {
+    return (size_t)p->na * p->b1_hb * ipow(p->rad[0], p->m);
 }
 
 size_t family_extra_bytes(const pvi_mdp* p) {
@@ -167,6 +224,10 @@ size_t family_extra_bytes(const pvi_mdp* p) {
         return sizeof(double) * (ut + ntab * tt + 3 * p->c_pmf.size() + p->c_r0.size() +
                                  p->c_binq.size() + p->c_binm.size());
     }
+    if (p->family == PVI_FAMILY_SUBST2_L1)
+        return sizeof(double) * (b1_w_entries(p) + b1_y_entries(p) + p->b1_pa.size() +
+                                 p->b1_pc.size() + p->b1_pb.size() + p->b1_fb.size() +
+                                 p->b1_j.size() + p->b1_jc.size() + p->b1_rev.size());
     return 0;
 }
 
@@ -210,6 +271,18 @@ pvi_status family_init(pvi_mdp* p) {
             upload_vec(&d.cpb, p->c_pair_base) != hipSuccess)
             return fail(PVI_E_NOMEM, "scenario C table allocation failed");
     }
+    if (p->family == PVI_FAMILY_SUBST2_L1) {
+        if (hipMalloc((void**)&d.b1w, sizeof(double) * b1_w_entries(p)) != hipSuccess ||
+            hipMalloc((void**)&d.b1y, sizeof(double) * b1_y_entries(p)) != hipSuccess ||
+            upload_vec(&d.b1pa, p->b1_pa) != hipSuccess ||
+            upload_vec(&d.b1pc, p->b1_pc) != hipSuccess ||
+            upload_vec(&d.b1pb, p->b1_pb) != hipSuccess ||
+            upload_vec(&d.b1fb, p->b1_fb) != hipSuccess ||
+            upload_vec(&d.b1j, p->b1_j) != hipSuccess ||
+            upload_vec(&d.b1jc, p->b1_jc) != hipSuccess ||
+            upload_vec(&d.b1rev, p->b1_rev) != hipSuccess)
+            return fail(PVI_E_NOMEM, "lead-time-1 two-product table allocation failed");
+    }
     return PVI_OK;
 }
 
@@ -217,9 +290,11 @@ void family_free(pvi_mdp* p) {
     auto& d = p->dev;
     void* bufs[] = {d.z,    d.rexp0, d.epmf,  d.ecdf,  d.etail, d.rexp1, d.cu,  d.ct0,
                     d.ct1,  d.cpmf,  d.ccdf,  d.ctail, d.cr0,   d.cbinq,  d.cbinm, d.cpy,
-                    d.cpr,  d.cpb, d.agroups, d.ctf};
+                    d.cpr,  d.cpb, d.agroups, d.ctf, d.b1w, d.b1y, d.b1pa, d.b1pc,
+                    d.b1pb, d.b1fb, d.b1j, d.b1jc, d.b1rev};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    d.b1w = d.b1y = d.b1pa = d.b1pc = d.b1pb = d.b1fb = d.b1j = d.b1jc = d.b1rev = nullptr;
     d.z = d.rexp0 = d.epmf = d.ecdf = d.etail = d.rexp1 = nullptr;
     d.cu = d.ct0 = d.ct1 = d.ctf = nullptr;
     d.cpmf = d.ccdf = d.ctail = d.cr0 = d.cbinq = d.cbinm = nullptr;
@@ -255,6 +330,13 @@ hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, int fixed
         c.v_out = vout;
         c.extract = extract;
         return launch_backup_c(c, fp32, extract, s);
+    }
+    if (p->family == PVI_FAMILY_SUBST2_L1) {
+        B1Dev b = make_b1dev(p);
+        b.v_in = vin;
+        b.v_out = vout;
+        b.extract = extract;
+        return launch_backup_b1(b, fp32, extract, s);
     }
     return hipErrorInvalidValue;
 }

@@ -21,5 +21,8 @@ hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, int fixed
 // True when the family's backup kernel reduces the span itself (its last
 // workgroup applies the stopping rule), so no separate span launch follows it.
 bool family_fused_span(const pvi_mdp* p);
+// Initial values of a family whose paper-defined V0 is not zero (the lead-time-1
+// two-product family: expected one-day revenue), written into v (FP64).
+hipError_t family_initial_values(pvi_mdp* p, double* v, hipStream_t s);
 
 }  // namespace pvi

@@ -83,7 +83,8 @@ struct Tally {
 }  // namespace
 
 // FAM 0: scenario A (state [O_{L-1}..O_1, X_m..X_1]); 1: scenario B with L = 0
-// ([A_{m-1}..A_1, B_{m-1}..B_1]); 2: scenario C ([tau, X_{m-1}..X_1]).
+// ([A_{m-1}..A_1, B_{m-1}..B_1]); 2: scenario C ([tau, X_{m-1}..X_1]); 3: scenario B
+// with lead time 1 ([Xa_m..Xa_1, Xb_m..Xb_1]; X holds product a, Y product b).
 template <int FAM>
 __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -134,6 +135,19 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
                     X[j] = (int)(idx % R0);
                     idx /= R0;
                 }
+        } else if (FAM == 3) {
+#pragma unroll
+            for (int j = 1; j <= kMaxM; ++j)
+                if (j <= m) {
+                    Y[j] = (int)(idx % s.R1);
+                    idx /= s.R1;
+                }
+#pragma unroll
+            for (int j = 1; j <= kMaxM; ++j)
+                if (j <= m) {
+                    X[j] = (int)(idx % R0);
+                    idx /= R0;
+                }
         } else {
 #pragma unroll
             for (int j = 1; j < kMaxM; ++j)
@@ -167,6 +181,13 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
 #pragma unroll
                 for (int j = kMaxM - 1; j >= 1; --j)
                     if (j <= m - 1) idx = idx * s.R1 + Y[j];
+            } else if (FAM == 3) {
+#pragma unroll
+                for (int j = kMaxM; j >= 1; --j)
+                    if (j <= m) idx = idx * R0 + X[j];
+#pragma unroll
+                for (int j = kMaxM; j >= 1; --j)
+                    if (j <= m) idx = idx * s.R1 + Y[j];
             } else {
                 idx = tau;
 #pragma unroll
@@ -181,10 +202,10 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
 #pragma unroll
             for (int i = 1; i <= kMaxO; ++i) I += O[i];
             a = min(max(prm[0] - I, 0), R0 - 1);
-        } else if (FAM == 1) {  // modified base stock per product
+        } else if (FAM == 1 || FAM == 3) {  // modified base stock per product
             int IA = 0, IB = 0;
 #pragma unroll
-            for (int j = 1; j < kMaxM; ++j) {
+            for (int j = 1; j <= kMaxM; ++j) {
                 IA += X[j];
                 IB += Y[j];
             }
@@ -296,6 +317,55 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
             }
             X[kMaxM] = Y[kMaxM] = 0;
             day = Tally{dA + dB, hA + hB + hS, W, aA + aB, stA + stB - hA - hB - hS - W};
+        } else if (FAM == 3) {
+            // lead time 1: today's orders arrive for tomorrow; product b's unmet
+            // customers may take product a's units left after a's own demand
+            const int aA = a / s.R1, aB = a - aA * s.R1;
+            const int dA = sample(cdf0, s.dmax0, unif(b0.w[0]));
+            const int dB = sample(cdf1, s.dmax1, unif(b0.w[1]));
+            int stA = 0, stB = 0;
+#pragma unroll
+            for (int j = 1; j <= kMaxM; ++j) {
+                stA += X[j];
+                stB += Y[j];
+            }
+            int rem = dB;
+#pragma unroll
+            for (int j = 1; j <= kMaxM; ++j) {
+                const int take = min(rem, Y[j]);
+                Y[j] -= take;
+                rem -= take;
+            }
+            const int hB = dB - rem, excess = rem;
+            int du = 0;
+            Block bu = b0;
+            for (int i = 0; i < excess; ++i) {
+                if ((i & 3) == 0) bu = philox(s.seed, r, (uint64_t)t, (uint64_t)(1 + (i >> 2)));
+                if (unif(word(bu, i & 3)) < s.rho) ++du;
+            }
+            rem = dA + du;
+#pragma unroll
+            for (int j = 1; j <= kMaxM; ++j) {
+                const int take = min(rem, X[j]);
+                X[j] -= take;
+                rem -= take;
+            }
+            const int hA = dA + du - rem;
+            const int W = X[1] + Y[1];
+            rew = -(s.cvar0 * aA + s.cvar1 * aB) + s.rev0 * hA + s.rev1 * hB;
+#pragma unroll
+            for (int j = 1; j < kMaxM; ++j) {
+                X[j] = j < m ? X[j + 1] : 0;
+                Y[j] = j < m ? Y[j + 1] : 0;
+            }
+            X[kMaxM] = Y[kMaxM] = 0;
+#pragma unroll
+            for (int j = 1; j <= kMaxM; ++j)
+                if (j == m) {
+                    X[j] = aA;
+                    Y[j] = aB;
+                }
+            day = Tally{dA + dB, hA + hB, W, aA + aB, stA + stB - hA - hB - W};
         } else {
             const int d = sample(cdf0 + tau * (s.dmax0 + 1), s.dmax0, unif(b0.w[0]));
             int y[kMaxM + 1] = {};
@@ -400,8 +470,10 @@ hipError_t launch_rollouts(const SimDev& s, hipStream_t st) {
         hipLaunchKernelGGL(rollout_kernel<0>, grid, block, lds, st, s);
     else if (s.family == 1)
         hipLaunchKernelGGL(rollout_kernel<1>, grid, block, lds, st, s);
-    else
+    else if (s.family == 2)
         hipLaunchKernelGGL(rollout_kernel<2>, grid, block, lds, st, s);
+    else
+        hipLaunchKernelGGL(rollout_kernel<3>, grid, block, lds, st, s);
     return hipGetLastError();
 }
 

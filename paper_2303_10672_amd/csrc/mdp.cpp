@@ -347,6 +347,112 @@ static void build_c_tables(pvi_mdp* p) {
     p->logical_per_sweep = p->ns * comps * (dm + 1);
 }
 
+// Scenario B as the paper runs it (Scenario B description, Appendix B).  With I_a,
+// I_b the stock of each product, the issued units (h_a, h_b) have
+//   P(h_a, h_b) = [h_b < I_b] P(D_b = h_b) PA[I_a][h_a] + [h_b = I_b] J[I_b][I_a][h_a]
+// where PA is the demand of a capped at I_a and J is the joint probability that b
+// runs out and a issues h_a: sum over D_b = I_b + c of P(D_b) P(min(D_a + Bin(c, rho),
+// I_a) = h_a).  Cumulative forms PC, JC serve the first point of the FIFO path.
+static void build_b1_tables(pvi_mdp* p) {
+    const int m = p->m, HA = m * (p->rad[0] - 1) + 1, HB = m * (p->rad[1] - 1) + 1;
+    const double rho = p->d.subst_rho;
+    const std::vector<double>& pa = p->pmf[0];  // [d_max0 + 1]
+    const std::vector<double>& pb = p->pmf[1];
+    const int da = p->dmax[0], db = p->dmax[1];
+    p->b1_ha = HA;
+    p->b1_hb = HB;
+    auto capped_row = [&](const std::vector<double>& dist, int I, double* out) {
+        double rest = 0.0;
+        for (int h = 0; h <= I; ++h) out[h] = 0.0;
+        for (size_t t = 0; t < dist.size(); ++t) {
+            if ((int)t < I) out[t] += dist[t];
+            else rest += dist[t];
+        }
+        out[I] += rest;
+    };
+    p->b1_pa.assign((size_t)HA * HA, 0.0);
+    p->b1_pc.assign((size_t)HA * HA, 0.0);
+    for (int Ia = 0; Ia < HA; ++Ia) {
+        capped_row(pa, Ia, &p->b1_pa[(size_t)Ia * HA]);
+        double c = 0.0;
+        for (int h = 0; h < HA; ++h) p->b1_pc[(size_t)Ia * HA + h] = c += p->b1_pa[(size_t)Ia * HA + h];
+    }
+    p->b1_pb.assign(HB + 1, 0.0);
+    p->b1_fb.assign(HB + 1, 1.0);
+    {
+        double c = 0.0;
+        for (int h = 0; h <= HB; ++h) {
+            const double v = h <= db ? pb[h] : 0.0;
+            p->b1_pb[h] = v;
+            c += v;
+            p->b1_fb[h] = h >= db ? 1.0 : c;
+        }
+    }
+    // distribution of D_a plus the accepted substitutes of c unmet customers of b
+    std::vector<std::vector<double>> plus(db + 1);
+    for (int c = 0; c <= db; ++c) {
+        std::vector<double>& v = plus[c];
+        v.assign(da + c + 1, 0.0);
+        for (int u = 0; u <= c; ++u) {
+            const double pu = binom_pmf(u, c, rho);
+            if (pu == 0.0) continue;
+            for (int d = 0; d <= da; ++d) v[d + u] += pa[d] * pu;
+        }
+    }
+    p->b1_j.assign((size_t)HB * HA * HA, 0.0);
+    p->b1_jc.assign((size_t)HB * HA * HA, 0.0);
+    std::vector<double> acc(da + db + 1), row(HA);
+    for (int Ib = 0; Ib < HB; ++Ib) {
+        std::fill(acc.begin(), acc.end(), 0.0);
+        for (int d = Ib; d <= db; ++d) {
+            const std::vector<double>& v = plus[d - Ib];
+            for (size_t t = 0; t < v.size(); ++t) acc[t] += pb[d] * v[t];
+        }
+        for (int Ia = 0; Ia < HA; ++Ia) {
+            capped_row(acc, Ia, row.data());
+            double c = 0.0;
+            for (int h = 0; h < HA; ++h) {
+                const double v = h <= Ia ? row[h] : 0.0;
+                p->b1_j[((size_t)Ib * HA + Ia) * HA + h] = v;
+                p->b1_jc[((size_t)Ib * HA + Ia) * HA + h] = c += v;
+            }
+        }
+    }
+    // expected one-day revenue per (I_a, I_b): the reward without the order cost,
+    // and the initial values of the solve
+    p->b1_rev.assign((size_t)HA * HB, 0.0);
+    const double ra = p->d.c_rev[0], rb = p->d.c_rev[1];
+    for (int Ia = 0; Ia < HA; ++Ia)
+        for (int Ib = 0; Ib < HB; ++Ib) {
+            double e = 0.0;
+            for (int hb = 0; hb < Ib; ++hb)
+                for (int ha = 0; ha <= Ia; ++ha)
+                    e += p->b1_pb[hb] * p->b1_pa[(size_t)Ia * HA + ha] * (ra * ha + rb * hb);
+            for (int ha = 0; ha <= Ia; ++ha)
+                e += p->b1_j[((size_t)Ib * HA + Ia) * HA + ha] * (ra * ha + rb * Ib);
+            p->b1_rev[(size_t)Ia * HB + Ib] = e;
+        }
+    // multiply-adds per sweep: stage W (one per B path point below I_b), stage Y (one
+    // per A path point per I_b), the final sum (one per A path point per action, plus Y)
+    const int64_t NA = p->ns / ipow_i(p->rad[1], m), NB = ipow_i(p->rad[1], m);
+    int64_t pts_a = 0, pts_b = 0;  // path points summed over all stock vectors
+    for (int64_t x = 0; x < NA; ++x) {
+        int64_t v = x;
+        int sum = 0, x1 = (int)(v % p->rad[0]);
+        for (int i = 0; i < m; ++i, v /= p->rad[0]) sum += (int)(v % p->rad[0]);
+        pts_a += sum - x1 + 1;
+    }
+    for (int64_t x = 0; x < NB; ++x) {
+        int64_t v = x;
+        int sum = 0, x1 = (int)(v % p->rad[1]);
+        for (int i = 0; i < m; ++i, v /= p->rad[1]) sum += (int)(v % p->rad[1]);
+        pts_b += sum > 0 ? std::max(sum - x1, 1) : 0;
+    }
+    const int64_t na1 = NA / p->rad[0];
+    p->executed_per_sweep = (int64_t)p->na * (na1 * pts_b + HB * pts_a + NB * (pts_a + NA));
+    p->logical_per_sweep = p->ns * p->na * (int64_t)HA * HB;
+}
+
 }  // namespace pvi
 
 using namespace pvi;
@@ -369,15 +475,17 @@ pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out) {
         return fail(PVI_E_INVALID, "mdp_create: issuing must be PVI_FIFO or PVI_LIFO");
     if (d.issuing == PVI_LIFO && d.family != PVI_FAMILY_LEADTIME)
         return fail(PVI_E_INVALID, "mdp_create: LIFO issuing is defined for scenario A only");
-    if (d.family < 0 || d.family > 2) return fail(PVI_E_INVALID, "mdp_create: bad family");
+    if (d.family < 0 || d.family > 3) return fail(PVI_E_INVALID, "mdp_create: bad family");
     if (d.m < 1 || d.m > PVI_MAX_LIFE) return fail(PVI_E_INVALID, "mdp_create: m out of range");
-    if (!(d.gamma > 0.0 && d.gamma < 1.0))
-        return fail(PVI_E_INVALID, "mdp_create: gamma must be in (0, 1)");
+    const bool b1 = d.family == PVI_FAMILY_SUBST2_L1;
+    if (!(d.gamma > 0.0 && (d.gamma < 1.0 || (b1 && d.gamma == 1.0))))
+        return fail(PVI_E_INVALID, b1 ? "mdp_create: gamma must be in (0, 1]"
+                                      : "mdp_create: gamma must be in (0, 1)");
     const double costs[] = {d.c_var[0], d.c_var[1], d.c_fixed, d.c_hold, d.c_short,
                             d.c_waste, d.c_rev[0], d.c_rev[1], d.subst_rho};
     for (double c : costs)
         if (!is_finite(c)) return fail(PVI_E_INVALID, "mdp_create: non-finite cost");
-    const int nprod = d.family == PVI_FAMILY_SUBST2 ? 2 : 1;
+    const int nprod = (d.family == PVI_FAMILY_SUBST2 || b1) ? 2 : 1;
     for (int k = 0; k < nprod; ++k) {
         if (d.a_max[k] < 0 || d.a_max[k] > 31)
             return fail(PVI_E_INVALID, "mdp_create: a_max must be in 0..31");
@@ -389,6 +497,10 @@ pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out) {
         if (d.lead_time < 1) return fail(PVI_E_INVALID, "mdp_create: scenario A needs L >= 1");
         if (d.m + d.lead_time - 1 > 12)
             return fail(PVI_E_INVALID, "mdp_create: too many state digits");
+    } else if (b1) {
+        if (d.lead_time != 1)
+            return fail(PVI_E_INVALID, "mdp_create: the lead-time-1 two-product family needs L = 1");
+        if (2 * d.m > 16) return fail(PVI_E_INVALID, "mdp_create: too many state digits");
     } else {
         if (d.lead_time != 0)
             return fail(PVI_E_INVALID, "mdp_create: scenarios B and C need L = 0");
@@ -401,7 +513,7 @@ pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out) {
     } else if (d.n_periods != 1 && d.n_periods != 0) {
         return fail(PVI_E_INVALID, "mdp_create: n_periods must be 1 for scenarios A and B");
     }
-    if (d.family == PVI_FAMILY_SUBST2 && !(d.subst_rho >= 0.0 && d.subst_rho <= 1.0))
+    if ((d.family == PVI_FAMILY_SUBST2 || b1) && !(d.subst_rho >= 0.0 && d.subst_rho <= 1.0))
         return fail(PVI_E_INVALID, "mdp_create: subst_rho must be in [0, 1]");
 
     pvi_mdp* p = new (std::nothrow) pvi_mdp();
@@ -426,6 +538,12 @@ pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out) {
             p->radix[i] = p->rad[0];
             p->radix[d.m - 1 + i] = p->rad[1];
         }
+    } else if (b1) {
+        p->ndig = 2 * d.m;
+        for (int i = 0; i < d.m; ++i) {
+            p->radix[i] = p->rad[0];
+            p->radix[d.m + i] = p->rad[1];
+        }
     } else {
         p->ndig = d.m;
         p->radix[0] = P;
@@ -439,7 +557,7 @@ pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out) {
             return fail(PVI_E_INVALID, "mdp_create: more than 2^31 states");
         }
     }
-    p->na = d.family == PVI_FAMILY_SUBST2 ? p->rad[0] * p->rad[1] : p->rad[0];
+    p->na = nprod == 2 ? p->rad[0] * p->rad[1] : p->rad[0];
     // demand PMFs
     std::string err;
     for (int k = 0; k < nprod; ++k) {
@@ -481,6 +599,7 @@ pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out) {
     if (d.family == PVI_FAMILY_LEADTIME) build_a_tables(p);
     if (d.family == PVI_FAMILY_SUBST2 && d.m >= 2) build_b_tables(p);
     if (d.family == PVI_FAMILY_RUL_WEEKDAY) build_c_tables(p);
+    if (b1) build_b1_tables(p);
     *out = p;
     return PVI_OK;
 }
@@ -520,7 +639,8 @@ pvi_status mdp_decode(const pvi_mdp* p, int64_t idx, int32_t* digits) {
 
 pvi_status mdp_demand_pmf(const pvi_mdp* p, int32_t product, int32_t period, double* out) {
     if (!p || !out) return fail(PVI_E_INVALID, "mdp_demand_pmf: NULL argument");
-    const int nprod = p->family == PVI_FAMILY_SUBST2 ? 2 : 1;
+    const int nprod =
+        (p->family == PVI_FAMILY_SUBST2 || p->family == PVI_FAMILY_SUBST2_L1) ? 2 : 1;
     if (product < 0 || product >= nprod || period < 0 || period >= p->P)
         return fail(PVI_E_INVALID, "mdp_demand_pmf: product or period out of range");
     const int n = p->dmax[product] + 1;

@@ -40,6 +40,10 @@ struct pvi_mdp {
     std::vector<double> c_pmf, c_cdf, c_tail, c_r0, c_binq, c_binm;
     std::vector<int32_t> c_pair_y, c_pair_r, c_pair_base;
 
+    // Scenario B as the paper runs it (lead time 1): issue probabilities and revenue
+    int b1_ha = 0, b1_hb = 0;  // m a_max + 1 per product
+    std::vector<double> b1_pa, b1_pc, b1_pb, b1_fb, b1_j, b1_jc, b1_rev;
+
     int64_t logical_per_sweep = 0;
     int64_t executed_per_sweep = 0;
 
@@ -67,6 +71,9 @@ struct pvi_mdp {
         double *cpmf = nullptr, *ccdf = nullptr, *ctail = nullptr, *cr0 = nullptr,
                *cbinq = nullptr, *cbinm = nullptr;
         int32_t *cpy = nullptr, *cpr = nullptr, *cpb = nullptr;
+        double *b1w = nullptr, *b1y = nullptr, *b1pa = nullptr, *b1pc = nullptr,
+               *b1pb = nullptr, *b1fb = nullptr, *b1j = nullptr, *b1jc = nullptr,
+               *b1rev = nullptr;
         int tiles = 0;
         size_t bytes = 0;
         std::vector<hipEvent_t> ev;

@@ -125,6 +125,31 @@ struct CDev {
     double gamma, cfixed;
 };
 
+// ------------------------------------------------------------------ family B, lead time 1
+struct B1Dev {
+    const void* v_in;
+    void* v_out;
+    int32_t* pi;
+    double* gap;
+    double* partials;     // [NB * ceil(NA / 256)][4]
+    double* w;            // [Ra][Rb][NB][na1]: sum over h_b < I_b of V, per next A part
+    double* y;            // [Ra][Rb][HB][NA]: the b-runs-out term per I_b
+    const double* pa;     // [HA][HA] demand of a capped at I_a
+    const double* pc;     // [HA][HA] its cumulative sum
+    const double* pb;     // [HB + 1] demand of b
+    const double* fb;     // [HB + 1] its CDF
+    const double* j;      // [HB][HA][HA] P(h_a, h_b = I_b | I_a, I_b)
+    const double* jc;     // [HB][HA][HA] cumulative over h_a
+    const double* rev;    // [HA][HB] expected one-day revenue
+    Ctl* ctl;
+    int32_t m, Ra, Rb, HA, HB, na1, nb1, NA, NB, extract;
+    int32_t gw;           // stage W: values of the next A part per workgroup
+    int32_t cb;           // final stage: orders of b per LDS chunk
+    double gamma, cva, cvb;
+};
+hipError_t launch_backup_b1(const B1Dev& p, int storage_fp32, int extract, hipStream_t s);
+hipError_t launch_b1_initial(const B1Dev& p, double* v, hipStream_t s);
+
 // ------------------------------------------------------------------ rollouts
 struct SimDev {
     int32_t family, m, L, P, kind, issuing;

@@ -39,7 +39,9 @@ struct SimBuffers {
 pvi_status check_kind(const pvi_mdp* p, int kind) {
     if (kind == PVI_POLICY_TABLE) return PVI_OK;
     if (kind == PVI_POLICY_BASE_STOCK && p->family == PVI_FAMILY_LEADTIME) return PVI_OK;
-    if (kind == PVI_POLICY_MOD_BASE_STOCK && p->family == PVI_FAMILY_SUBST2) return PVI_OK;
+    if (kind == PVI_POLICY_MOD_BASE_STOCK &&
+        (p->family == PVI_FAMILY_SUBST2 || p->family == PVI_FAMILY_SUBST2_L1))
+        return PVI_OK;
     if (kind == PVI_POLICY_S_S && p->family == PVI_FAMILY_RUL_WEEKDAY) return PVI_OK;
     return fail(PVI_E_INVALID, "policy_rollouts: the policy kind does not suit the family");
 }
@@ -71,7 +73,8 @@ pvi_status run_rollouts(pvi_mdp* p, const pvi_rollout_opts* o, double* stats, do
     if (p->m > PVI_MAX_LIFE || (p->family == PVI_FAMILY_LEADTIME && p->L - 1 > 11))
         return fail(PVI_E_INVALID, w + ": state too long for the simulator");
 
-    const int R0 = p->rad[0], R1 = p->family == PVI_FAMILY_SUBST2 ? p->rad[1] : 1;
+    const bool two = p->family == PVI_FAMILY_SUBST2 || p->family == PVI_FAMILY_SUBST2_L1;
+    const int R0 = p->rad[0], R1 = two ? p->rad[1] : 1;
     // demand CDFs, summed left to right over the PMF of each period
     const int P = p->family == PVI_FAMILY_RUL_WEEKDAY ? p->P : 1;
     std::vector<double> cdf0((size_t)P * (p->dmax[0] + 1)), cdf1;
@@ -82,7 +85,7 @@ pvi_status run_rollouts(pvi_mdp* p, const pvi_rollout_opts* o, double* stats, do
             cdf0[(size_t)t * (p->dmax[0] + 1) + d] = c;
         }
     }
-    if (p->family == PVI_FAMILY_SUBST2) {
+    if (two) {
         cdf1.resize(p->dmax[1] + 1);
         double c = 0.0;
         for (int d = 0; d <= p->dmax[1]; ++d) cdf1[d] = c += p->pmf[1][d];
@@ -126,7 +129,10 @@ pvi_status run_rollouts(pvi_mdp* p, const pvi_rollout_opts* o, double* stats, do
         s = B.own;
     }
     SimDev d{};
-    d.family = p->family == PVI_FAMILY_LEADTIME ? 0 : p->family == PVI_FAMILY_SUBST2 ? 1 : 2;
+    d.family = p->family == PVI_FAMILY_LEADTIME     ? 0
+               : p->family == PVI_FAMILY_SUBST2       ? 1
+               : p->family == PVI_FAMILY_RUL_WEEKDAY  ? 2
+                                                      : 3;
     d.m = p->m;
     d.L = p->L;
     d.P = P;
@@ -135,7 +141,7 @@ pvi_status run_rollouts(pvi_mdp* p, const pvi_rollout_opts* o, double* stats, do
     d.R0 = R0;
     d.R1 = R1;
     d.dmax0 = p->dmax[0];
-    d.dmax1 = p->family == PVI_FAMILY_SUBST2 ? p->dmax[1] : 0;
+    d.dmax1 = two ? p->dmax[1] : 0;
     d.n_pol = n_pol;
     d.n_roll = o->n_rollouts;
     d.warmup = o->warmup_days;

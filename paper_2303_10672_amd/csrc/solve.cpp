@@ -309,7 +309,10 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
     auto& d = p->dev;
     hipStream_t s = o->stream ? (hipStream_t)o->stream : d.own;
     const double g = p->d.gamma;
-    const double thr = o->stop_rule == PVI_STOP_SPAN ? o->eps * (1.0 - g) / g : o->eps;
+    // span rule: eps (1 - gamma)/gamma; undiscounted (gamma = 1), span < eps as in
+    // Appendix B's test
+    const double thr =
+        o->stop_rule == PVI_STOP_SPAN && g < 1.0 ? o->eps * (1.0 - g) / g : o->eps;
     const bool periodic = o->stop_rule == PVI_STOP_PERIODIC && o->fixed_sweeps <= 0;
     const int period = p->P > 0 ? p->P : 1;
     if (periodic && (st = ensure_ring(p, period + 1)) != PVI_OK) return st;
@@ -322,6 +325,10 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
     if (o->v0) {
         PVI_HIP(hipMemcpyAsync(d.v64[0], o->v0, sizeof(double) * p->ns, hipMemcpyHostToDevice, s));
         c0 = midrange(o->v0, p->ns);
+    } else if (p->family == PVI_FAMILY_SUBST2_L1) {
+        PVI_HIP(family_initial_values(p, d.v64[0], s));
+        const auto mm = std::minmax_element(p->b1_rev.begin(), p->b1_rev.end());
+        c0 = 0.5 * (*mm.first + *mm.second);
     } else {
         PVI_HIP(launch_fill(d.v64[0], 0.0, p->ns, s));
     }

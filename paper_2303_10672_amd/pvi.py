@@ -20,7 +20,7 @@ PVI_OK, PVI_E_INVALID, PVI_E_NOMEM, PVI_E_DEVICE = 0, 1, 2, 3
 PVI_E_NOT_CONVERGED, PVI_E_NOT_READY, PVI_E_CANCELLED, PVI_E_BUSY = 4, 5, 6, 7
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGED",
                 5: "NOT_READY", 6: "CANCELLED", 7: "BUSY"}
-FAMILY = {"A": 0, "B": 1, "C": 2}
+FAMILY = {"A": 0, "B": 1, "C": 2, "B1": 3}
 DEMAND = {"none": 0, "poisson": 1, "gamma": 2, "negbin": 3, "table": 4}
 ISSUING = {"fifo": 0, "lifo": 1}
 STOP_RULE = {"span": 0, "supnorm": 1, "periodic": 2}

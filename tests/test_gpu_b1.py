@@ -1,0 +1,161 @@
+"""GPU parity of Scenario B as the paper runs it (lead time 1, outcome = units issued,
+gamma = 1, V0 = expected revenue, span stop) through the C ABI, against the oracle.
+
+Tolerances as for the other families: one FP64 backup 1e-12 normwise, FP32 storage
+1e-6; converged FP64 solves match the oracle's sweep count and V to 1e-12 and its
+policy wherever the oracle's gap exceeds 1e-6.  At the paper's m = 3 sizes (up to
+16,777,216 states) sampled states are checked one by one, and the converged solve by
+the span certificate: with V_n - V_{n-1} in [dmin, dmax], one more backup moves
+every state by an amount in [gamma dmin, gamma dmax].  The GPU-solved policies,
+rolled out on the GPU, must reproduce the paper's printed returns.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.oracle import Oracle
+from paper_2303_10672_amd import pvi
+
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_rollouts.json")))
+
+SMALL = [
+    W.scenario_b1(m=2, a_max=(2, 3), means=(1.5, 2.0), rho=0.5, d_max=7, gamma=0.9),
+    W.scenario_b1(m=3, a_max=(2, 1), means=(2.0, 1.0), rho=0.3, d_max=6, gamma=1.0),
+    W.scenario_b1(m=2, a_max=(5, 4), means=(3.0, 2.0), rho=0.7, d_max=12, gamma=0.95),
+    W.scenario_b1(m=1, a_max=(6, 5), means=(3.0, 2.5), rho=0.5, d_max=10, gamma=0.9),
+    W.scenario_b1(m=3, a_max=(3, 2), means=(2.0, 1.5), rho=0.0, d_max=8, gamma=1.0),
+]
+IDS = ["m2", "m3-g1", "m2-R6", "m1", "m3-rho0"]
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("sc", SMALL, ids=IDS)
+def test_one_backup(sc):
+    o = Oracle(sc)
+    m = pvi.mdp_create(sc)
+    for seed in (41, 42):
+        V = W.random_values(o.n_states, seed=seed, scale=5.0, offset=20.0)
+        Vo, pio, gapo = o.sweep(V)
+        Vg, pig, gapg = pvi.vi_backup(m, V, "fp64")
+        assert relerr(Vg, Vo) < 1e-12
+        clear = gapo > 1e-9
+        assert np.array_equal(pig[clear], pio[clear])
+        assert np.allclose(gapg[clear], gapo[clear], rtol=1e-8, atol=1e-9)
+        V32, _, _ = pvi.vi_backup(m, V, "fp32")
+        assert relerr(V32, Vo) < 1e-6
+
+
+@pytest.mark.parametrize("sc", SMALL, ids=IDS)
+def test_converged_from_expected_revenue(sc):
+    o = Oracle(sc)
+    ref = o.solve()
+    m = pvi.mdp_create(sc)
+    res = pvi.vi_solve(m, precision="fp64")
+    assert res["status"] == pvi.PVI_OK
+    assert res["sweeps_fp64"] == ref["sweeps"]
+    assert relerr(pvi.value_get(m), ref["V"]) < 1e-12
+    pol, _ = pvi.policy_get(m)
+    clear = ref["gap"] > 1e-6
+    assert np.array_equal(pol[clear], ref["pi"][clear])
+    res = pvi.vi_solve(m, precision="fp32")
+    assert res["status"] == pvi.PVI_OK and res["final_span"] < res["threshold"]
+    pol, _ = pvi.policy_get(m)
+    clear = ref["gap"] > 1e-3
+    assert np.array_equal(pol[clear], ref["pi"][clear])
+
+
+@pytest.mark.parametrize("exp", ["1", "2"])
+def test_paper_m2_converged(exp):
+    sc = W.scenario_b_paper(2, exp)
+    o = Oracle(sc)
+    ref = o.solve()
+    m = pvi.mdp_create(sc)
+    assert (m.n_states, m.n_actions) == ({"1": 14641, "2": 11025}[exp],
+                                         {"1": 121, "2": 105}[exp])
+    res = pvi.vi_solve(m, precision="fp64")
+    assert res["sweeps_fp64"] == ref["sweeps"]
+    assert res["threshold"] == 1e-4                     # gamma = 1: span < eps
+    assert relerr(pvi.value_get(m), ref["V"]) < 1e-12
+    pol, _ = pvi.policy_get(m)
+    clear = ref["gap"] > 1e-6
+    assert clear.mean() > 0.9
+    assert np.array_equal(pol[clear], ref["pi"][clear])
+
+
+def test_ortega_p1_hundred_sweeps():
+    """Experiment P1: exactly 100 sweeps from V0 = expected revenue."""
+    sc = W.scenario_b_paper(2, "P1")
+    ref = Oracle(sc).solve(fixed_sweeps=100)
+    m = pvi.mdp_create(sc)
+    res = pvi.vi_solve(m, precision="fp64", fixed_sweeps=100)
+    assert res["sweeps_fp64"] == 100 == ref["sweeps"]
+    assert relerr(pvi.value_get(m), ref["V"]) < 1e-12
+
+
+@pytest.mark.parametrize("exp,n", [("4", 1157625), ("1", 16777216)])
+def test_paper_m3_sampled(exp, n):
+    sc = W.scenario_b_paper(3, exp)
+    o = Oracle(sc)
+    m = pvi.mdp_create(sc)
+    assert m.n_states == o.n_states == n
+    V = W.random_values(n, seed=43, scale=5.0, offset=30.0)
+    Vg, pig, _ = pvi.vi_backup(m, V, "fp64")
+    idx = W.sample_indices(n, 60, seed=43)
+    Q = o.q_states(V, idx)
+    assert relerr(Vg[idx], Q.max(axis=1)) < 1e-12
+    Qs = np.sort(Q, axis=1)
+    clear = (Qs[:, -1] - Qs[:, -2]) > 1e-9
+    assert np.array_equal(pig[idx][clear], Q.argmax(axis=1)[clear])
+    res = pvi.vi_solve(m, precision="fp64")
+    assert res["status"] == pvi.PVI_OK and res["final_span"] < 1e-4
+    Vc = pvi.value_get(m)
+    pol, _ = pvi.policy_get(m)
+    idx = W.sample_indices(n, 60, seed=44)
+    Q = o.q_states(Vc, idx)
+    step = Q.max(axis=1) - Vc[idx]
+    g, tol = sc["gamma"], 1e-9
+    assert np.all(step >= g * res["dmin"] - tol) and np.all(step <= g * res["dmax"] + tol)
+    Qs = np.sort(Q, axis=1)
+    clear = (Qs[:, -1] - Qs[:, -2]) > 2 * (res["dmax"] - res["dmin"]) + 1e-9
+    assert np.array_equal(pol[idx][clear], Q.argmax(axis=1)[clear])
+
+
+def test_rollouts_match_oracle():
+    sc = W.scenario_b1(m=2, a_max=(5, 4), means=(3.0, 2.0), rho=0.6, d_max=12)
+    o = Oracle(sc)
+    m = pvi.mdp_create(sc)
+    rng = np.random.default_rng([19, 0])
+    table = rng.integers(0, o.n_actions, size=o.n_states).astype(np.int32)
+    g = pvi.policy_rollouts(m, table=table, n_rollouts=300, warmup=10, horizon=80, seed=5)
+    ret, kpi = o.simulate("table", table=table, n_rollouts=300, warmup=10, horizon=80, seed=5)
+    assert np.allclose(g["ret"], ret, rtol=1e-12, atol=1e-9)
+    assert np.array_equal(g["kpi"], kpi)
+    grid = [[a, b] for a in range(0, 11, 2) for b in range(0, 9, 2)]
+    g = pvi.policy_rollouts(m, policy="mod_base_stock", params=grid, n_rollouts=200, seed=6)
+    ret, kpi = o.simulate("mod_base_stock", params=grid, n_rollouts=200, seed=6)
+    assert np.allclose(g["ret"], ret, rtol=1e-12, atol=1e-9)
+    assert np.array_equal(g["kpi"], kpi)
+
+
+def _close(ours, printed, sd):
+    return abs(ours - printed) <= 4.0 * sd * np.sqrt(2.0 / 10000) + 0.5
+
+
+@pytest.mark.parametrize("m_exp,paper", [
+    ((2, "1"), [1644, 33]), ((3, "4"), [1762, 32]), ((3, "1"), [1761, 32])])
+def test_paper_runs_end_to_end(m_exp, paper):
+    """Results table of Appendix B: 10,000 rollouts of the GPU-solved policy."""
+    sc = W.scenario_b_paper(*m_exp)
+    m = pvi.mdp_create(sc)
+    pvi.vi_solve(m, precision="fp64")
+    st = pvi.policy_rollouts(m, n_rollouts=10000, seed=1, per_rollout=False)["stats"][0]
+    assert _close(st[0], paper[0], st[1])
+    assert abs(st[1] - paper[1]) <= 2.0
