@@ -89,15 +89,24 @@ static B1Dev make_b1dev(const pvi_mdp* p) {
     b.NA = (int)ipow(b.Ra, m);
     b.NB = (int)ipow(b.Rb, m);
     b.gw = std::max(1, std::min(b.na1, 4096 / std::max(1, b.nb1)));
-    b.cb = std::max(1, std::min({16, b.Rb, 8192 / std::max(1, b.na1)}));
+    // the final stage keeps cb orders' W slices (rows of cbp doubles) and three demand
+    // tables in 64 KB of LDS
+    auto stride = [](int cb) {
+        int c = (cb + 1) / 2 * 2;
+        return c % 4 == 0 ? c + 2 : c;
+    };
+    b.cb = std::min(16, b.Rb);
+    while (b.cb > 1 && (int64_t)b.na1 * stride(b.cb) + 3 * (b.HA + 1) > 8192) --b.cb;
+    b.cbp = stride(b.cb);
     b.gamma = p->d.gamma;
     b.cva = p->d.c_var[0];
     b.cvb = p->d.c_var[1];
     const auto& d = p->dev;
     b.w = d.b1w;
     b.y = d.b1y;
-    b.pa = d.b1pa;
-    b.pc = d.b1pc;
+    b.pa1 = d.b1pa;
+    b.fa = d.b1fa;
+    b.ga = d.b1ga;
     b.pb = d.b1pb;
     b.fb = d.b1fb;
     b.j = d.b1j;
@@ -178,7 +187,7 @@ std::string family_support_msg(const pvi_mdp* p) {
         const int64_t na1 = ipow(p->rad[0], p->m - 1), nb1 = ipow(p->rad[1], p->m - 1);
         if (ipow(p->rad[1], p->m) > 65535)
             return "the lead-time-1 two-product family needs (a_max[1]+1)^m <= 65535 on the GPU";
-        if (na1 > 8192 || nb1 > 4096)
+        if (2 * na1 + 3 * (p->b1_ha + 1) > 8192 || nb1 > 4096)
             return "the lead-time-1 two-product family: aged stock of one product exceeds LDS";
         return "ok";
     }
@@ -225,8 +234,8 @@ size_t family_extra_bytes(const pvi_mdp* p) {
                                  p->c_binq.size() + p->c_binm.size());
     }
     if (p->family == PVI_FAMILY_SUBST2_L1)
-        return sizeof(double) * (b1_w_entries(p) + b1_y_entries(p) + p->b1_pa.size() +
-                                 p->b1_pc.size() + p->b1_pb.size() + p->b1_fb.size() +
+        return sizeof(double) * (b1_w_entries(p) + b1_y_entries(p) + 3 * p->b1_pa1.size() +
+                                 p->b1_pb.size() + p->b1_fb.size() +
                                  p->b1_j.size() + p->b1_jc.size() + p->b1_rev.size());
     return 0;
 }
@@ -274,8 +283,9 @@ pvi_status family_init(pvi_mdp* p) {
     if (p->family == PVI_FAMILY_SUBST2_L1) {
         if (hipMalloc((void**)&d.b1w, sizeof(double) * b1_w_entries(p)) != hipSuccess ||
             hipMalloc((void**)&d.b1y, sizeof(double) * b1_y_entries(p)) != hipSuccess ||
-            upload_vec(&d.b1pa, p->b1_pa) != hipSuccess ||
-            upload_vec(&d.b1pc, p->b1_pc) != hipSuccess ||
+            upload_vec(&d.b1pa, p->b1_pa1) != hipSuccess ||
+            upload_vec(&d.b1fa, p->b1_fa) != hipSuccess ||
+            upload_vec(&d.b1ga, p->b1_ga) != hipSuccess ||
             upload_vec(&d.b1pb, p->b1_pb) != hipSuccess ||
             upload_vec(&d.b1fb, p->b1_fb) != hipSuccess ||
             upload_vec(&d.b1j, p->b1_j) != hipSuccess ||
@@ -290,11 +300,12 @@ void family_free(pvi_mdp* p) {
     auto& d = p->dev;
     void* bufs[] = {d.z,    d.rexp0, d.epmf,  d.ecdf,  d.etail, d.rexp1, d.cu,  d.ct0,
                     d.ct1,  d.cpmf,  d.ccdf,  d.ctail, d.cr0,   d.cbinq,  d.cbinm, d.cpy,
-                    d.cpr,  d.cpb, d.agroups, d.ctf, d.b1w, d.b1y, d.b1pa, d.b1pc,
+                    d.cpr,  d.cpb, d.agroups, d.ctf, d.b1w, d.b1y, d.b1pa, d.b1fa, d.b1ga,
                     d.b1pb, d.b1fb, d.b1j, d.b1jc, d.b1rev};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
-    d.b1w = d.b1y = d.b1pa = d.b1pc = d.b1pb = d.b1fb = d.b1j = d.b1jc = d.b1rev = nullptr;
+    d.b1w = d.b1y = d.b1pa = d.b1fa = d.b1ga = d.b1pb = d.b1fb = d.b1j = d.b1jc = d.b1rev =
+        nullptr;
     d.z = d.rexp0 = d.epmf = d.ecdf = d.etail = d.rexp1 = nullptr;
     d.cu = d.ct0 = d.ct1 = d.ctf = nullptr;
     d.cpmf = d.ccdf = d.ctail = d.cr0 = d.cbinq = d.cbinm = nullptr;

@@ -139,19 +139,33 @@ __global__ __launch_bounds__(256) void b1_stage_y_kernel(B1Dev p) {
 }
 
 // Q over the joint orders and the max, one lane per x_a, one workgroup row per x_b.
+// The W slice of a chunk of orders of b sits in LDS point-major ([g][order], rows
+// padded to an odd number of 16-byte units so the four paths of a wavefront fall in
+// different banks), so a path point feeds the chunk's accumulators from one
+// contiguous run; the weights
+// come from the 1-D demand tables of a in LDS: F(x_1) at the first point (all of the
+// mass when no older stock is left), P(x_1 + k) inside, P(D >= I_a) at the last.
+// The 16 lanes that differ only in X_1 share the path, so their LDS reads coincide.
 template <typename VT, bool EXTRACT>
 __global__ __launch_bounds__(256) void b1_final_kernel(B1Dev p) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[64];
     if (!EXTRACT && p.ctl->stop) return;
-    double* ws = reinterpret_cast<double*>(smem);  // [cb][na1]
+    double* ws = reinterpret_cast<double*>(smem);  // [na1][cbp]
+    double* wp = ws + (size_t)p.na1 * p.cbp;       // [HA + 1] P(D_a = h)
+    double* wf = wp + (p.HA + 1);                  // [HA + 1] P(D_a <= h)
+    double* wg = wf + (p.HA + 1);                  // [HA + 1] P(D_a >= h)
+    for (int i = threadIdx.x; i <= p.HA; i += blockDim.x) {
+        wp[i] = p.pa1[i];
+        wf[i] = p.fa[i];
+        wg[i] = p.ga[i];
+    }
     const int xb = blockIdx.y;
     const int xa = blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = xa < p.NA;
     const Digits da = digits_of(ok ? xa : 0, p.Ra, p.m);
     const Digits db = digits_of(xb, p.Rb, p.m);
     const int Ia = da.sum, Ib = db.sum, x1 = da.d[0], K = Ia - x1, g0 = (ok ? xa : 0) / p.Ra;
-    const double* PA = p.pa + (size_t)Ia * p.HA;
     const double rev = p.rev[(size_t)Ia * p.HB + Ib];
     double best = -DBL_MAX, second = -DBL_MAX;
     int arg = 0;
@@ -161,25 +175,26 @@ __global__ __launch_bounds__(256) void b1_final_kernel(B1Dev p) {
             __syncthreads();
             for (int i = threadIdx.x; i < nb * p.na1; i += blockDim.x) {
                 const int jb = i / p.na1, g = i - jb * p.na1;
-                ws[i] = p.w[((int64_t)(aa * p.Rb + ab0 + jb) * p.NB + xb) * p.na1 + g];
+                ws[g * p.cbp + jb] = p.w[((int64_t)(aa * p.Rb + ab0 + jb) * p.NB + xb) * p.na1 + g];
             }
             __syncthreads();
             if (!ok) continue;
             double acc[kCB];
+            {
+                const double w0 = K > 0 ? wf[x1] : 1.0;
+                const double* row = ws + g0 * p.cbp;
 #pragma unroll
-            for (int jb = 0; jb < kCB; ++jb) acc[jb] = 0.0;
+                for (int jb = 0; jb < kCB; ++jb) acc[jb] = jb < nb ? w0 * row[jb] : 0.0;
+            }
             int off = g0;
-            double wgt = p.pc[(size_t)Ia * p.HA + x1];
-#pragma unroll
-            for (int jb = 0; jb < kCB; ++jb)
-                if (jb < nb) acc[jb] = wgt * ws[jb * p.na1 + off];
             PathWalk w{1, da.d[1], 1};
             for (int k = 1; k <= K; ++k) {
                 off -= step(w, da, p.Ra);
-                wgt = PA[x1 + k];
+                const double wgt = k < K ? wp[x1 + k] : wg[Ia];
+                const double* row = ws + off * p.cbp;
 #pragma unroll
                 for (int jb = 0; jb < kCB; ++jb)
-                    if (jb < nb) acc[jb] = fma(wgt, ws[jb * p.na1 + off], acc[jb]);
+                    if (jb < nb) acc[jb] = fma(wgt, row[jb], acc[jb]);
             }
 #pragma unroll
             for (int jb = 0; jb < kCB; ++jb) {
@@ -237,11 +252,11 @@ __global__ __launch_bounds__(256) void b1_initial_kernel(B1Dev p, double* v) {
 
 template <typename VT, bool EXTRACT>
 static hipError_t launch_b1_t(const B1Dev& p, hipStream_t s) {
-    if (p.m < 1 || p.m > kMaxM || p.cb < 1 || p.cb > kCB || p.gw < 1)
+    if (p.m < 1 || p.m > kMaxM || p.cb < 1 || p.cb > kCB || p.cbp < p.cb || p.gw < 1)
         return hipErrorInvalidConfiguration;
     const size_t lw = sizeof(double) * (size_t)p.gw * p.nb1;
     const size_t ly = sizeof(double) * (size_t)p.na1;
-    const size_t lf = sizeof(double) * (size_t)p.cb * p.na1;
+    const size_t lf = sizeof(double) * ((size_t)p.cbp * p.na1 + 3 * (size_t)(p.HA + 1));
     if (lw > 65536 || ly > 65536 || lf > 65536) return hipErrorInvalidConfiguration;
     const unsigned nact = (unsigned)(p.Ra * p.Rb);
     hipLaunchKernelGGL((b1_stage_w_kernel<VT>), dim3((p.na1 + p.gw - 1) / p.gw, nact), dim3(256),

@@ -352,7 +352,8 @@ static void build_c_tables(pvi_mdp* p) {
 //   P(h_a, h_b) = [h_b < I_b] P(D_b = h_b) PA[I_a][h_a] + [h_b = I_b] J[I_b][I_a][h_a]
 // where PA is the demand of a capped at I_a and J is the joint probability that b
 // runs out and a issues h_a: sum over D_b = I_b + c of P(D_b) P(min(D_a + Bin(c, rho),
-// I_a) = h_a).  Cumulative forms PC, JC serve the first point of the FIFO path.
+// I_a) = h_a).  The cumulative form JC serves the first point of the FIFO path; the
+// kernels weight a's own demand from the 1-D tables P(D_a = h), P(D_a <= h), P(D_a >= h).
 static void build_b1_tables(pvi_mdp* p) {
     const int m = p->m, HA = m * (p->rad[0] - 1) + 1, HB = m * (p->rad[1] - 1) + 1;
     const double rho = p->d.subst_rho;
@@ -371,11 +372,23 @@ static void build_b1_tables(pvi_mdp* p) {
         out[I] += rest;
     };
     p->b1_pa.assign((size_t)HA * HA, 0.0);
-    p->b1_pc.assign((size_t)HA * HA, 0.0);
-    for (int Ia = 0; Ia < HA; ++Ia) {
-        capped_row(pa, Ia, &p->b1_pa[(size_t)Ia * HA]);
+    for (int Ia = 0; Ia < HA; ++Ia) capped_row(pa, Ia, &p->b1_pa[(size_t)Ia * HA]);
+    p->b1_pa1.assign(HA + 1, 0.0);
+    p->b1_fa.assign(HA + 1, 1.0);
+    p->b1_ga.assign(HA + 1, 0.0);
+    {
         double c = 0.0;
-        for (int h = 0; h < HA; ++h) p->b1_pc[(size_t)Ia * HA + h] = c += p->b1_pa[(size_t)Ia * HA + h];
+        for (int h = 0; h <= HA; ++h) {
+            const double v = h <= da ? pa[h] : 0.0;
+            p->b1_pa1[h] = v;
+            c += v;
+            p->b1_fa[h] = h >= da ? 1.0 : c;
+        }
+        double t = 0.0;
+        for (int h = da; h >= 0; --h) {
+            t += pa[h];
+            if (h <= HA) p->b1_ga[h] = t;
+        }
     }
     p->b1_pb.assign(HB + 1, 0.0);
     p->b1_fb.assign(HB + 1, 1.0);

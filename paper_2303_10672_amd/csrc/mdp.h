@@ -42,7 +42,8 @@ struct pvi_mdp {
 
     // Scenario B as the paper runs it (lead time 1): issue probabilities and revenue
     int b1_ha = 0, b1_hb = 0;  // m a_max + 1 per product
-    std::vector<double> b1_pa, b1_pc, b1_pb, b1_fb, b1_j, b1_jc, b1_rev;
+    std::vector<double> b1_pa, b1_pb, b1_fb, b1_j, b1_jc, b1_rev;
+    std::vector<double> b1_pa1, b1_fa, b1_ga;  // [HA + 1] P(D_a = h), P(D_a <= h), P(D_a >= h)
 
     int64_t logical_per_sweep = 0;
     int64_t executed_per_sweep = 0;
@@ -71,7 +72,7 @@ struct pvi_mdp {
         double *cpmf = nullptr, *ccdf = nullptr, *ctail = nullptr, *cr0 = nullptr,
                *cbinq = nullptr, *cbinm = nullptr;
         int32_t *cpy = nullptr, *cpr = nullptr, *cpb = nullptr;
-        double *b1w = nullptr, *b1y = nullptr, *b1pa = nullptr, *b1pc = nullptr,
+        double *b1w = nullptr, *b1y = nullptr, *b1pa = nullptr, *b1fa = nullptr, *b1ga = nullptr,
                *b1pb = nullptr, *b1fb = nullptr, *b1j = nullptr, *b1jc = nullptr,
                *b1rev = nullptr;
         int tiles = 0;

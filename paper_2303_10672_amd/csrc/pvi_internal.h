@@ -134,8 +134,9 @@ struct B1Dev {
     double* partials;     // [NB * ceil(NA / 256)][4]
     double* w;            // [Ra][Rb][NB][na1]: sum over h_b < I_b of V, per next A part
     double* y;            // [Ra][Rb][HB][NA]: the b-runs-out term per I_b
-    const double* pa;     // [HA][HA] demand of a capped at I_a
-    const double* pc;     // [HA][HA] its cumulative sum
+    const double* pa1;    // [HA + 1] P(D_a = h)
+    const double* fa;     // [HA + 1] P(D_a <= h)
+    const double* ga;     // [HA + 1] P(D_a >= h)
     const double* pb;     // [HB + 1] demand of b
     const double* fb;     // [HB + 1] its CDF
     const double* j;      // [HB][HA][HA] P(h_a, h_b = I_b | I_a, I_b)
@@ -145,6 +146,7 @@ struct B1Dev {
     int32_t m, Ra, Rb, HA, HB, na1, nb1, NA, NB, extract;
     int32_t gw;           // stage W: values of the next A part per workgroup
     int32_t cb;           // final stage: orders of b per LDS chunk
+    int32_t cbp;          // its LDS row stride in doubles (even, 2 mod 4)
     double gamma, cva, cvb;
 };
 hipError_t launch_backup_b1(const B1Dev& p, int storage_fp32, int extract, hipStream_t s);
