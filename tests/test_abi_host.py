@@ -192,3 +192,25 @@ def test_no_device_fails_loudly_without_gpu():
     with pytest.raises(pvi.PviError) as e:
         pvi.vi_solve(m)
     assert e.value.status == pvi.PVI_E_DEVICE
+
+
+def test_lead_time_one_two_product_family_validation():
+    """The paper's scenario B: gamma = 1 only for this family, L = 1, and a clear
+    INVALID (before any device work) when one product's stock vectors exceed what the
+    GPU stages in LDS."""
+    lib = ctypes.CDLL(pvi.LIB_PATH)
+    lib.mdp_create.argtypes = [ctypes.POINTER(pvi.Desc), ctypes.POINTER(ctypes.c_void_p)]
+    h = ctypes.c_void_p()
+    d, keep = pvi.make_desc(W.scenario_b_paper(2, 1))
+    assert lib.mdp_create(ctypes.byref(d), ctypes.byref(h)) == pvi.PVI_OK
+    d.lead_time = 0
+    assert lib.mdp_create(ctypes.byref(d), ctypes.byref(h)) == pvi.PVI_E_INVALID
+    a, keep2 = pvi.make_desc(W.config0())
+    a.gamma = 1.0
+    assert lib.mdp_create(ctypes.byref(a), ctypes.byref(h)) == pvi.PVI_E_INVALID
+    big = pvi.mdp_create(W.scenario_b1(m=4, a_max=(1, 16), means=(1.0, 5.0)))
+    with pytest.raises(pvi.PviError) as e:
+        pvi.vi_solve(big, precision="fp64")
+    assert e.value.status == pvi.PVI_E_INVALID and "on the GPU" in str(e.value)
+    m = pvi.mdp_create(W.scenario_b_paper(3, 1))
+    assert (m.n_states, m.n_actions) == (16777216, 256)
