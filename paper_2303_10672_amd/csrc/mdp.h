@@ -78,6 +78,14 @@ struct pvi_mdp {
         int tiles = 0;
         size_t bytes = 0;
         std::vector<hipEvent_t> ev;
+        // instantiated graphs of kGraphSweeps sweeps (backup + span launches), keyed by
+        // storage precision, compensated sums and fixed-length runs; their kernel
+        // arguments hold this handle's buffers, so they live and die with them
+        struct SweepGraph {
+            int key = -1;
+            hipGraphExec_t exec = nullptr;
+        };
+        std::vector<SweepGraph> graphs;
     } dev;
 
     // results of the last solve; have_result = 2 means they are in the host

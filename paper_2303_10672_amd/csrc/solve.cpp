@@ -45,6 +45,8 @@ void free_device(pvi_mdp* p) {
     family_free(p);
     if (d.h_ctl) (void)hipHostFree(d.h_ctl);
     for (auto e : d.ev) (void)hipEventDestroy(e);
+    for (auto& g : d.graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (d.own) (void)hipStreamDestroy(d.own);
     (void)hipSetDevice(prev);
     d = pvi_mdp::Dev{};
@@ -168,6 +170,54 @@ pvi_status init_ctl(pvi_mdp* p, hipStream_t s, double thr, double c0, int rule) 
     return PVI_OK;
 }
 
+// Sweeps per captured graph: an even number, so every replay starts on the same
+// ping-pong table.
+constexpr int kGraphSweeps = 8;
+
+// Launch the backup and span kernels of sweep `launched` (ping-pong tables; no
+// events, no periodic test).
+pvi_status launch_sweep(pvi_mdp* p, const Phase& ph, int launched, hipStream_t s) {
+    auto& d = p->dev;
+    const void* vin = ph.fp32 ? (const void*)d.v32[launched & 1] : v64_slot(p, launched & 1);
+    void* vout = ph.fp32 ? (void*)d.v32[(launched + 1) & 1] : v64_slot(p, (launched + 1) & 1);
+    PVI_HIP(family_backup(p, ph.fp32, ph.kahan, 0, ph.fixed > 0, vin, vout, s));
+    if (!family_fused_span(p))
+        PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, ph.fp32 ? 1 : 0, ph.fixed > 0,
+                            p->d.gamma, s));
+    return PVI_OK;
+}
+
+// The instantiated graph of kGraphSweeps sweeps from an even sweep index, captured
+// on stream s at first use.  Each sweep's launches read the device stop flag, so a
+// replay after the stopping rule fired does no work; the host still checks the flag
+// between replays, as between batches of direct launches.
+pvi_status sweep_graph(pvi_mdp* p, const Phase& ph, hipStream_t s, hipGraphExec_t* out) {
+    auto& d = p->dev;
+    const int key = (ph.fp32 ? 1 : 0) | (ph.kahan << 1) | ((ph.fixed > 0 ? 1 : 0) << 2);
+    for (auto& g : d.graphs)
+        if (g.key == key) {
+            *out = g.exec;
+            return PVI_OK;
+        }
+    hipGraph_t graph = nullptr;
+    PVI_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    pvi_status st = PVI_OK;
+    for (int i = 0; i < kGraphSweeps && st == PVI_OK; ++i) st = launch_sweep(p, ph, i, s);
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (st != PVI_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    PVI_HIP(ec);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    PVI_HIP(ei);
+    d.graphs.push_back({key, exec});
+    *out = exec;
+    return PVI_OK;
+}
+
 pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) {
     auto& d = p->dev;
     int launched = 0, k = ph.k0;
@@ -181,32 +231,44 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
             d.ev.push_back(e);
         }
     }
+    // graphs serve the plain ping-pong loop; timed runs and the periodic rule (whose
+    // value tables rotate through a longer ring) launch directly
+    const bool graphs = !ph.time && ph.period == 0 && ph.ring == 2;
     while (launched < limit) {
-        const int n = std::min(k, limit - launched);
+        int n = std::min(k, limit - launched);
         const int before = d.h_ctl->sweeps;
-        for (int i = 0; i < n; ++i) {
-            const void* vin = ph.fp32 ? (const void*)d.v32[launched & 1]
-                                      : v64_slot(p, launched % ph.ring);
-            void* vout = ph.fp32 ? (void*)d.v32[(launched + 1) & 1]
-                                 : v64_slot(p, (launched + 1) % ph.ring);
-            if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i], s));
-            PVI_HIP(family_backup(p, ph.fp32, ph.kahan, 0, ph.fixed > 0, vin, vout, s));
-            if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i + 1], s));
-            if (!family_fused_span(p))
-                PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, ph.fp32 ? 1 : 0, ph.fixed > 0,
-                                    p->d.gamma, s));
-            ++launched;
-            if (ph.period > 0 && launched >= ph.period) {
-                // V_{i-j} for j = 0..P, i = launched (a sweep that was skipped after the
-                // stop flag leaves its table untouched, and so does this check)
-                PeriodicArgs a{};
-                for (int j = 0; j <= ph.period; ++j)
-                    a.v[j] = v64_slot(p, (launched - j) % ph.ring);
-                a.P = ph.period;
-                a.gamma = ph.gamma;
-                a.thr = ph.thr;
-                a.n = p->ns;
-                PVI_HIP(launch_periodic_check(d.ctl, a, d.pparts, s));
+        if (graphs && (launched & 1) == 0 && n >= kGraphSweeps) {
+            n -= n % kGraphSweeps;
+            hipGraphExec_t exec = nullptr;
+            const pvi_status st = sweep_graph(p, ph, s, &exec);
+            if (st != PVI_OK) return st;
+            for (int i = 0; i < n; i += kGraphSweeps) PVI_HIP(hipGraphLaunch(exec, s));
+            launched += n;
+        } else {
+            for (int i = 0; i < n; ++i) {
+                const void* vin = ph.fp32 ? (const void*)d.v32[launched & 1]
+                                          : v64_slot(p, launched % ph.ring);
+                void* vout = ph.fp32 ? (void*)d.v32[(launched + 1) & 1]
+                                     : v64_slot(p, (launched + 1) % ph.ring);
+                if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i], s));
+                PVI_HIP(family_backup(p, ph.fp32, ph.kahan, 0, ph.fixed > 0, vin, vout, s));
+                if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i + 1], s));
+                if (!family_fused_span(p))
+                    PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, ph.fp32 ? 1 : 0,
+                                        ph.fixed > 0, p->d.gamma, s));
+                ++launched;
+                if (ph.period > 0 && launched >= ph.period) {
+                    // V_{i-j} for j = 0..P, i = launched (a sweep that was skipped after
+                    // the stop flag leaves its table untouched, and so does this check)
+                    PeriodicArgs a{};
+                    for (int j = 0; j <= ph.period; ++j)
+                        a.v[j] = v64_slot(p, (launched - j) % ph.ring);
+                    a.P = ph.period;
+                    a.gamma = ph.gamma;
+                    a.thr = ph.thr;
+                    a.n = p->ns;
+                    PVI_HIP(launch_periodic_check(d.ctl, a, d.pparts, s));
+                }
             }
         }
         PVI_HIP(hipMemcpyAsync(d.h_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
