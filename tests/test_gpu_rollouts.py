@@ -154,3 +154,21 @@ def test_paper_largest_runs_end_to_end(fam, args, paper):
     assert _close(st[2], paper["vi_service"], st[3], digits=1)
     assert _close(st[4], paper["vi_wastage"], st[5], digits=1)
     assert _close(st[6], paper["vi_holding"], st[7], digits=1)
+
+
+@pytest.mark.parametrize("row", GOLD["scenario_c_heuristic"],
+                         ids=lambda r: f"m{r['m']}e{r['exp']}")
+def test_paper_c_heuristic_on_the_gpu(row):
+    """The paper's best weekday (s, S) parameters rolled out on the GPU: its
+    simulation-optimization return and KPIs, and the oracle's rollouts draw for draw."""
+    sc = W.scenario_c_paper(row["m"], row["exp"])
+    m = pvi.mdp_create(sc)
+    prm = [v for pair in zip(row["s"], row["S"]) for v in pair]
+    r = pvi.policy_rollouts(m, policy="s_S", params=[prm], n_rollouts=10000, seed=1)
+    st = r["stats"][0]
+    assert _close(st[0], row["so_return"][0], st[1])
+    assert _close(st[2], row["so_service"], st[3], digits=1)
+    assert _close(st[4], row["so_wastage"], st[5], digits=1)
+    assert _close(st[6], row["so_holding"], st[7], digits=1)
+    ref = Oracle(sc).simulate("s_S", params=[prm], n_rollouts=10000, seed=1)
+    _same(r, ref)

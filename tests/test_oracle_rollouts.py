@@ -221,3 +221,21 @@ def test_scenario_c_rollouts_match_the_paper(row):
     assert _close(k[:, 0].mean(), row["vi_service"], k[:, 0].std(), digits=1)
     assert _close(k[:, 1].mean(), row["vi_wastage"], k[:, 1].std(), digits=1)
     assert _close(k[:, 2].mean(), row["vi_holding"], k[:, 2].std(), digits=1)
+
+
+@pytest.mark.parametrize("row", GOLD["scenario_c_heuristic"],
+                         ids=lambda r: f"m{r['m']}e{r['exp']}")
+def test_scenario_c_heuristic_matches_the_paper(row):
+    """The paper's best weekday (s, S) parameters, rolled out 10,000 times, give its
+    simulation-optimization return and KPIs."""
+    sc = W.scenario_c_paper(row["m"], row["exp"])
+    o = Oracle(sc)
+    prm = [v for pair in zip(row["s"], row["S"]) for v in pair]
+    ret, kpi = o.simulate("s_S", params=[prm], n_rollouts=10000, seed=1)
+    mean, sd = ret[0].mean(), ret[0].std(ddof=1)
+    assert _close(mean, row["so_return"][0], sd)
+    assert abs(sd - row["so_return"][1]) <= 2.0
+    k = kpi[0]
+    assert _close(k[:, 0].mean(), row["so_service"], k[:, 0].std(), digits=1)
+    assert _close(k[:, 1].mean(), row["so_wastage"], k[:, 1].std(), digits=1)
+    assert _close(k[:, 2].mean(), row["so_holding"], k[:, 2].std(), digits=1)
