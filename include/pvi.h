@@ -53,6 +53,10 @@
  *    not be used by two threads at once.  Server calls are thread-safe.
  *  - There is no CPU fallback: without a usable gfx950 device, solves return
  *    PVI_E_DEVICE.
+ *  - Scenario C times its merge kernels at each candidate block width at the first
+ *    solve of a shape (R, m, weekdays) in a process and keeps the fastest; results do
+ *    not depend on the choice.  PVI_TUNE=0 in the environment skips the timing (the
+ *    LDS rule then chooses); PVI_TUNE_VERBOSE=1 prints the choices to stderr.
  */
 #ifndef PVI_H
 #define PVI_H

@@ -2,6 +2,13 @@
 #include "families.h"
 
 #include <algorithm>
+#include <array>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace pvi {
 
@@ -145,6 +152,7 @@ static CDev make_cdev(const pvi_mdp* p) {
     c.t0 = d.ct0;
     c.t1 = d.ct1;
     c.tf = d.ctf;
+    std::memcpy(c.lb, p->c_lb, sizeof(c.lb));
     c.exogenous = p->c_exogenous ? 1 : 0;
     c.alim = R - 1;
     c.top_only = 0;
@@ -247,6 +255,50 @@ static hipError_t upload_vec(T** dst, const std::vector<T>& src) {
     return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
 }
 
+// Merge block widths chosen by timing, per (R, m, number of weekdays), shared by every
+// handle of the process.  PVI_TUNE=0 in the environment keeps the LDS rule instead.
+namespace {
+using TuneKey = std::tuple<int, int, int>;
+using TuneVal = std::array<std::array<int32_t, 10>, 2>;
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+pvi_status tune_c(pvi_mdp* p) {
+    std::memset(p->c_lb, 0, sizeof(p->c_lb));
+    const char* env = std::getenv("PVI_TUNE");
+    if ((env && std::strcmp(env, "0") == 0) || p->m < 4) return PVI_OK;
+    const TuneKey key{p->rad[0], p->m, p->P};
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+            return fail(PVI_E_DEVICE, "scenario C tuning: stream creation failed");
+        int32_t lb[2][10];
+        const hipError_t e = tune_c_merge(make_cdev(p), s, lb);
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+        if (e != hipSuccess)
+            return fail(PVI_E_DEVICE, std::string("scenario C tuning: ") + hipGetErrorString(e));
+        TuneVal v{};
+        for (int a = 0; a < 2; ++a)
+            for (int j = 0; j < 10; ++j) v[a][j] = lb[a][j];
+        it = g_tune.emplace(key, v).first;
+        const char* verbose = std::getenv("PVI_TUNE_VERBOSE");
+        if (verbose && std::strcmp(verbose, "1") == 0) {
+            std::fprintf(stderr, "pvi: scenario C R=%d m=%d P=%d merge block widths", p->rad[0],
+                         p->m, p->P);
+            for (int j = 3; j <= p->m - 1 && j < 10; ++j)
+                std::fprintf(stderr, " j=%d: fp64 %d fp32 %d;", j, lb[0][j], lb[1][j]);
+            std::fprintf(stderr, "\n");
+        }
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int j = 0; j < 10; ++j) p->c_lb[a][j] = it->second[a][j];
+    return PVI_OK;
+}
+}  // namespace
+
 pvi_status family_init(pvi_mdp* p) {
     auto& d = p->dev;
     if (p->family == PVI_FAMILY_LEADTIME && upload_vec(&d.agroups, p->a_groups) != hipSuccess)
@@ -279,6 +331,8 @@ pvi_status family_init(pvi_mdp* p) {
             upload_vec(&d.cpr, p->c_pair_r) != hipSuccess ||
             upload_vec(&d.cpb, p->c_pair_base) != hipSuccess)
             return fail(PVI_E_NOMEM, "scenario C table allocation failed");
+        const pvi_status st = tune_c(p);
+        if (st != PVI_OK) return st;
     }
     if (p->family == PVI_FAMILY_SUBST2_L1) {
         if (hipMalloc((void**)&d.b1w, sizeof(double) * b1_w_entries(p)) != hipSuccess ||

@@ -270,6 +270,18 @@ __global__ __launch_bounds__(256) void c_final_kernel(CDev p, const void* tin) {
 }
 
 template <typename VT>
+static size_t c_lds_for(const CDev& p, int lb) {
+    return sizeof(VT) * (size_t)p.R * p.R * lb + sizeof(double) * p.R * p.R;
+}
+
+template <typename VT>
+static int c_default_lb(const CDev& p) {
+    int lb = (int)(64 / sizeof(VT));
+    while (lb > 4 && (c_lds_for<VT>(p, lb) > 32768 || p.R * lb > 1024)) lb /= 2;
+    return lb;
+}
+
+template <typename VT>
 static hipError_t launch_c_chain(const CDev& p, void* top, hipStream_t s);
 template <typename VT>
 static hipError_t launch_merge_lb(const CDev& p, int j, const void* in, void* out, int lb,
@@ -324,14 +336,14 @@ static hipError_t launch_c_chain(const CDev& p, void* top, hipStream_t s) {
             hipLaunchKernelGGL((c_merge2_kernel<VT>), dim3((unsigned)(p.nblk / (p.R * p.R)), p.P * p.R),
                                dim3(threads), 0, s, q, in, out);
         } else {
-            // the widest block of low digits (up to 64 bytes per slab row) whose slab
-            // stays within 32 KB of LDS, so several workgroups share a CU
-            auto lds_for = [&](int lb) {
-                return sizeof(VT) * (size_t)p.R * p.R * lb + sizeof(double) * p.R * p.R;
-            };
-            int lb = (int)(64 / sizeof(VT));
-            while (lb > 4 && (lds_for(lb) > 32768 || p.R * lb > 1024)) lb /= 2;
-            if (lds_for(lb) > 65536 || p.R * lb > 1024) return hipErrorInvalidConfiguration;
+            // the tuned block width of this level, else the widest block of low digits
+            // (up to 64 bytes per slab row) whose slab stays within 32 KB of LDS, so
+            // several workgroups share a CU
+            const int tuned = p.lb[sizeof(VT) == 4 ? 1 : 0][j];
+            const int lb = tuned > 0 ? tuned : c_default_lb<VT>(p);
+            if (c_lds_for<VT>(p, lb) > 65536 || p.R * lb > 1024)
+                return hipErrorInvalidConfiguration;
+            auto lds_for = [&](int w) { return c_lds_for<VT>(p, w); };
             const int64_t nlo = p.pow_r[j - 1];
             const int64_t nlob = (nlo + lb - 1) / lb;
             const int64_t nhi = p.nblk / (nlo * p.R);
@@ -372,6 +384,66 @@ static hipError_t launch_merge_lb(const CDev& p, int j, const void* in, void* ou
     if (lb == 16) return launch_merge_rc<VT, 16>(p, j, in, out, grid, threads, lds, s);
     if (lb == 8) return launch_merge_rc<VT, 8>(p, j, in, out, grid, threads, lds, s);
     return launch_merge_rc<VT, 4>(p, j, in, out, grid, threads, lds, s);
+}
+
+// One merge launch of level j at block width lb (the launch_c_chain arithmetic).
+template <typename VT>
+static hipError_t launch_merge_once(const CDev& p, int j, int lb, hipStream_t s) {
+    const int64_t nlo = p.pow_r[j - 1];
+    const int64_t nlob = (nlo + lb - 1) / lb;
+    const int64_t nhi = p.nblk / (nlo * p.R);
+    const int threads = ((p.R * lb + 63) / 64) * 64;
+    const int64_t nwg = nhi * nlob * p.P * p.R;
+    if (nwg > 0x7fffffff || nlo * p.R > 0x7fffffff || p.R > 32 ||
+        c_lds_for<VT>(p, lb) > 65536 || p.R * lb > 1024)
+        return hipErrorInvalidConfiguration;
+    return launch_merge_lb<VT>(p, j, p.t0, p.t1, lb, dim3((unsigned)nwg), threads,
+                               c_lds_for<VT>(p, lb), s);
+}
+
+template <typename VT>
+static hipError_t tune_levels(const CDev& p, hipStream_t s, int32_t* lb_out) {
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return e;
+    }
+    for (int j = 3; j <= p.m - 1 && j < 10 && e == hipSuccess; ++j) {
+        float best = 1e30f;
+        for (int lb : {4, 8, 16}) {
+            if (c_lds_for<VT>(p, lb) > 65536 || p.R * lb > 1024) continue;
+            if ((e = launch_merge_once<VT>(p, j, lb, s)) != hipSuccess) break;  // warm-up
+            if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_merge_once<VT>(p, j, lb, s);
+            if (e != hipSuccess || (e = hipEventRecord(e1, s)) != hipSuccess ||
+                (e = hipEventSynchronize(e1)) != hipSuccess)
+                break;
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (ms < best) {
+                best = ms;
+                lb_out[j] = lb;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return e;
+}
+
+hipError_t tune_c_merge(const CDev& pin, hipStream_t s, int32_t lb[2][10]) {
+    CDev p = pin;
+    p.extract = 1;  // the merge kernels then ignore the stop flag
+    p.alim = p.R - 1;
+    p.top_only = 0;
+    for (int v = 0; v < 2; ++v)
+        for (int j = 0; j < 10; ++j) lb[v][j] = 0;
+    if (p.m < 4) return hipSuccess;  // no level j >= 3
+    hipError_t e = tune_levels<double>(p, s, lb[0]);
+    if (e == hipSuccess) e = tune_levels<float>(p, s, lb[1]);
+    return e;
 }
 
 hipError_t launch_backup_c(const CDev& p, int storage_fp32, int extract, hipStream_t s) {

@@ -36,6 +36,7 @@ struct pvi_mdp {
 
     // Scenario C kernel tables
     bool c_exogenous = true;
+    int32_t c_lb[2][10] = {};  // merge block width per [FP32 storage][level] (0: LDS rule)
     int c_tab = 0, c_xt = 0, c_lpmax = 0, c_npair = 0;
     std::vector<double> c_pmf, c_cdf, c_tail, c_r0, c_binq, c_binm;
     std::vector<int32_t> c_pair_y, c_pair_r, c_pair_base;

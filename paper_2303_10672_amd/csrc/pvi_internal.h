@@ -118,6 +118,7 @@ struct CDev {
     Ctl* ctl;
     int64_t nblk;         // R^(m-1) states per weekday
     int32_t R, m, P, nzu, npair, tab, xt, lpmax, dmax, extract;
+    int32_t lb[2][10];    // merge block width per [FP32 storage][level j] (0: the LDS rule)
     int32_t exogenous;    // 0: one merge chain per order size a
     int32_t alim;         // merges compute rows with y_m + r <= alim
     int32_t top_only;     // and, when set, only the row r = alim - y_m
@@ -212,6 +213,9 @@ hipError_t launch_to_f32(const double* v64, float* v32, double c, int64_t n, hip
 hipError_t launch_fill(double* v, double value, int64_t n, hipStream_t s);
 // kernels_c.hip
 hipError_t launch_backup_c(const CDev& p, int storage_fp32, int extract, hipStream_t s);
+// Time the merge kernels of levels 3..m-1 at each block width that fits (4, 8, 16 low
+// digits per workgroup) on the handle's own tables, and write the fastest into lb.
+hipError_t tune_c_merge(const CDev& p, hipStream_t s, int32_t lb[2][10]);
 // kernels_b.hip
 hipError_t launch_backup_b(const BDev& p, int storage_fp32, int extract, hipStream_t s);
 
