@@ -289,7 +289,12 @@ pvi_status pvi_server_stats(pvi_server* server, double* p50_ms, double* p99_ms,
  *   S_S             scenario C: [S_tau - I]^+ when I <= s_tau and s_tau < S_tau,
  *                   else 0, for weekday tau; params[2 tau] = s_tau,
  *                   params[2 tau + 1] = S_tau.
- * Every order is capped at a_max. */
+ * Heuristic orders are placed as the formulas give them, without a cap at a_max
+ * (a heuristic's largest order is its S; the scenario-B search of the
+ * Simulation-optimization passage runs S_k up to 2 a_max[k]), except scenario C's,
+ * capped at a_max, the range of its remaining-life distribution.  Parameters
+ * must lie in [-2^20, 2^20], and horizon_days x the largest daily count (demand,
+ * or 2 (m + L) x the largest order) must stay below 2^31. */
 typedef enum {
     PVI_POLICY_TABLE = 0,
     PVI_POLICY_BASE_STOCK = 1,
@@ -300,7 +305,8 @@ typedef enum {
 #define PVI_POLICY_PARAMS 16
 
 typedef struct pvi_rollout_opts {
-    uint32_t struct_size;      /* sizeof(pvi_rollout_opts) */
+    uint32_t struct_size;      /* sizeof(pvi_rollout_opts); at least the offset of
+                                  product_kpis */
     int32_t kind;              /* pvi_policy_kind; must suit the handle's family */
     const int32_t* table;      /* TABLE: host [n_states], or NULL (last solved policy) */
     const int32_t* params;     /* heuristics: host [n_policies][PVI_POLICY_PARAMS] */
@@ -311,23 +317,35 @@ typedef struct pvi_rollout_opts {
     uint64_t seed;
     int64_t start_state;       /* state index at day 0, 0 = empty */
     void* stream;              /* optional hipStream_t; NULL = a stream of the call */
+    /* Per-product KPIs of the two-product families (Appendix B, KPI tables),
+     * optional host outputs, NULL to skip (must be NULL for one product).  A
+     * caller whose struct_size ends before these fields gets neither. */
+    double* product_kpis;      /* [n_policies][n_rollouts][2][3]: service, wastage,
+                                  holding of product k alone */
+    double* product_stats;     /* [n_policies][2][6]: mean and sample standard
+                                  deviation of the three KPIs of product k */
 } pvi_rollout_opts;
 
 /* Run the rollouts on the device and return, per policy, stats[8 p .. 8 p + 7] =
  * mean and sample standard deviation (n - 1) of the return, the service level,
  * the wastage and the holding.  returns ([n_policies][n_rollouts]) and kpis
  * ([n_policies][n_rollouts][3]: service, wastage, holding) are optional host
- * outputs (NULL to skip).  Blocks until done.  Errors: PVI_E_INVALID (options,
- * a kind that does not suit the family, table entries out of range),
- * PVI_E_NOT_READY (TABLE with NULL table before any solve), PVI_E_NOMEM,
- * PVI_E_DEVICE.  Device buffers are taken and released within the call. */
+ * outputs (NULL to skip).  Per product, the service level of the product whose
+ * unmet customers may substitute counts the units the other product gave them
+ * (scenario B with lead time 0: product 0; with lead time 1: product 1), and
+ * the wastage and holding count the product's own units.  Blocks until done.
+ * Errors: PVI_E_INVALID (options, a kind that does not suit the family, table
+ * entries out of range, per-product outputs for one product), PVI_E_NOT_READY
+ * (TABLE with NULL table before any solve), PVI_E_NOMEM, PVI_E_DEVICE.  Device
+ * buffers are taken and released within the call. */
 pvi_status policy_rollouts(pvi_mdp* mdp, const pvi_rollout_opts* opts, double* stats,
                            double* returns, double* kpis);
 
 /* Simulation optimization over a grid of heuristic parameter vectors (a
  * heuristic kind, n_policies candidates, common random numbers): the rollouts of
  * policy_rollouts, then *best = the candidate with the highest mean return, ties
- * to the lowest index.  stats as for policy_rollouts (may be NULL). */
+ * to the lowest index.  stats as for policy_rollouts (may be NULL); the
+ * per-product outputs of opts are filled as by policy_rollouts. */
 pvi_status heuristic_search(pvi_mdp* mdp, const pvi_rollout_opts* opts, double* stats,
                             int32_t* best);
 

@@ -84,7 +84,7 @@ def _load():
                                     P(ctypes.c_int32), P(ctypes.c_double), ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_uint64, ctypes.c_int64, P(ctypes.c_double),
-                                    P(ctypes.c_double)]
+                                    P(ctypes.c_double), P(ctypes.c_double)]
         lib.or_arrival_prob.restype = ctypes.c_double
         lib.or_arrival_prob.argtypes = [P(_OrMdp), ctypes.c_int32, P(ctypes.c_int32)]
         _lib = lib
@@ -313,13 +313,15 @@ class Oracle:
 
     # rollouts --------------------------------------------------------------
     def simulate(self, policy="table", table=None, params=None, n_rollouts=1000, warmup=100,
-                 horizon=365, seed=0, start=0):
+                 horizon=365, seed=0, start=0, by_product=False):
         """Rollouts of one tabulated policy or of several heuristic parameter vectors.
 
         policy: "table" (table = action per state), "base_stock" (params rows [S]),
         "mod_base_stock" ([S_0, S_1]) or "s_S" ([s_0, S_0, ..., s_6, S_6]).
         Returns (ret [n_pol, n_rollouts], kpi [n_pol, n_rollouts, 3]) with the KPIs
-        service level %, wastage % and mean holding."""
+        service level %, wastage % and mean holding; with by_product (two-product
+        families) also pkpi [n_pol, n_rollouts, 2, 3], the same KPIs per product
+        (Appendix B, KPI tables)."""
         kind = {"table": 0, "base_stock": 1, "mod_base_stock": 2, "s_S": 3}[policy]
         if kind == 0:
             tab = np.ascontiguousarray(table, dtype=np.int32)
@@ -335,12 +337,16 @@ class Oracle:
         mu = np.array([float(self.sc["demand"][k]["mean"][0]) for k in range(2)])
         ret = np.zeros((n_pol, n_rollouts))
         kpi = np.zeros((n_pol, n_rollouts, 3))
+        if by_product:
+            assert self.sc["family"] in ("B", "B1"), "per-product KPIs need two products"
+            pkpi = np.zeros((n_pol, n_rollouts, 2, 3))
         null_i = ctypes.POINTER(ctypes.c_int32)()
         self.lib.or_simulate(self.ref, kind, _ip(tab) if tab is not None else null_i,
                              _ip(prm) if prm is not None else null_i, _dp(mu), n_pol,
                              int(n_rollouts), int(warmup), int(horizon),
-                             ctypes.c_uint64(int(seed)), int(start), _dp(ret), _dp(kpi))
-        return ret, kpi
+                             ctypes.c_uint64(int(seed)), int(start), _dp(ret), _dp(kpi),
+                             _dp(pkpi) if by_product else ctypes.POINTER(ctypes.c_double)())
+        return (ret, kpi, pkpi) if by_product else (ret, kpi)
 
 
 def philox4x64_10(counter, key):

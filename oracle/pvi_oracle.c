@@ -615,56 +615,82 @@ static int sample_pmf(const double* pmf, int dmax, double u) {
     return dmax;
 }
 
-/* Heuristic and tabulated policies (Simulation optimization, per scenario):
- *  kind 0: table[s];
+/* Heuristic and tabulated policies (Simulation optimization, per scenario), the
+ * order written to act[0] (two products: act[0], act[1]):
+ *  kind 0: table[s], split into the two products' orders for scenario B;
  *  kind 1: base stock (Scenario A): [S - I]^+, I = stock on hand and in transit;
  *  kind 2: modified base stock (Scenario B), per product k with on-hand stock I_k,
  *          oldest stock X1_k and mean demand mu_k: floor([S_k - I_k + [X1_k - mu_k]^+]^+);
  *  kind 3: (s, S) per weekday (Scenario C): [S_tau - I]^+ when I <= s_tau and
  *          s_tau < S_tau, else 0.
- * Every order is capped at the maximum order quantity. */
-static int policy_action(const or_mdp* p, int kind, const int32_t* table,
-                         const int32_t* prm, const double* mu, int64_t s, const int32_t* dig) {
+ * The heuristics place orders as their formulas give them, with no cap at the
+ * maximum order quantity (S is the largest order a heuristic places, and the
+ * paper searches S^a, S^b up to twice the maximum order quantities), except
+ * Scenario C's, capped at the maximum order quantity, the range over which the
+ * remaining-life distribution of an order is given.  Digits may therefore exceed
+ * the state space's ranges under a heuristic; a table policy keeps them inside. */
+static void policy_action(const or_mdp* p, int kind, const int32_t* table,
+                          const int32_t* prm, const double* mu, const int32_t* dig,
+                          int* act) {
     int nd = n_digits(p);
-    if (kind == 0) return table[s];
+    int two = p->family == 1 || p->family == 3;
+    if (kind == 0) {
+        int a = table[or_encode(p, dig)];
+        if (two) {
+            act[0] = a / (p->a_max[1] + 1);
+            act[1] = a % (p->a_max[1] + 1);
+        } else {
+            act[0] = a;
+        }
+        return;
+    }
     if (kind == 1) {
         int I = 0;
         for (int i = 0; i < nd; ++i) I += dig[i];
-        int a = ipos(prm[0] - I);
-        return a < p->a_max[0] ? a : p->a_max[0];
+        act[0] = ipos(prm[0] - I);
+        return;
     }
     if (kind == 2) {
-        int m = p->m, q[2];
+        int m = p->m;
         int w = p->family == 3 ? m : m - 1; /* digits per product */
         for (int k = 0; k < 2; ++k) {
             int I = 0;
             for (int j = 0; j < w; ++j) I += dig[k * w + j];
             int x1 = dig[k * w + (w - 1)]; /* life 1: last digit of the product */
             double v = pos((double)prm[k] - I + pos((double)x1 - mu[k]));
-            int a = (int)floor(v);
-            q[k] = a < p->a_max[k] ? a : p->a_max[k];
+            act[k] = (int)floor(v);
         }
-        return q[0] * (p->a_max[1] + 1) + q[1];
+        return;
     }
     {
         int tau = dig[0], I = 0;
         for (int i = 1; i < nd; ++i) I += dig[i];
         int s_lo = prm[2 * tau], S_hi = prm[2 * tau + 1];
-        if (!(s_lo < S_hi) || I > s_lo) return 0;
-        int a = ipos(S_hi - I);
-        return a < p->a_max[0] ? a : p->a_max[0];
+        int a = (s_lo < S_hi && I <= s_lo) ? ipos(S_hi - I) : 0;
+        act[0] = a < p->a_max[0] ? a : p->a_max[0];
     }
 }
 
+/* the day's KPI quantities, in total and (two-product families) per product */
 typedef struct {
     int64_t demand, met, expired, received, held;
+    int64_t pd[2], pm[2], pe[2], pr[2], ph[2];
 } or_counts;
+
+static void or_product(or_counts* c, int k, int64_t demand, int64_t met, int64_t expired,
+                       int64_t received, int64_t held) {
+    c->pd[k] += demand;
+    c->pm[k] += met;
+    c->pe[k] += expired;
+    c->pr[k] += received;
+    c->ph[k] += held;
+}
 
 /* one day: sample the outcome, apply T, count the KPI quantities */
 static double sim_day(const or_mdp* p, uint64_t seed, int64_t r, int t, const int32_t* dig,
-                      int a, int32_t* nd, or_counts* c) {
+                      const int* act, int32_t* nd, or_counts* c) {
     double rew;
-    int m = p->m;
+    int m = p->m, a = act[0];
     if (p->family == 0) {
         int d = sample_pmf(p->pmf0, p->d_max[0], draw(seed, r, t, 0, 0));
         trans_a(p, dig, a, d, nd, &rew);
@@ -683,7 +709,7 @@ static double sim_day(const or_mdp* p, uint64_t seed, int64_t r, int t, const in
         c->held += tot - met - W;
         c->received += nd[L - 1]; /* X_m of the next state: the units that arrived */
     } else if (p->family == 1) {
-        int nb = p->a_max[1] + 1, aA = a / nb, aB = a % nb;
+        int aA = act[0], aB = act[1];
         int dA = sample_pmf(p->pmf0, p->d_max[0], draw(seed, r, t, 0, 0));
         int dB = sample_pmf(p->pmf1, p->d_max[1], draw(seed, r, t, 0, 1));
         int sA = aA, sB = aB;
@@ -707,8 +733,11 @@ static double sim_day(const or_mdp* p, uint64_t seed, int64_t r, int t, const in
         c->received += aA + aB;
         c->held += keptA + keptB;
         c->expired += (sA - hA - keptA) + (sB - hB - hS - keptB);
+        /* product 0's customers served by product 1 count as met for product 0 */
+        or_product(c, 0, dA, hA + hS, sA - hA - keptA, aA, keptA);
+        or_product(c, 1, dB, hB, sB - hB - hS - keptB, aB, keptB);
     } else if (p->family == 3) {
-        int nb = p->a_max[1] + 1, aA = a / nb, aB = a % nb;
+        int aA = act[0], aB = act[1];
         int dA = sample_pmf(p->pmf0, p->d_max[0], draw(seed, r, t, 0, 0));
         int dB = sample_pmf(p->pmf1, p->d_max[1], draw(seed, r, t, 0, 1));
         int Ia = 0, Ib = 0;
@@ -731,6 +760,11 @@ static double sim_day(const or_mdp* p, uint64_t seed, int64_t r, int t, const in
         c->received += aA + aB;
         c->held += keptA + keptB;
         c->expired += (Ia - hA - keptA) + (Ib - hB - keptB);
+        /* of product a's issues, its own customers took min(dA, Ia) (they come
+         * first); the rest went to product b's customers */
+        int ownA = dA < Ia ? dA : Ia;
+        or_product(c, 0, dA, ownA, Ia - hA - keptA, aA, keptA);
+        or_product(c, 1, dB, hB + (hA - ownA), Ib - hB - keptB, aB, keptB);
     } else {
         int d = sample_pmf(p->pmf0 + (size_t)dig[0] * (p->d_max[0] + 1), p->d_max[0],
                            draw(seed, r, t, 0, 0));
@@ -771,10 +805,21 @@ static double sim_day(const or_mdp* p, uint64_t seed, int64_t r, int t, const in
  * ret[p*n_roll + r] = sum_{t=warmup}^{warmup+horizon-1} gamma^(t-warmup) R_t;
  * kpi[(p*n_roll + r)*3 + 0..2] = service level % (met/demand, 100 when no demand),
  * wastage % (expired/received, 0 when nothing arrived), mean holding per day; all
- * counted over the horizon days only. */
+ * counted over the horizon days only.  pkpi (NULL to skip; two-product families)
+ * [(p*n_roll + r)*2 + k][3]: the same three KPIs of product k alone, the demand of
+ * the product whose customers substitute counting as met when the other product
+ * serves it (Appendix B, KPI tables). */
+static void or_kpis(double* out, int64_t demand, int64_t met, int64_t expired,
+                    int64_t received, int64_t held, int32_t horizon) {
+    out[0] = demand > 0 ? 100.0 * (double)met / (double)demand : 100.0;
+    out[1] = received > 0 ? 100.0 * (double)expired / (double)received : 0.0;
+    out[2] = horizon > 0 ? (double)held / (double)horizon : 0.0;
+}
+
 int or_simulate(const or_mdp* p, int32_t kind, const int32_t* table, const int32_t* params,
                 const double* mu, int32_t n_pol, int32_t n_roll, int32_t warmup,
-                int32_t horizon, uint64_t seed, int64_t start, double* ret, double* kpi) {
+                int32_t horizon, uint64_t seed, int64_t start, double* ret, double* kpi,
+                double* pkpi) {
     int64_t total = (int64_t)n_pol * n_roll;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < total; ++i) {
@@ -782,14 +827,17 @@ int or_simulate(const or_mdp* p, int32_t kind, const int32_t* table, const int32
         int64_t r = i % n_roll;
         const int32_t* prm = params ? params + (size_t)pol * 16 : NULL;
         int32_t dig[OR_MAXD], nd[OR_MAXD];
-        int64_t s = start;
+        int nd_count = n_digits(p);
         double g = 1.0, acc = 0.0;
-        or_counts c = {0, 0, 0, 0, 0};
+        or_decode(p, start, dig);
+        or_counts c;
+        memset(&c, 0, sizeof c);
         for (int t = 0; t < warmup + horizon; ++t) {
-            or_decode(p, s, dig);
-            int a = policy_action(p, kind, table, prm, mu, s, dig);
-            or_counts day = {0, 0, 0, 0, 0};
-            double rew = sim_day(p, seed, r, t, dig, a, nd, &day);
+            int act[2] = {0, 0};
+            policy_action(p, kind, table, prm, mu, dig, act);
+            or_counts day;
+            memset(&day, 0, sizeof day);
+            double rew = sim_day(p, seed, r, t, dig, act, nd, &day);
             if (t >= warmup) {
                 acc += g * rew;
                 g *= p->gamma;
@@ -798,13 +846,17 @@ int or_simulate(const or_mdp* p, int32_t kind, const int32_t* table, const int32
                 c.expired += day.expired;
                 c.received += day.received;
                 c.held += day.held;
+                for (int k = 0; k < 2; ++k)
+                    or_product(&c, k, day.pd[k], day.pm[k], day.pe[k], day.pr[k], day.ph[k]);
             }
-            s = or_encode(p, nd);
+            memcpy(dig, nd, sizeof(int32_t) * nd_count); /* the state is kept as digits */
         }
         ret[i] = acc;
-        kpi[3 * i + 0] = c.demand > 0 ? 100.0 * (double)c.met / (double)c.demand : 100.0;
-        kpi[3 * i + 1] = c.received > 0 ? 100.0 * (double)c.expired / (double)c.received : 0.0;
-        kpi[3 * i + 2] = horizon > 0 ? (double)c.held / (double)horizon : 0.0;
+        or_kpis(kpi + 3 * i, c.demand, c.met, c.expired, c.received, c.held, horizon);
+        if (pkpi)
+            for (int k = 0; k < 2; ++k)
+                or_kpis(pkpi + (2 * i + k) * 3, c.pd[k], c.pm[k], c.pe[k], c.pr[k], c.ph[k],
+                        horizon);
     }
     return 0;
 }

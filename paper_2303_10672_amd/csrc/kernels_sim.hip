@@ -80,6 +80,21 @@ struct Tally {
     int demand, met, expired, received, held;
 };
 
+__device__ __forceinline__ void add(Tally& c, const Tally& d) {
+    c.demand += d.demand;
+    c.met += d.met;
+    c.expired += d.expired;
+    c.received += d.received;
+    c.held += d.held;
+}
+
+// service %, wastage %, mean holding per day of a rollout's counts
+__device__ __forceinline__ void kpis(double* k, const Tally& c, int horizon) {
+    k[0] = c.demand > 0 ? 100.0 * (double)c.met / (double)c.demand : 100.0;
+    k[1] = c.received > 0 ? 100.0 * (double)c.expired / (double)c.received : 0.0;
+    k[2] = horizon > 0 ? (double)c.held / (double)horizon : 0.0;
+}
+
 }  // namespace
 
 // FAM 0: scenario A (state [O_{L-1}..O_1, X_m..X_1]); 1: scenario B with L = 0
@@ -159,12 +174,15 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
         }
     }
 
+    constexpr bool kTwo = FAM == 1 || FAM == 3;
     double g = 1.0, acc = 0.0;
     Tally c = {0, 0, 0, 0, 0};
+    Tally c0 = {0, 0, 0, 0, 0}, c1 = {0, 0, 0, 0, 0};  // per product (two products)
     const int days = s.warmup + s.horizon;
     for (int t = 0; t < days; ++t) {
-        // ---- action
-        int a;
+        // ---- action (two products: aA, aB; heuristic orders are not capped,
+        // except scenario C's, whose remaining-life table ends at a_max)
+        int a = 0, aA = 0, aB = 0;
         if (s.kind == PVI_POLICY_TABLE) {
             int64_t idx = 0;
             if (FAM == 0) {
@@ -195,14 +213,18 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
                     if (j <= m - 1) idx = idx * R0 + X[j];
             }
             a = s.table[idx];
+            if (kTwo) {
+                aA = a / s.R1;
+                aB = a - aA * s.R1;
+            }
         } else if (FAM == 0) {  // base stock on stock on hand and in transit
             int I = 0;
 #pragma unroll
             for (int j = 1; j <= kMaxM; ++j) I += X[j];
 #pragma unroll
             for (int i = 1; i <= kMaxO; ++i) I += O[i];
-            a = min(max(prm[0] - I, 0), R0 - 1);
-        } else if (FAM == 1 || FAM == 3) {  // modified base stock per product
+            a = max(prm[0] - I, 0);
+        } else if (kTwo) {  // modified base stock per product
             int IA = 0, IB = 0;
 #pragma unroll
             for (int j = 1; j <= kMaxM; ++j) {
@@ -211,8 +233,8 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
             }
             const double va = posd(((double)prm[0] - IA) + posd((double)X[1] - s.mu0));
             const double vb = posd(((double)prm[1] - IB) + posd((double)Y[1] - s.mu1));
-            const int qa = min((int)floor(va), R0 - 1), qb = min((int)floor(vb), s.R1 - 1);
-            a = qa * s.R1 + qb;
+            aA = (int)floor(va);
+            aB = (int)floor(vb);
         } else {  // (s, S) of the weekday
             int I = 0;
 #pragma unroll
@@ -224,7 +246,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
         // ---- outcome and transition
         const Block b0 = philox(s.seed, r, (uint64_t)t, 0);
         double rew;
-        Tally day;
+        Tally day, day0 = {0, 0, 0, 0, 0}, day1 = {0, 0, 0, 0, 0};
         if (FAM == 0) {
             const int d = sample(cdf0, s.dmax0, unif(b0.w[0]));
             int tot = 0;
@@ -263,7 +285,6 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
                 if (i == s.L - 1) O[i] = a;
             day = Tally{d, met, W, arrive, held};
         } else if (FAM == 1) {
-            const int aA = a / s.R1, aB = a - aA * s.R1;
             const int dA = sample(cdf0, s.dmax0, unif(b0.w[0]));
             const int dB = sample(cdf1, s.dmax1, unif(b0.w[1]));
 #pragma unroll
@@ -308,7 +329,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
                 rem -= take;
             }
             const int hS = k - rem;
-            const int W = X[1] + Y[1];
+            const int wA = X[1], wB = Y[1], W = wA + wB;
             rew = -(s.cvar0 * aA + s.cvar1 * aB) + s.rev0 * hA + s.rev1 * (hB + hS);
 #pragma unroll
             for (int j = 1; j < kMaxM; ++j) {
@@ -317,10 +338,12 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
             }
             X[kMaxM] = Y[kMaxM] = 0;
             day = Tally{dA + dB, hA + hB + hS, W, aA + aB, stA + stB - hA - hB - hS - W};
+            // product 0's customers served by product 1 count as met for product 0
+            day0 = Tally{dA, hA + hS, wA, aA, stA - hA - wA};
+            day1 = Tally{dB, hB, wB, aB, stB - hB - hS - wB};
         } else if (FAM == 3) {
             // lead time 1: today's orders arrive for tomorrow; product b's unmet
             // customers may take product a's units left after a's own demand
-            const int aA = a / s.R1, aB = a - aA * s.R1;
             const int dA = sample(cdf0, s.dmax0, unif(b0.w[0]));
             const int dB = sample(cdf1, s.dmax1, unif(b0.w[1]));
             int stA = 0, stB = 0;
@@ -351,7 +374,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
                 rem -= take;
             }
             const int hA = dA + du - rem;
-            const int W = X[1] + Y[1];
+            const int wA = X[1], wB = Y[1], W = wA + wB;
             rew = -(s.cvar0 * aA + s.cvar1 * aB) + s.rev0 * hA + s.rev1 * hB;
 #pragma unroll
             for (int j = 1; j < kMaxM; ++j) {
@@ -366,6 +389,11 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
                     Y[j] = aB;
                 }
             day = Tally{dA + dB, hA + hB, W, aA + aB, stA + stB - hA - hB - W};
+            // product a's own customers come first; the rest of its issues went to
+            // product b's customers and count as met for product b
+            const int ownA = min(dA, stA);
+            day0 = Tally{dA, ownA, wA, aA, stA - hA - wA};
+            day1 = Tally{dB, hB + (hA - ownA), wB, aB, stB - hB - wB};
         } else {
             const int d = sample(cdf0 + tau * (s.dmax0 + 1), s.dmax0, unif(b0.w[0]));
             int y[kMaxM + 1] = {};
@@ -408,35 +436,37 @@ __global__ __launch_bounds__(64) void rollout_kernel(SimDev s) {
         if (t >= s.warmup) {
             acc += g * rew;
             g *= s.gamma;
-            c.demand += day.demand;
-            c.met += day.met;
-            c.expired += day.expired;
-            c.received += day.received;
-            c.held += day.held;
+            add(c, day);
+            if (kTwo) {
+                add(c0, day0);
+                add(c1, day1);
+            }
         }
     }
     s.ret[lane] = acc;
-    double* k = s.kpi + 3 * lane;
-    k[0] = c.demand > 0 ? 100.0 * (double)c.met / (double)c.demand : 100.0;
-    k[1] = c.received > 0 ? 100.0 * (double)c.expired / (double)c.received : 0.0;
-    k[2] = s.horizon > 0 ? (double)c.held / (double)s.horizon : 0.0;
+    kpis(s.kpi + 3 * lane, c, s.horizon);
+    if (kTwo && s.pkpi) {
+        kpis(s.pkpi + 6 * lane, c0, s.horizon);
+        kpis(s.pkpi + 6 * lane + 3, c1, s.horizon);
+    }
 }
 
-// Mean and sample standard deviation (n - 1) of the return and the three KPIs of
-// each policy: one workgroup per policy, two passes, fixed summation order.
-__global__ __launch_bounds__(256) void rollout_stats_kernel(const double* ret, const double* kpi,
-                                                            int n_roll, double* stats) {
+// Mean and sample standard deviation (n - 1) of ncol columns of each policy's
+// [n_roll][stride] block: one workgroup per policy, two passes, fixed summation
+// order (so a column's figures do not depend on the other columns).
+__global__ __launch_bounds__(256) void column_stats_kernel(const double* x, int stride, int ncol,
+                                                           int n_roll, double* out, int ostride,
+                                                           int ooff) {
     __shared__ double red[256];
     const int pol = blockIdx.x, tid = threadIdx.x;
-    const double* rp = ret + (size_t)pol * n_roll;
-    const double* kp = kpi + (size_t)pol * n_roll * 3;
-    for (int q = 0; q < 4; ++q) {
+    const double* xp = x + (size_t)pol * n_roll * stride;
+    for (int q = 0; q < ncol; ++q) {
         double mean = 0.0;
         for (int pass = 0; pass < 2; ++pass) {
             double sum = 0.0;
             for (int i = tid; i < n_roll; i += 256) {
-                const double x = q == 0 ? rp[i] : kp[3 * (size_t)i + (q - 1)];
-                sum += pass == 0 ? x : (x - mean) * (x - mean);
+                const double v = xp[(size_t)i * stride + q];
+                sum += pass == 0 ? v : (v - mean) * (v - mean);
             }
             red[tid] = sum;
             __syncthreads();
@@ -449,8 +479,8 @@ __global__ __launch_bounds__(256) void rollout_stats_kernel(const double* ret, c
             if (pass == 0) {
                 mean = total / (double)n_roll;
             } else if (tid == 0) {
-                stats[(size_t)pol * 8 + 2 * q] = mean;
-                stats[(size_t)pol * 8 + 2 * q + 1] =
+                out[(size_t)pol * ostride + ooff + 2 * q] = mean;
+                out[(size_t)pol * ostride + ooff + 2 * q + 1] =
                     n_roll > 1 ? sqrt(total / (double)(n_roll - 1)) : 0.0;
             }
         }
@@ -477,11 +507,12 @@ hipError_t launch_rollouts(const SimDev& s, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_rollout_stats(const double* ret, const double* kpi, int n_pol, int n_roll,
-                                double* stats, hipStream_t st) {
-    if (n_pol <= 0 || n_roll <= 0) return hipSuccess;
-    hipLaunchKernelGGL(rollout_stats_kernel, dim3(n_pol), dim3(256), 0, st, ret, kpi, n_roll,
-                       stats);
+hipError_t launch_column_stats(const double* x, int stride, int ncol, int n_pol, int n_roll,
+                               double* out, int ostride, int ooff, hipStream_t st) {
+    if (n_pol <= 0 || n_roll <= 0 || ncol <= 0) return hipSuccess;
+    if (ncol > stride || ooff + 2 * ncol > ostride) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(column_stats_kernel, dim3(n_pol), dim3(256), 0, st, x, stride, ncol,
+                       n_roll, out, ostride, ooff);
     return hipGetLastError();
 }
 

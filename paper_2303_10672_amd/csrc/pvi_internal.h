@@ -171,10 +171,13 @@ struct SimDev {
     const double* lifecum;     // C: [a_max + 1][m], p_1(a) + ... + p_k(a) at a*m + k-1
     double* ret;               // [n_pol * n_roll]
     double* kpi;               // [n_pol * n_roll][3]
+    double* pkpi;              // two products: [n_pol * n_roll][2][3], or null
 };
 hipError_t launch_rollouts(const SimDev& s, hipStream_t st);
-hipError_t launch_rollout_stats(const double* ret, const double* kpi, int n_pol, int n_roll,
-                                double* stats, hipStream_t st);
+// Mean and sample standard deviation of ncol columns of x ([n_pol][n_roll][stride],
+// column c at offset c), written to out[p * ostride + ooff + 2 c] and the next slot.
+hipError_t launch_column_stats(const double* x, int stride, int ncol, int n_pol, int n_roll,
+                               double* out, int ostride, int ooff, hipStream_t st);
 
 // ------------------------------------------------------------------ batched small instances
 struct BatchItem {

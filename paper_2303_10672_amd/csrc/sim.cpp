@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -46,12 +47,25 @@ pvi_status check_kind(const pvi_mdp* p, int kind) {
     return fail(PVI_E_INVALID, "policy_rollouts: the policy kind does not suit the family");
 }
 
+// Options up to and including `stream` are required; the per-product outputs
+// that follow are read only when struct_size covers them.
+constexpr size_t kOptsBase = offsetof(pvi_rollout_opts, product_kpis);
+
+template <class T>
+T opt_field(const pvi_rollout_opts* o, T pvi_rollout_opts::*f, size_t off) {
+    return o->struct_size >= off + sizeof(T) ? o->*f : T{};
+}
+
 pvi_status run_rollouts(pvi_mdp* p, const pvi_rollout_opts* o, double* stats, double* returns,
                         double* kpis, const char* who) {
     const std::string w(who);
     if (!p || !o) return fail(PVI_E_INVALID, w + ": NULL argument");
-    if (o->struct_size < sizeof(pvi_rollout_opts))
+    if (o->struct_size < kOptsBase)
         return fail(PVI_E_INVALID, w + ": struct_size too small");
+    double* pkpis = opt_field(o, &pvi_rollout_opts::product_kpis,
+                              offsetof(pvi_rollout_opts, product_kpis));
+    double* pstats = opt_field(o, &pvi_rollout_opts::product_stats,
+                               offsetof(pvi_rollout_opts, product_stats));
     if (o->kind < PVI_POLICY_TABLE || o->kind > PVI_POLICY_S_S)
         return fail(PVI_E_INVALID, w + ": bad policy kind");
     pvi_status st = check_kind(p, o->kind);
@@ -72,8 +86,34 @@ pvi_status run_rollouts(pvi_mdp* p, const pvi_rollout_opts* o, double* stats, do
         return fail(PVI_E_INVALID, w + ": a heuristic policy needs params");
     if (p->m > PVI_MAX_LIFE || (p->family == PVI_FAMILY_LEADTIME && p->L - 1 > 11))
         return fail(PVI_E_INVALID, w + ": state too long for the simulator");
+    // Heuristic orders are not capped (scenario C's are), so a parameter bounds the
+    // largest order; the per-rollout counts are 32-bit.
+    int64_t qmax = std::max(p->d.a_max[0], p->d.a_max[1]);
+    if (o->kind != PVI_POLICY_TABLE) {
+        const int used = o->kind == PVI_POLICY_BASE_STOCK ? 1
+                         : o->kind == PVI_POLICY_MOD_BASE_STOCK ? 2 : 14;
+        for (int64_t i = 0; i < (int64_t)n_pol; ++i)
+            for (int j = 0; j < used; ++j) {
+                const int64_t v = o->params[i * PVI_POLICY_PARAMS + j];
+                if (v > (1 << 20) || v < -(1 << 20))
+                    return fail(PVI_E_INVALID, w + ": heuristic parameters must lie in "
+                                                   "[-2^20, 2^20]");
+                qmax = std::max(qmax, v);
+            }
+    }
+    {
+        const int64_t dsum = (int64_t)p->dmax[0] + (p->family == PVI_FAMILY_SUBST2 ||
+                                                    p->family == PVI_FAMILY_SUBST2_L1
+                                                ? p->dmax[1] : 0);
+        const int64_t per_day = std::max<int64_t>(dsum, 2 * (int64_t)(p->m + p->L) * qmax);
+        if ((int64_t)o->horizon_days * per_day > 0x7fffffffLL)
+            return fail(PVI_E_INVALID, w + ": horizon_days too long for the 32-bit KPI counts "
+                                           "at these order and demand sizes");
+    }
 
     const bool two = p->family == PVI_FAMILY_SUBST2 || p->family == PVI_FAMILY_SUBST2_L1;
+    if (!two && (pkpis || pstats))
+        return fail(PVI_E_INVALID, w + ": per-product KPIs need a two-product family");
     const int R0 = p->rad[0], R1 = two ? p->rad[1] : 1;
     // demand CDFs, summed left to right over the PMF of each period
     const int P = p->family == PVI_FAMILY_RUL_WEEKDAY ? p->P : 1;
@@ -165,11 +205,15 @@ pvi_status run_rollouts(pvi_mdp* p, const pvi_rollout_opts* o, double* stats, do
     d.rev1 = p->d.c_rev[1];
 
     const size_t lanes = (size_t)n_pol * o->n_rollouts;
-    double *dc0, *dc1, *dlc, *dret, *dkpi, *dstats;
+    const bool split = pkpis || pstats;
+    double *dc0, *dc1, *dlc, *dret, *dkpi, *dstats, *dpkpi = nullptr, *dpstats = nullptr;
     int32_t *dprm = nullptr, *dtab = nullptr;
     if (B.alloc(&dc0, cdf0.size()) != hipSuccess || B.alloc(&dc1, cdf1.size()) != hipSuccess ||
         B.alloc(&dlc, lcum.size()) != hipSuccess || B.alloc(&dret, lanes) != hipSuccess ||
         B.alloc(&dkpi, 3 * lanes) != hipSuccess || B.alloc(&dstats, 8 * (size_t)n_pol) != hipSuccess)
+        return fail(PVI_E_NOMEM, w + ": device allocation failed");
+    if (split && (B.alloc(&dpkpi, 6 * lanes) != hipSuccess ||
+                  B.alloc(&dpstats, 12 * (size_t)n_pol) != hipSuccess))
         return fail(PVI_E_NOMEM, w + ": device allocation failed");
     PVI_HIP(hipMemcpyAsync(dc0, cdf0.data(), sizeof(double) * cdf0.size(), hipMemcpyHostToDevice, s));
     if (!cdf1.empty())
@@ -193,14 +237,24 @@ pvi_status run_rollouts(pvi_mdp* p, const pvi_rollout_opts* o, double* stats, do
     d.lifecum = dlc;
     d.ret = dret;
     d.kpi = dkpi;
+    d.pkpi = dpkpi;
     PVI_HIP(launch_rollouts(d, s));
-    PVI_HIP(launch_rollout_stats(dret, dkpi, n_pol, o->n_rollouts, dstats, s));
+    // stats[p] = (return, service, wastage, holding) x (mean, sd)
+    PVI_HIP(launch_column_stats(dret, 1, 1, n_pol, o->n_rollouts, dstats, 8, 0, s));
+    PVI_HIP(launch_column_stats(dkpi, 3, 3, n_pol, o->n_rollouts, dstats, 8, 2, s));
+    if (split)
+        PVI_HIP(launch_column_stats(dpkpi, 6, 6, n_pol, o->n_rollouts, dpstats, 12, 0, s));
     std::vector<double> hst(8 * (size_t)n_pol);
     PVI_HIP(hipMemcpyAsync(hst.data(), dstats, sizeof(double) * hst.size(), hipMemcpyDeviceToHost, s));
     if (returns)
         PVI_HIP(hipMemcpyAsync(returns, dret, sizeof(double) * lanes, hipMemcpyDeviceToHost, s));
     if (kpis)
         PVI_HIP(hipMemcpyAsync(kpis, dkpi, sizeof(double) * 3 * lanes, hipMemcpyDeviceToHost, s));
+    if (pkpis)
+        PVI_HIP(hipMemcpyAsync(pkpis, dpkpi, sizeof(double) * 6 * lanes, hipMemcpyDeviceToHost, s));
+    if (pstats)
+        PVI_HIP(hipMemcpyAsync(pstats, dpstats, sizeof(double) * 12 * n_pol, hipMemcpyDeviceToHost,
+                               s));
     PVI_HIP(hipStreamSynchronize(s));
     if (stats) std::memcpy(stats, hst.data(), sizeof(double) * hst.size());
     return PVI_OK;
@@ -217,7 +271,7 @@ pvi_status policy_rollouts(pvi_mdp* p, const pvi_rollout_opts* o, double* stats,
 
 pvi_status heuristic_search(pvi_mdp* p, const pvi_rollout_opts* o, double* stats, int32_t* best) {
     if (!p || !o || !best) return fail(PVI_E_INVALID, "heuristic_search: NULL argument");
-    if (o->struct_size >= sizeof(pvi_rollout_opts) && o->kind == PVI_POLICY_TABLE)
+    if (o->struct_size >= kOptsBase && o->kind == PVI_POLICY_TABLE)
         return fail(PVI_E_INVALID, "heuristic_search: needs a heuristic policy kind");
     const int n = o->n_policies;
     std::vector<double> st(8 * (size_t)std::max(n, 1));

@@ -92,6 +92,8 @@ class RolloutOpts(ctypes.Structure):
         ("warmup_days", ctypes.c_int32), ("horizon_days", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("start_state", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
+        ("product_kpis", ctypes.POINTER(ctypes.c_double)),
+        ("product_stats", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -434,34 +436,58 @@ def _rollout_opts(m, policy, table, params, n_rollouts, warmup, horizon, seed, s
     return o, keep
 
 
+def _product_outputs(o, n_rollouts, by_product, per_rollout):
+    """Host arrays for the per-product KPIs (pkpi [n_pol, n_rollouts, 2, 3] when
+    per_rollout, pstats [n_pol, 2, 6]) pointed to by the options."""
+    if not by_product:
+        return None, None
+    pstats = np.zeros((o.n_policies, 2, 6))
+    pkpi = np.zeros((o.n_policies, int(n_rollouts), 2, 3)) if per_rollout else None
+    o.product_stats = _dptr(pstats)
+    if per_rollout:
+        o.product_kpis = _dptr(pkpi)
+    return pkpi, pstats
+
+
 def policy_rollouts(m, policy="table", table=None, params=None, n_rollouts=10000, warmup=100,
-                    horizon=365, seed=0, start=0, stream=None, per_rollout=True):
+                    horizon=365, seed=0, start=0, stream=None, per_rollout=True,
+                    by_product=False):
     """Rollouts of a policy (table: the given one, or the handle's solved policy when
     table is None) or of heuristic parameter rows.  Returns dict(stats [n_pol, 8],
     ret [n_pol, n_rollouts], kpi [n_pol, n_rollouts, 3]) (ret, kpi None unless
-    per_rollout)."""
+    per_rollout); with by_product (two-product families) also pstats [n_pol, 2, 6]
+    (mean, sd of service, wastage, holding per product) and pkpi [n_pol, n_rollouts,
+    2, 3]."""
     o, keep = _rollout_opts(m, policy, table, params, n_rollouts, warmup, horizon, seed, start,
                             stream)
     n = o.n_policies
     stats = np.zeros((n, 8))
     ret = np.zeros((n, int(n_rollouts))) if per_rollout else None
     kpi = np.zeros((n, int(n_rollouts), 3)) if per_rollout else None
+    pkpi, pstats = _product_outputs(o, n_rollouts, by_product, per_rollout)
     null = _P(ctypes.c_double)()
     _check(_lib.policy_rollouts(m.handle, ctypes.byref(o), _dptr(stats),
                                 _dptr(ret) if per_rollout else null,
                                 _dptr(kpi) if per_rollout else null), "policy_rollouts")
     del keep
-    return {"stats": stats, "ret": ret, "kpi": kpi}
+    out = {"stats": stats, "ret": ret, "kpi": kpi}
+    if by_product:
+        out.update(pstats=pstats, pkpi=pkpi)
+    return out
 
 
 def heuristic_search(m, policy, params, n_rollouts=10000, warmup=100, horizon=365, seed=0,
-                     start=0, stream=None):
-    """Simulation optimization over heuristic parameter rows: (best row index, stats)."""
+                     start=0, stream=None, by_product=False):
+    """Simulation optimization over heuristic parameter rows: (best row index, stats),
+    and with by_product the per-product statistics [n_pol, 2, 6] as a third item."""
     o, keep = _rollout_opts(m, policy, None, params, n_rollouts, warmup, horizon, seed, start,
                             stream)
     stats = np.zeros((o.n_policies, 8))
+    _, pstats = _product_outputs(o, n_rollouts, by_product, False)
     best = ctypes.c_int32()
     _check(_lib.heuristic_search(m.handle, ctypes.byref(o), _dptr(stats), ctypes.byref(best)),
            "heuristic_search")
     del keep
+    if by_product:
+        return int(best.value), stats, pstats
     return int(best.value), stats

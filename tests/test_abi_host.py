@@ -33,7 +33,8 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(pvi.Desc) % 8 == 0
     assert ctypes.sizeof(pvi.Opts) == 56
     assert ctypes.sizeof(pvi.Result) == 96
-    assert ctypes.sizeof(pvi.RolloutOpts) == 64
+    assert ctypes.sizeof(pvi.RolloutOpts) == 80
+    assert pvi.RolloutOpts.product_kpis.offset == 64
 
 
 def test_rollout_options_are_validated_before_the_device():
@@ -61,7 +62,26 @@ def test_rollout_options_are_validated_before_the_device():
     assert run(w=-1) == pvi.PVI_E_INVALID
     assert run(start=121) == pvi.PVI_E_INVALID
     assert run(set={"struct_size": 60}) == pvi.PVI_E_INVALID
+    msg = pvi._lib.pvi_last_error().decode()
+    assert "struct_size" in msg
+    # per-product outputs need two products ...
+    out = np.zeros(12)
+    assert run(set={"product_stats": pvi._dptr(out)}) == pvi.PVI_E_INVALID
+    assert "two-product" in pvi._lib.pvi_last_error().decode()
+    assert run(set={"product_kpis": pvi._dptr(out)}) == pvi.PVI_E_INVALID
+    # ... and are not read when struct_size stops before them, so a caller built
+    # before they existed (64 bytes) is served: these requests reach the device
+    assert run(set={"product_stats": pvi._dptr(out), "struct_size": 72}) == pvi.PVI_E_DEVICE
+    assert run(set={"product_kpis": pvi._dptr(out), "struct_size": 64}) == pvi.PVI_E_DEVICE
     assert run(set={"kind": 9}) == pvi.PVI_E_INVALID
+    # heuristic orders are uncapped, so parameters and the 32-bit counts are bounded
+    assert run(params=[[1 << 21]]) == pvi.PVI_E_INVALID
+    assert "2^20" in pvi._lib.pvi_last_error().decode()
+    assert run(params=[[5], [-(1 << 21)]]) == pvi.PVI_E_INVALID
+    assert run(params=[[1 << 16]], h=1 << 14) == pvi.PVI_E_INVALID
+    assert "32-bit" in pvi._lib.pvi_last_error().decode()
+    assert run(params=[[1 << 20]], h=1 << 10) == pvi.PVI_E_INVALID   # 2 (m + L) 2^20 2^10
+    assert run(params=[[1 << 20]], h=1 << 8) == pvi.PVI_E_DEVICE
     bad = np.zeros(121, np.int32)
     bad[7] = 11                                       # 11 actions: 0..10
     assert run(policy="table", table=bad) == pvi.PVI_E_INVALID

@@ -145,17 +145,45 @@ def test_rollouts_match_oracle():
     assert np.array_equal(g["kpi"], kpi)
 
 
-def _close(ours, printed, sd):
-    return abs(ours - printed) <= 4.0 * sd * np.sqrt(2.0 / 10000) + 0.5
+def _close(ours, printed, sd, digits=0):
+    return abs(ours - printed) <= 4.0 * sd * np.sqrt(2.0 / 10000) + 0.5 * 10.0 ** -digits
 
 
-@pytest.mark.parametrize("m_exp,paper", [
-    ((2, "1"), [1644, 33]), ((3, "4"), [1762, 32]), ((3, "1"), [1761, 32])])
-def test_paper_runs_end_to_end(m_exp, paper):
-    """Results table of Appendix B: 10,000 rollouts of the GPU-solved policy."""
-    sc = W.scenario_b_paper(*m_exp)
+def _product_kpis_match(pstats, printed):
+    """pstats [2, 6] (mean, sd of service, wastage, holding per product) against the
+    paper's per-product KPI rows, printed to one decimal."""
+    for q, name in enumerate(("service", "wastage", "holding")):
+        for k in range(2):
+            mean, sd = pstats[k, 2 * q], pstats[k, 2 * q + 1]
+            assert _close(mean, printed[name][k][0], sd, digits=1), (name, k, mean)
+            assert abs(sd - printed[name][k][1]) <= 0.15, (name, k, sd)
+
+
+ROWS = GOLD["scenario_b"] + GOLD["scenario_b_gpu"]
+
+
+@pytest.mark.parametrize("row", ROWS, ids=lambda r: f"m{r['m']}e{r['exp']}")
+def test_paper_runs_end_to_end(row):
+    """Results and KPI tables of Appendix B: 10,000 rollouts of the GPU-solved policy
+    (experiments P1-P4: 100 sweeps) and of the best modified base stock of a grid
+    around the paper's (S_a, S_b), the return and the per-product KPIs."""
+    sc = W.scenario_b_paper(row["m"], row["exp"])
     m = pvi.mdp_create(sc)
-    pvi.vi_solve(m, precision="fp64")
-    st = pvi.policy_rollouts(m, n_rollouts=10000, seed=1, per_rollout=False)["stats"][0]
-    assert _close(st[0], paper[0], st[1])
-    assert abs(st[1] - paper[1]) <= 2.0
+    if row["exp"].startswith("P"):
+        pvi.vi_solve(m, precision="fp64", fixed_sweeps=100)
+    else:
+        pvi.vi_solve(m, precision="fp64")
+    r = pvi.policy_rollouts(m, n_rollouts=10000, seed=1, per_rollout=False, by_product=True)
+    st = r["stats"][0]
+    assert _close(st[0], row["vi_return"][0], st[1])
+    assert abs(st[1] - row["vi_return"][1]) <= 2.0
+    _product_kpis_match(r["pstats"][0], row["vi_kpi"])
+    Sa, Sb = row["s_best"]
+    grid = [[a, b] for a in range(Sa - 2, Sa + 3) for b in range(Sb - 2, Sb + 3)]
+    best, stats, pstats = pvi.heuristic_search(m, "mod_base_stock", grid, n_rollouts=10000,
+                                               seed=1, by_product=True)
+    at = grid.index([Sa, Sb])
+    # the paper's levels are the grid's best or within sampling error of it
+    assert stats[best, 0] - stats[at, 0] <= 4.0 * stats[at, 1] * np.sqrt(2.0 / 10000)
+    assert _close(stats[at, 0], row["so_return"][0], stats[at, 1])
+    _product_kpis_match(pstats[at], row["so_kpi"])

@@ -101,6 +101,42 @@ def test_heuristic_grid_matches_oracle(name, kind, grid):
     assert np.allclose(stats, g["stats"], rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("name", ["B", "B1"])
+def test_per_product_kpis_match_oracle(name):
+    """The per-product split of both two-product families, draw for draw: a seeded
+    table and a modified base-stock grid; the totals do not change when the split
+    is asked for, and heuristic_search reports the same per-product statistics."""
+    sc = FAMILIES["B"] if name == "B" else W.scenario_b1(m=2, a_max=(5, 4), means=(3.0, 2.0),
+                                                          rho=0.6, d_max=12)
+    o = Oracle(sc)
+    m = pvi.mdp_create(sc)
+    rng = np.random.default_rng([20, len(name)])
+    table = rng.integers(0, o.n_actions, size=o.n_states).astype(np.int32)
+    grid = [[a, b] for a in range(0, 11, 3) for b in range(0, 9, 3)]
+    for kw in ({"policy": "table", "table": table}, {"policy": "mod_base_stock", "params": grid}):
+        plain = pvi.policy_rollouts(m, n_rollouts=300, warmup=10, horizon=90, seed=8, **kw)
+        g = pvi.policy_rollouts(m, n_rollouts=300, warmup=10, horizon=90, seed=8,
+                                by_product=True, **kw)
+        oracle_kw = {"table": table} if "table" in kw else {"params": grid}
+        ret, kpi, pkpi = o.simulate(kw["policy"], n_rollouts=300, warmup=10, horizon=90, seed=8,
+                                    by_product=True, **oracle_kw)
+        _same(g, (ret, kpi))
+        assert np.array_equal(g["pkpi"], pkpi)
+        for f in ("ret", "kpi", "stats"):
+            assert np.array_equal(g[f], plain[f])
+        for p_ in range(pkpi.shape[0]):
+            for k in range(2):
+                for q in range(3):
+                    x = pkpi[p_, :, k, q]
+                    assert np.isclose(g["pstats"][p_, k, 2 * q], x.mean(), rtol=1e-12,
+                                      atol=1e-12)
+                    assert np.isclose(g["pstats"][p_, k, 2 * q + 1], x.std(ddof=1), rtol=1e-9,
+                                      atol=1e-12)
+    best, stats, pstats = pvi.heuristic_search(m, "mod_base_stock", grid, n_rollouts=300,
+                                               warmup=10, horizon=90, seed=8, by_product=True)
+    assert np.array_equal(pstats, g["pstats"]) and np.array_equal(stats, g["stats"])
+
+
 def test_large_table_and_base_stock_at_the_largest_preset():
     """1,771,561 states: a seeded random table (one 4-byte gather per day over 7 MB)
     and the base-stock grid, against the oracle."""

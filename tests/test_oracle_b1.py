@@ -93,17 +93,51 @@ def _close(ours, printed, sd, digits=0):
     return abs(ours - printed) <= 4.0 * sd * np.sqrt(2.0 / 10000) + 0.5 * 10.0 ** -digits
 
 
+def _product_kpis_match(pkpi, printed):
+    """pkpi [n_rollouts, 2, 3] against the paper's per-product KPI rows (mean and
+    standard deviation, printed to one decimal)."""
+    for q, name in enumerate(("service", "wastage", "holding")):
+        for k in range(2):
+            x = pkpi[:, k, q]
+            mean, sd = printed[name][k]
+            assert _close(x.mean(), mean, x.std(ddof=1), digits=1), (name, k, x.mean(), mean)
+            assert abs(x.std(ddof=1) - sd) <= 0.1 + 0.05, (name, k, x.std(ddof=1), sd)
+
+
 @pytest.mark.parametrize("row", GOLD["scenario_b"], ids=lambda r: f"m{r['m']}e{r['exp']}")
 def test_scenario_b_rollouts_match_the_paper(row):
+    """Results and KPI tables of Appendix B (m = 2): the return and the per-product
+    service level, wastage and holding of the value-iteration policy and of the best
+    modified base stock."""
     sc = W.scenario_b_paper(row["m"], row["exp"])
     o = Oracle(sc)
     vi = o.solve()
-    ret, _ = o.simulate("table", table=vi["pi"], n_rollouts=10000, seed=1)
+    ret, _, pkpi = o.simulate("table", table=vi["pi"], n_rollouts=10000, seed=1,
+                              by_product=True)
     assert _close(ret[0].mean(), row["vi_return"][0], ret[0].std(ddof=1))
     assert abs(ret[0].std(ddof=1) - row["vi_return"][1]) <= 2.0
+    _product_kpis_match(pkpi[0], row["vi_kpi"])
     Sa, Sb = row["s_best"]
     grid = [[a, b] for a in range(Sa - 2, Sa + 3) for b in range(Sb - 2, Sb + 3)]
-    g, _ = o.simulate("mod_base_stock", params=grid, n_rollouts=10000, seed=1)
+    g, _, pg = o.simulate("mod_base_stock", params=grid, n_rollouts=10000, seed=1,
+                          by_product=True)
     best = int(np.argmax(g.mean(axis=1)))
     assert grid[best] == [Sa, Sb]
     assert _close(g[best].mean(), row["so_return"][0], g[best].std(ddof=1))
+    _product_kpis_match(pg[best], row["so_kpi"])
+
+
+@pytest.mark.parametrize("row", GOLD["scenario_b"] + GOLD["scenario_b_gpu"],
+                         ids=lambda r: f"m{r['m']}e{r['exp']}")
+def test_scenario_b_heuristic_matches_the_paper(row):
+    """Results and KPI tables of Appendix B, every experiment: the paper's best
+    modified base-stock levels give its simulation-optimization return and
+    per-product KPIs.  Orders are not capped at the maximum order quantity: in m = 3
+    experiment 4 product b's best level (8) exceeds its maximum order (4), and the
+    paper prints the same figures as for experiment 2, whose maximum order is 9."""
+    sc = W.scenario_b_paper(row["m"], row["exp"])
+    ret, _, pk = Oracle(sc).simulate("mod_base_stock", params=[row["s_best"]],
+                                     n_rollouts=10000, seed=1, by_product=True)
+    assert _close(ret[0].mean(), row["so_return"][0], ret[0].std(ddof=1))
+    assert abs(ret[0].std(ddof=1) - row["so_return"][1]) <= 2.0
+    _product_kpis_match(pk[0], row["so_kpi"])

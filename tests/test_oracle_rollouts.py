@@ -61,9 +61,11 @@ def _replay(sc, table, n_roll, warmup, horizon, seed):
     life = life_probabilities(sc) if fam == "C" else None
     ret = np.zeros(n_roll)
     kpi = np.zeros((n_roll, 3))
+    pkpi = np.zeros((n_roll, 2, 3))
     for r in range(n_roll):
         s, g, acc = 0, 1.0, 0.0
         tot = {"demand": 0, "met": 0, "expired": 0, "received": 0, "held": 0}
+        per = [dict(tot), dict(tot)]
         for t in range(warmup + horizon):
             a = int(table[s])
             dig = U.decode(sc, s)
@@ -103,11 +105,19 @@ def _replay(sc, table, n_roll, warmup, horizon, seed):
                 g *= sc["gamma"]
                 for key in tot:
                     tot[key] += cnt[key]
+                    for k in range(2 if "product" in cnt else 0):
+                        per[k][key] += cnt["product"][k][key]
         ret[r] = acc
-        kpi[r, 0] = 100.0 * tot["met"] / tot["demand"] if tot["demand"] else 100.0
-        kpi[r, 1] = 100.0 * tot["expired"] / tot["received"] if tot["received"] else 0.0
-        kpi[r, 2] = tot["held"] / horizon
-    return ret, kpi
+        kpi[r] = _kpis(tot, horizon)
+        for k in range(2):
+            pkpi[r, k] = _kpis(per[k], horizon)
+    return ret, kpi, pkpi
+
+
+def _kpis(tot, horizon):
+    return (100.0 * tot["met"] / tot["demand"] if tot["demand"] else 100.0,
+            100.0 * tot["expired"] / tot["received"] if tot["received"] else 0.0,
+            tot["held"] / horizon)
 
 
 REPLAY = [
@@ -126,9 +136,14 @@ def test_rollouts_match_unit_model_replay(sc):
     rng = np.random.default_rng(5)
     table = rng.integers(0, o.n_actions, size=o.n_states).astype(np.int32)
     ret, kpi = o.simulate("table", table=table, n_rollouts=6, warmup=4, horizon=25, seed=77)
-    r2, k2 = _replay(sc, table, 6, 4, 25, 77)
+    r2, k2, p2 = _replay(sc, table, 6, 4, 25, 77)
     assert np.allclose(ret[0], r2, rtol=1e-13, atol=1e-9)
     assert np.array_equal(kpi[0], k2)
+    if sc["family"] in ("B", "B1"):
+        _, kpi3, pkpi = o.simulate("table", table=table, n_rollouts=6, warmup=4, horizon=25,
+                                   seed=77, by_product=True)
+        assert np.array_equal(kpi3, kpi)
+        assert np.array_equal(pkpi[0], p2)
 
 
 def test_heuristics_follow_their_definitions():
@@ -137,20 +152,21 @@ def test_heuristics_follow_their_definitions():
     or below s and only when s < S."""
     sc = W.scenario_a(m=2, L=2, a_max=6, d_max=8)
     o = Oracle(sc)
-    for S in (0, 4, 9):
-        table = np.array([min(max(S - int(np.sum(U.decode(sc, s))), 0), 6)
+    for S in (0, 4, 6):                   # orders <= S <= a_max: the state space holds them
+        table = np.array([max(S - int(np.sum(U.decode(sc, s))), 0)
                           for s in range(o.n_states)], dtype=np.int32)
         a, ka = o.simulate("base_stock", params=[[S]], n_rollouts=5, warmup=3, horizon=20)
         b, kb = o.simulate("table", table=table, n_rollouts=5, warmup=3, horizon=20)
         assert np.array_equal(a, b) and np.array_equal(ka, kb)
     sc = W.scenario_b(m=3, a_max=(4, 3), d_max=(6, 5), means=(3.0, 2.0), rho=0.5)
     o = Oracle(sc)
-    SA, SB = 6, 4
+    SA, SB = 4, 3
     rows = []
     for s in range(o.n_states):
         dig = U.decode(sc, s)
-        qa = min(int(np.floor(max(SA - sum(dig[:2]) + max(dig[1] - 3.0, 0.0), 0.0))), 4)
-        qb = min(int(np.floor(max(SB - sum(dig[2:]) + max(dig[3] - 2.0, 0.0), 0.0))), 3)
+        qa = int(np.floor(max(SA - sum(dig[:2]) + max(dig[1] - 3.0, 0.0), 0.0)))
+        qb = int(np.floor(max(SB - sum(dig[2:]) + max(dig[3] - 2.0, 0.0), 0.0)))
+        assert qa <= SA and qb <= SB
         rows.append(qa * 4 + qb)
     a, _ = o.simulate("mod_base_stock", params=[[SA, SB]], n_rollouts=5, warmup=2, horizon=15)
     b, _ = o.simulate("table", table=np.array(rows, np.int32), n_rollouts=5, warmup=2,
@@ -169,6 +185,33 @@ def test_heuristics_follow_their_definitions():
     b, _ = o.simulate("table", table=np.array(rows, np.int32), n_rollouts=5, warmup=2,
                       horizon=15)
     assert np.array_equal(a, b)
+
+
+def test_heuristic_orders_are_not_capped():
+    """With nothing on hand or in transit a heuristic orders S units, S being its
+    largest order (Heuristic policies passage), also above the maximum order
+    quantity of value iteration: one day from the empty state shows the order in
+    the reward and, for scenario B, in the units received."""
+    sc = W.scenario_a(m=2, L=2, a_max=6, d_max=8)
+    o = Oracle(sc)
+    pmf = demand_pmf(sc["demand"][0], sc["d_max"][0])
+    c = sc["costs"]
+    for S in (3, 9, 40):
+        ret, _ = o.simulate("base_stock", params=[[S]], n_rollouts=4, warmup=0, horizon=1,
+                            seed=6)
+        for r in range(4):
+            d = _inverse_cdf(pmf, _u(6, r, 0, 0, 0))
+            want = -c["var"][0] * S - c["short"] * d     # empty shelf: all demand unmet
+            assert abs(ret[0, r] - want) < 1e-12
+    sc = W.scenario_b1(m=2, a_max=(4, 3), means=(3.0, 2.5), rho=0.5, d_max=10)
+    o = Oracle(sc)
+    c = sc["costs"]
+    for SA, SB in ((2, 1), (9, 7), (30, 0)):
+        ret, kpi, pk = o.simulate("mod_base_stock", params=[[SA, SB]], n_rollouts=3, warmup=0,
+                                  horizon=1, seed=2, by_product=True)
+        assert np.all(ret == -(c["var"][0] * SA + c["var"][1] * SB))  # nothing to sell yet
+        assert np.all(pk[0, :, :, 1] == 0.0)                          # received, none expired
+        assert np.all(kpi[0, :, 2] == 0.0) and np.all(pk[0, :, :, 2] == 0.0)
 
 
 def test_policies_share_random_numbers():

@@ -88,7 +88,8 @@ def step(sc, s, a, omega):
 def day(sc, s, a, omega):
     """One day of the unit model: (next state index, reward, counts), where counts
     holds the day's demand, demand met, units expired, units received into stock and
-    units held at the end of the day (scenario C: including tonight's expiries)."""
+    units held at the end of the day (scenario C: including tonight's expiries); for
+    two products also "product", the same counts per product."""
     fam, m, L = sc["family"], sc["m"], sc["L"]
     c = sc["costs"]
     dig = decode(sc, s)
@@ -134,6 +135,12 @@ def day(sc, s, a, omega):
         dB_ = [aB] + [sum(1 for u in nB if u == life) for life in range(m - 1, 0, -1)]
         tally = {"demand": dA + dB, "met": hA + hS + hB, "received": aA + aB,
                  "expired": sum(1 for u in leftA + leftB if u == 1), "held": len(nA) + len(nB)}
+        # per product: product b's customers served by product a count for b
+        tally["product"] = [
+            {"demand": dA, "met": hA, "received": aA,
+             "expired": sum(1 for u in leftA if u == 1), "held": len(nA)},
+            {"demand": dB, "met": hB + hS, "received": aB,
+             "expired": sum(1 for u in leftB if u == 1), "held": len(nB)}]
         return encode(sc, dA_ + dB_), float(reward), tally
     if fam == "B":
         nb = sc["a_max"][1] + 1
@@ -153,6 +160,12 @@ def day(sc, s, a, omega):
         dB_ = [sum(1 for u in nB if u == life) for life in range(m - 1, 0, -1)]
         tally = {"demand": dA + dB, "met": hA + hB + hS, "received": aA + aB,
                  "expired": sum(1 for u in leftA + leftB if u == 1), "held": len(nA) + len(nB)}
+        # per product: product 0's customers served by product 1 count for product 0
+        tally["product"] = [
+            {"demand": dA, "met": hA + hS, "received": aA,
+             "expired": sum(1 for u in leftA if u == 1), "held": len(nA)},
+            {"demand": dB, "met": hB, "received": aB,
+             "expired": sum(1 for u in leftB if u == 1), "held": len(nB)}]
         return encode(sc, dA_ + dB_), float(reward), tally
     # C
     cap = sc["a_max"][0]
