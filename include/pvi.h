@@ -75,7 +75,8 @@ typedef enum {
     PVI_E_NOT_CONVERGED = 4, /* max_sweeps reached; V and policy still readable */
     PVI_E_NOT_READY = 5,     /* ticket still running, or no solve yet */
     PVI_E_CANCELLED = 6,     /* request cancelled or server shut down */
-    PVI_E_BUSY = 7           /* request does not fit the server's HBM budget */
+    PVI_E_BUSY = 7,          /* request does not fit the server's HBM budget */
+    PVI_E_IO = 8             /* a checkpoint file could not be read or written */
 } pvi_status;
 
 typedef enum {
@@ -170,12 +171,28 @@ typedef struct pvi_solve_opts {
     int32_t check_every;       /* sweeps launched between host checks; 0 = default */
     int32_t time_kernels;      /* 1: time every backup launch with HIP events */
     int32_t stop_rule;         /* pvi_stop_rule (absent in older callers' struct_size: SPAN) */
+    /* Checkpoint files (fields absent in older callers' struct_size read 0).  With
+     * a path and checkpoint_every > 0, the FP64 sweeps write the file (to
+     * `path`.tmp, then renamed over `path`) at the first host check after every
+     * checkpoint_every sweeps, and once more when the solve ends.  With resume = 1
+     * the solve starts from the file at `path` instead of v0: its value history
+     * and sweep count (which max_sweeps and fixed_sweeps include), continuing with
+     * FP64 sweeps whatever the precision, so a resumed solve with the same options
+     * ends with the V, policy and FP64 sweep count of the uninterrupted solve whose
+     * FP64 sweeps wrote the file.  The file must come from a handle with
+     * the same descriptor (checked by a fingerprint of the state space, costs,
+     * discount and demand and life distributions).  FP32 storage sweeps are not
+     * checkpointed.  Not accepted by the request server. */
+    const char* checkpoint_path;
+    int32_t checkpoint_every;  /* >= 0; 0 = no checkpoints written */
+    int32_t resume;            /* 1: start from the checkpoint at checkpoint_path */
 } pvi_solve_opts;
 
 typedef struct pvi_result {
     int32_t status;            /* pvi_status of the solve */
     int32_t sweeps_fp32;       /* sweeps run with FP32 storage */
-    int32_t sweeps_fp64;       /* sweeps run in FP64 (including polish) */
+    int32_t sweeps_fp64;       /* sweeps run in FP64 (including polish; a resumed
+                                  solve counts its checkpoint's too) */
     int32_t backup_launches[2];/* backup launches timed (time_kernels = 1); [0] FP64
                                   storage sweeps, [1] FP32 storage sweeps */
     double final_span;         /* span of the last V_new - V */
@@ -183,7 +200,8 @@ typedef struct pvi_result {
     double dmax, dmin;         /* max and min of the last V_new - V */
     double wall_ms;            /* host wall time of the solve */
     double backup_ms[2];       /* summed backup kernel time of those launches */
-    int64_t logical_backups;   /* sum over sweeps of N_S * sum_a |Omega(s,a)| */
+    int64_t logical_backups;   /* sum over the sweeps this call ran (and the policy
+                                  extraction) of N_S * sum_a |Omega(s,a)| */
     int64_t executed_terms;    /* multiply-adds the kernels actually ran */
 } pvi_result;
 
@@ -230,6 +248,20 @@ pvi_status vi_solve(pvi_mdp* mdp, const pvi_solve_opts* opts, pvi_result* res);
  * precision only; NULL allowed).  For parity checks of single sweeps. */
 pvi_status vi_backup(pvi_mdp* mdp, int32_t precision, const double* v_in, double* v_out,
                      int32_t* policy, double* q_gap);
+
+/* Checkpoint file (little-endian): the 8 bytes "PVICKPT1", uint32 version (1),
+ * uint32 family, uint64 fingerprint of the descriptor, int64 N_S, int32 N_A, int32
+ * stop rule, int32 FP64 sweeps done, int32 stopped (1 when the stopping rule had
+ * fired at that sweep), int32 H, int32 reserved (0), then H tables of N_S FP64
+ * values: V after the last sweep, then the H - 1 before it (H = 1, or under the
+ * periodic rule min(sweeps, P) + 1, the tables its test reads).
+ * checkpoint_read checks the file against the handle and returns the sweep count,
+ * stopped flag and the last table (v: host [N_S], NULL to skip).  Errors:
+ * PVI_E_IO (missing, unreadable or short file), PVI_E_INVALID (wrong magic or
+ * version, a file of another descriptor).  vi_solve returns the same codes for
+ * its checkpoint files (PVI_E_IO also when one cannot be written). */
+pvi_status checkpoint_read(const pvi_mdp* mdp, const char* path, double* v, int32_t* sweeps,
+                           int32_t* stopped);
 
 /* Results of the last solve: policy[N_S] (and q_gap[N_S], nullable) and the FP64
  * values V[N_S] (= c + v for FP32 storage).  PVI_E_NOT_READY before a solve. */

@@ -378,6 +378,9 @@ pvi_status vi_batch_submit(pvi_server* S, pvi_mdp* const* mdps, const pvi_solve_
     if (opts->stop_rule != PVI_STOP_SPAN && opts->stop_rule != PVI_STOP_SUPNORM &&
         opts->stop_rule != PVI_STOP_PERIODIC)
         return fail(PVI_E_INVALID, "vi_batch_submit: bad stop_rule");
+    if (opts->checkpoint_path || opts->checkpoint_every != 0 || opts->resume != 0)
+        return fail(PVI_E_INVALID, "vi_batch_submit: checkpoint files are not served; "
+                                   "call vi_solve");
     for (int i = 0; i < n; ++i) {
         if (!mdps[i]) return fail(PVI_E_INVALID, "vi_batch_submit: NULL handle");
         if (!pvi::family_supported(mdps[i]))

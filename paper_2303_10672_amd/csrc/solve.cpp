@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "checkpoint.h"
 #include "families.h"
 #include "mdp.h"
 
@@ -132,7 +133,11 @@ struct Phase {
     bool time = false;
     int ring = 2;        // FP64 value tables cycled through (period + 1 for the periodic rule)
     int period = 0;      // > 0: run the periodic test after every sweep from this many on
+    int hist0 = 0;       // earlier sweeps whose tables sit in the ring (a resumed solve)
     double gamma = 0.0, thr = 0.0;
+    // checkpoints of FP64 sweeps: file, interval, sweeps done before the phase, rule
+    const char* ckpt = nullptr;
+    int ckpt_every = 0, sweeps0 = 0, rule = 0;
 };
 
 struct PhaseOut {
@@ -144,6 +149,21 @@ struct PhaseOut {
 
 // FP64 value table of slot k: the two ping-pong tables, then the ring's extras.
 double* v64_slot(pvi_mdp* p, int k) { return k < 2 ? p->dev.v64[k] : p->dev.vring[k]; }
+
+// Ring slot of the table `back` sweeps before sweep `i` of a phase.
+int ring_slot(int i, int back, int ring) { return ((i - back) % ring + ring) % ring; }
+
+// Write the checkpoint after `done` sweeps of an FP64 phase: the last table, and
+// under the periodic rule the earlier ones its test reads.
+pvi_status write_checkpoint(pvi_mdp* p, const Phase& ph, int done, bool stopped,
+                            hipStream_t s) {
+    // tables in the ring: those a resume loaded (hist0 before its first) and the
+    // sweeps since
+    const int n = ph.period > 0 ? std::min(ph.hist0 + done, ph.period) + 1 : 1;
+    const double* t[PVI_MAX_PERIODS + 1];
+    for (int j = 0; j < n; ++j) t[j] = v64_slot(p, ring_slot(done, j, ph.ring));
+    return checkpoint_store(p, ph.ckpt, ph.rule, ph.sweeps0 + done, stopped ? 1 : 0, t, n, s);
+}
 
 pvi_status ensure_ring(pvi_mdp* p, int ring) {
     auto& d = p->dev;
@@ -222,7 +242,7 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
     auto& d = p->dev;
     int launched = 0, k = ph.k0;
     double prev_span = -1.0;
-    int prev_sweeps = 0;
+    int prev_sweeps = 0, last_ckpt = 0;
     const int limit = ph.fixed > 0 ? ph.fixed : ph.max_sweeps;
     if (ph.time && (int)d.ev.size() < 2 * ph.kmax) {
         for (int i = (int)d.ev.size(); i < 2 * ph.kmax; ++i) {
@@ -247,9 +267,9 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
         } else {
             for (int i = 0; i < n; ++i) {
                 const void* vin = ph.fp32 ? (const void*)d.v32[launched & 1]
-                                          : v64_slot(p, launched % ph.ring);
+                                          : v64_slot(p, ring_slot(launched, 0, ph.ring));
                 void* vout = ph.fp32 ? (void*)d.v32[(launched + 1) & 1]
-                                     : v64_slot(p, (launched + 1) % ph.ring);
+                                     : v64_slot(p, ring_slot(launched + 1, 0, ph.ring));
                 if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i], s));
                 PVI_HIP(family_backup(p, ph.fp32, ph.kahan, 0, ph.fixed > 0, vin, vout, s));
                 if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i + 1], s));
@@ -257,12 +277,12 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
                     PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, ph.fp32 ? 1 : 0,
                                         ph.fixed > 0, p->d.gamma, s));
                 ++launched;
-                if (ph.period > 0 && launched >= ph.period) {
+                if (ph.period > 0 && launched + ph.hist0 >= ph.period) {
                     // V_{i-j} for j = 0..P, i = launched (a sweep that was skipped after
                     // the stop flag leaves its table untouched, and so does this check)
                     PeriodicArgs a{};
                     for (int j = 0; j <= ph.period; ++j)
-                        a.v[j] = v64_slot(p, (launched - j) % ph.ring);
+                        a.v[j] = v64_slot(p, ring_slot(launched, j, ph.ring));
                     a.P = ph.period;
                     a.gamma = ph.gamma;
                     a.thr = ph.thr;
@@ -286,6 +306,11 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
         if (h.stop) {
             out.stopped = true;
             break;
+        }
+        if (ph.ckpt && ph.ckpt_every > 0 && !ph.fp32 && h.sweeps - last_ckpt >= ph.ckpt_every) {
+            const pvi_status st = write_checkpoint(p, ph, h.sweeps, false, s);
+            if (st != PVI_OK) return st;
+            last_ckpt = h.sweeps;
         }
         // size the next batch from the observed contraction of the span
         if (ph.fixed > 0) {
@@ -364,9 +389,22 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
         return fail(PVI_E_INVALID, "vi_solve: max_sweeps must be > 0");
     if (o->fixed_sweeps < 0) return fail(PVI_E_INVALID, "vi_solve: fixed_sweeps < 0");
     if (!family_supported(p)) return fail(PVI_E_INVALID, "vi_solve: " + family_support_msg(p));
+    if (o->checkpoint_every < 0 || (o->resume != 0 && o->resume != 1))
+        return fail(PVI_E_INVALID, "vi_solve: checkpoint_every >= 0 and resume 0 or 1 required");
+    if ((o->checkpoint_every > 0 || o->resume) && !o->checkpoint_path)
+        return fail(PVI_E_INVALID, "vi_solve: checkpoints need checkpoint_path");
+    const bool resumed = o->resume != 0;
+    Checkpoint ck;
+    pvi_status st = PVI_OK;
+    if (resumed) {
+        if ((st = checkpoint_load(p, o->checkpoint_path, true, ck)) != PVI_OK) return st;
+        if (o->fixed_sweeps > 0 && ck.sweeps > o->fixed_sweeps)
+            return fail(PVI_E_INVALID, "vi_solve: the checkpoint is past fixed_sweeps");
+    }
+    const int k0 = resumed ? ck.sweeps : 0;  // FP64 sweeps done before this call
     std::lock_guard<std::mutex> lock(p->mu);
     const auto t0 = std::chrono::steady_clock::now();
-    pvi_status st = ensure_device(p);
+    st = ensure_device(p);
     if (st != PVI_OK) return st;
     auto& d = p->dev;
     hipStream_t s = o->stream ? (hipStream_t)o->stream : d.own;
@@ -382,9 +420,18 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
     const int kmax = o->check_every > 0 ? o->check_every : 64;
     p->have_result = 0;
 
-    // initial values
+    // initial values: a checkpoint's tables (newest in ring slot 0, earlier ones
+    // behind it), v0, the family's default
     double c0 = 0.0;
-    if (o->v0) {
+    int hist0 = 0;
+    if (resumed) {
+        const int ring = periodic ? period + 1 : 2;
+        const int nt = std::min<int>((int)ck.tables.size(), ring);
+        for (int j = 0; j < nt; ++j)
+            PVI_HIP(hipMemcpyAsync(v64_slot(p, ring_slot(0, j, ring)), ck.tables[j].data(),
+                                   sizeof(double) * p->ns, hipMemcpyHostToDevice, s));
+        hist0 = periodic ? nt - 1 : 0;
+    } else if (o->v0) {
         PVI_HIP(hipMemcpyAsync(d.v64[0], o->v0, sizeof(double) * p->ns, hipMemcpyHostToDevice, s));
         c0 = midrange(o->v0, p->ns);
     } else if (p->family == PVI_FAMILY_SUBST2_L1) {
@@ -395,7 +442,7 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
         PVI_HIP(launch_fill(d.v64[0], 0.0, p->ns, s));
     }
     PhaseOut o32, o64;
-    const bool fp32 = o->precision != PVI_FP64;
+    const bool fp32 = o->precision != PVI_FP64 && !resumed;  // a resume goes on in FP64
     const int kahan = o->precision == PVI_FP32 ? 1 : 0;
     if (fp32) {
         PVI_HIP(launch_to_f32(d.v64[0], d.v32[0], c0, p->ns, s));
@@ -416,8 +463,8 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
     if (fp64_phase) {
         if ((st = init_ctl(p, s, thr, 0.0, o->stop_rule)) != PVI_OK) return st;
         Phase ph;
-        ph.fixed = fp32 ? 0 : o->fixed_sweeps;
-        ph.max_sweeps = max_sweeps;
+        ph.fixed = fp32 ? 0 : (o->fixed_sweeps > 0 ? o->fixed_sweeps - k0 : 0);
+        ph.max_sweeps = max_sweeps - k0;
         ph.kmax = kmax;
         ph.k0 = fp32 ? 1 : 4;
         ph.time = o->time_kernels != 0;
@@ -427,8 +474,23 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
             ph.gamma = g;
             ph.thr = thr;
         }
-        if ((st = run_phase(p, ph, s, o64)) != PVI_OK) return st;
-        p->ret_buf = o64.sweeps % ph.ring;
+        ph.hist0 = hist0;
+        ph.ckpt = o->checkpoint_every > 0 ? o->checkpoint_path : nullptr;
+        ph.ckpt_every = o->checkpoint_every;
+        ph.sweeps0 = k0;
+        ph.rule = o->stop_rule;
+        // a resumed solve whose checkpoint already met the same stopping rule, or
+        // reached its fixed sweep count or the sweep cap, runs no more sweeps
+        const bool done_before = resumed && o->fixed_sweeps <= 0 && ck.stopped &&
+                                 ck.rule == o->stop_rule;
+        const bool nothing_left = o->fixed_sweeps > 0 ? ph.fixed <= 0 : ph.max_sweeps <= 0;
+        if (done_before || nothing_left)
+            o64.stopped = done_before;
+        else if ((st = run_phase(p, ph, s, o64)) != PVI_OK)
+            return st;
+        p->ret_buf = ring_slot(o64.sweeps, 0, ph.ring);
+        if (ph.ckpt && (st = write_checkpoint(p, ph, o64.sweeps, o64.stopped, s)) != PVI_OK)
+            return st;
     } else {
         p->ret_buf = 0;
     }
@@ -442,7 +504,7 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
         const Ctl& h = *d.h_ctl;
         res->status = converged ? PVI_OK : PVI_E_NOT_CONVERGED;
         res->sweeps_fp32 = o32.sweeps;
-        res->sweeps_fp64 = fp64_phase ? o64.sweeps : 0;
+        res->sweeps_fp64 = fp64_phase ? k0 + o64.sweeps : 0;
         res->backup_launches[0] = o64.timed;
         res->backup_launches[1] = o32.timed;
         res->final_span = h.span;
@@ -451,7 +513,7 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
         res->dmin = h.dmin;
         res->backup_ms[0] = o64.backup_ms;
         res->backup_ms[1] = o32.backup_ms;
-        const int64_t sweeps = res->sweeps_fp32 + res->sweeps_fp64 + 1;
+        const int64_t sweeps = o32.sweeps + o64.sweeps + 1;  // run by this call
         res->logical_backups = p->logical_per_sweep * sweeps;
         res->executed_terms = p->executed_per_sweep * sweeps;
         res->wall_ms = std::chrono::duration<double, std::milli>(

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpvi.so")
 
 PVI_OK, PVI_E_INVALID, PVI_E_NOMEM, PVI_E_DEVICE = 0, 1, 2, 3
 PVI_E_NOT_CONVERGED, PVI_E_NOT_READY, PVI_E_CANCELLED, PVI_E_BUSY = 4, 5, 6, 7
+PVI_E_IO = 8
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGED",
                 5: "NOT_READY", 6: "CANCELLED", 7: "BUSY"}
 FAMILY = {"A": 0, "B": 1, "C": 2, "B1": 3}
@@ -59,6 +60,8 @@ class Opts(ctypes.Structure):
         ("fixed_sweeps", ctypes.c_int32), ("v0", ctypes.POINTER(ctypes.c_double)),
         ("stream", ctypes.c_void_p), ("check_every", ctypes.c_int32),
         ("time_kernels", ctypes.c_int32), ("stop_rule", ctypes.c_int32),
+        ("checkpoint_path", ctypes.c_char_p), ("checkpoint_every", ctypes.c_int32),
+        ("resume", ctypes.c_int32),
     ]
 
 
@@ -124,6 +127,7 @@ def load():
         "vi_backup": (i32, [vp, i32, dp, dp, _P(i32), dp]),
         "policy_get": (i32, [vp, _P(i32), dp]),
         "value_get": (i32, [vp, dp]),
+        "checkpoint_read": (i32, [vp, ctypes.c_char_p, dp, _P(i32), _P(i32)]),
         "policy_get_device": (i32, [vp, vp, vp]),
         "pvi_server_create": (i32, [i64, i32, _P(vp)]),
         "pvi_server_destroy": (i32, [vp]),
@@ -268,8 +272,13 @@ def mdp_life_probs(m):
 
 
 def make_opts(precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0, v0=None,
-              stream=None, check_every=0, time_kernels=False, sc=None, stop_rule="span"):
+              stream=None, check_every=0, time_kernels=False, sc=None, stop_rule="span",
+              checkpoint=None, checkpoint_every=0, resume=False):
     o = Opts()
+    if checkpoint is not None:
+        o.checkpoint_path = os.fsencode(checkpoint)
+    o.checkpoint_every = int(checkpoint_every)
+    o.resume = 1 if resume else 0
     o.stop_rule = STOP_RULE[stop_rule]
     o.struct_size = ctypes.sizeof(Opts)
     o.precision = PRECISION[precision]
@@ -285,11 +294,12 @@ def make_opts(precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0, v0=
 
 def vi_solve(m, precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0, v0=None,
              stream=None, check_every=0, time_kernels=False, allow_not_converged=False,
-             stop_rule="span"):
-    """Blocking solve; returns the pvi_result fields as a dict."""
+             stop_rule="span", checkpoint=None, checkpoint_every=0, resume=False):
+    """Blocking solve; returns the pvi_result fields as a dict.  checkpoint: file
+    written every checkpoint_every FP64 sweeps and at the end, or read when resume."""
     v0a = None if v0 is None else np.ascontiguousarray(v0, dtype=np.float64)
     o = make_opts(precision, eps, max_sweeps, fixed_sweeps, v0a, stream, check_every,
-                  time_kernels, m.sc, stop_rule)
+                  time_kernels, m.sc, stop_rule, checkpoint, checkpoint_every, resume)
     r = Result()
     st = _lib.vi_solve(m.handle, ctypes.byref(o), ctypes.byref(r))
     if not (allow_not_converged and st == PVI_E_NOT_CONVERGED):
@@ -321,6 +331,15 @@ def value_get(m):
     v = np.zeros(m.n_states)
     _check(_lib.value_get(m.handle, _dptr(v)), "value_get")
     return v
+
+
+def checkpoint_read(m, path):
+    """(last V [N_S], FP64 sweeps, stopped) of a checkpoint file of this handle's MDP."""
+    v = np.zeros(m.n_states)
+    sweeps, stopped = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.checkpoint_read(m.handle, os.fsencode(path), _dptr(v), ctypes.byref(sweeps),
+                                ctypes.byref(stopped)), "checkpoint_read")
+    return v, int(sweeps.value), bool(stopped.value)
 
 
 def policy_get_device(m, d_policy_ptr, stream=None):

@@ -2,6 +2,7 @@
 import ctypes
 import os
 import re
+import struct
 
 import numpy as np
 import pytest
@@ -31,7 +32,8 @@ def test_library_exports_every_declared_function():
 def test_struct_sizes_match_header_layout():
     # pvi_mdp_desc: 5 int32 + 3x2 int32 + 2x7x2 doubles + 2 ptrs + 16 doubles + ...
     assert ctypes.sizeof(pvi.Desc) % 8 == 0
-    assert ctypes.sizeof(pvi.Opts) == 56
+    assert ctypes.sizeof(pvi.Opts) == 72
+    assert pvi.Opts.checkpoint_path.offset == 56
     assert ctypes.sizeof(pvi.Result) == 96
     assert ctypes.sizeof(pvi.RolloutOpts) == 80
     assert pvi.RolloutOpts.product_kpis.offset == 64
@@ -234,3 +236,43 @@ def test_lead_time_one_two_product_family_validation():
     assert e.value.status == pvi.PVI_E_INVALID and "on the GPU" in str(e.value)
     m = pvi.mdp_create(W.scenario_b_paper(3, 1))
     assert (m.n_states, m.n_actions) == (16777216, 256)
+
+
+def test_checkpoint_options_are_checked_before_the_device(tmp_path):
+    """Checkpoint options and files are validated on the host: a bad interval, a
+    missing path, a missing file (PVI_E_IO), a file that is not a checkpoint or is of
+    another version (PVI_E_INVALID); checkpoint_read reports the same."""
+    m = pvi.mdp_create(W.config0())
+
+    def solve(**kw):
+        o = pvi.make_opts("fp64", 1e-4, 1000, 0, None, None, 0, False, m.sc, "span",
+                          kw.get("checkpoint"), kw.get("every", 0), kw.get("resume", False))
+        return pvi._lib.vi_solve(m.handle, ctypes.byref(o), None)
+
+    err = lambda: pvi._lib.pvi_last_error().decode()
+    assert solve(every=-1, checkpoint="x") == pvi.PVI_E_INVALID
+    assert solve(every=5) == pvi.PVI_E_INVALID and "checkpoint_path" in err()
+    assert solve(resume=True) == pvi.PVI_E_INVALID
+    missing = str(tmp_path / "none.ckpt")
+    assert solve(checkpoint=missing, resume=True) == pvi.PVI_E_IO
+    junk = tmp_path / "junk.ckpt"
+    junk.write_bytes(b"not a checkpoint at all, just some bytes of text" * 2)
+    assert solve(checkpoint=str(junk), resume=True) == pvi.PVI_E_INVALID
+    assert "not a checkpoint" in err()
+    short = tmp_path / "short.ckpt"
+    short.write_bytes(b"PVICKPT1")
+    assert solve(checkpoint=str(short), resume=True) == pvi.PVI_E_IO
+    # right magic, another descriptor's fingerprint
+    hdr = struct.pack("<8sIIQqiiiiii", b"PVICKPT1", 1, 0, 12345, 121, 11, 0, 3, 0, 1, 0)
+    other = tmp_path / "other.ckpt"
+    other.write_bytes(hdr + np.zeros(121).tobytes())
+    assert solve(checkpoint=str(other), resume=True) == pvi.PVI_E_INVALID
+    assert "another MDP" in err()
+    newer = tmp_path / "newer.ckpt"
+    newer.write_bytes(struct.pack("<8sIIQqiiiiii", b"PVICKPT1", 2, 0, 0, 121, 11, 0, 3, 0, 1, 0))
+    assert solve(checkpoint=str(newer), resume=True) == pvi.PVI_E_INVALID
+    assert "version" in err()
+    with pytest.raises(pvi.PviError):
+        pvi.checkpoint_read(m, missing)
+    with pytest.raises(pvi.PviError):
+        pvi.checkpoint_read(m, str(other))

@@ -1,0 +1,158 @@
+"""Checkpoint files of vi_solve: written during and at the end of the FP64 sweeps,
+read back by a fresh handle, which then ends exactly where an uninterrupted solve
+ends (V, policy and sweep count bit-identical), under the span, sup-norm and
+periodic stopping rules (the periodic rule's history travels in the file).  The
+file layout is checked against its documented fields and against the value tables
+of solves stopped at the same sweeps.
+"""
+import os
+import struct
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2303_10672_amd import pvi
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "A-span": (W.config0(), "span"),
+    "A-lifo-supnorm": (W.scenario_a_paper(2, 1, 7.0, "lifo"), "supnorm"),
+    "B-span": (W.scenario_b(m=3, a_max=(6, 5), d_max=(12, 10), means=(4.0, 3.0), rho=0.5),
+               "span"),
+    "B1-gamma1": (W.scenario_b_paper(2, "1"), "span"),
+    "C-periodic": (W.scenario_c(m=3, a_max=6, d_max=10, c0=[0.0, 1.0, 0.5]), "periodic"),
+}
+
+HEADER = struct.Struct("<8sIIQqiiiiii")
+
+
+def _parse(path, n_states):
+    raw = open(path, "rb").read()
+    (magic, version, family, _fp, ns, na, rule, sweeps, stopped, hist,
+     reserved) = HEADER.unpack_from(raw)
+    assert magic == b"PVICKPT1" and version == 1 and reserved == 0 and ns == n_states
+    tables = np.frombuffer(raw, dtype="<f8", offset=HEADER.size)
+    assert tables.size == hist * ns
+    return dict(family=family, na=na, rule=rule, sweeps=sweeps, stopped=stopped,
+                tables=tables.reshape(hist, ns))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_resume_equals_uninterrupted(name, tmp_path):
+    sc, rule = CASES[name]
+    ref_m = pvi.mdp_create(sc)
+    ref = pvi.vi_solve(ref_m, precision="fp64", stop_rule=rule)
+    n = ref["sweeps_fp64"]
+    V_ref, (P_ref, G_ref) = pvi.value_get(ref_m), pvi.policy_get(ref_m)
+    ks = sorted({1, 3, max(1, n // 3), n // 2, n - 1} - {0})
+    for k in ks:
+        path = str(tmp_path / f"{name}-{k}.ckpt")
+        m = pvi.mdp_create(sc)
+        r = pvi.vi_solve(m, precision="fp64", stop_rule=rule, max_sweeps=k, checkpoint=path,
+                         checkpoint_every=2, allow_not_converged=True)
+        assert r["status"] == pvi.PVI_E_NOT_CONVERGED and r["sweeps_fp64"] == k
+        v, sweeps, stopped = pvi.checkpoint_read(m, path)
+        assert (sweeps, stopped) == (k, False)
+        assert np.array_equal(v, pvi.value_get(m))
+        f = _parse(path, m.n_states)
+        assert f["rule"] == pvi.STOP_RULE[rule] and f["na"] == m.n_actions
+        assert f["tables"].shape[0] == (min(k, sc["n_periods"]) + 1 if rule == "periodic"
+                                        else 1)
+        del m
+        fresh = pvi.mdp_create(sc)                      # a new process would do the same
+        res = pvi.vi_solve(fresh, precision="fp64", stop_rule=rule, checkpoint=path,
+                           resume=True)
+        assert res["status"] == pvi.PVI_OK and res["sweeps_fp64"] == n
+        assert np.array_equal(pvi.value_get(fresh), V_ref)
+        P, G = pvi.policy_get(fresh)
+        assert np.array_equal(P, P_ref) and np.array_equal(G, G_ref)
+
+
+def test_periodic_history_tables():
+    """Under the periodic rule the file holds V_k, V_{k-1}, ..., V_{k-P}: each equals
+    the last table of a solve stopped after that many sweeps."""
+    sc, rule = CASES["C-periodic"]
+    P = sc["n_periods"]
+    k = P + 4
+    path = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"pvi-hist-{os.getpid()}.ckpt")
+    m = pvi.mdp_create(sc)
+    pvi.vi_solve(m, precision="fp64", stop_rule=rule, max_sweeps=k, checkpoint=path,
+                 checkpoint_every=100, allow_not_converged=True)
+    f = _parse(path, m.n_states)
+    os.remove(path)
+    assert f["sweeps"] == k and f["tables"].shape[0] == P + 1
+    for j in range(P + 1):
+        pvi.vi_solve(m, precision="fp64", stop_rule=rule, max_sweeps=k - j,
+                     allow_not_converged=True)
+        assert np.array_equal(f["tables"][j], pvi.value_get(m)), j
+
+
+def test_periodic_checkpoints_during_the_solve(tmp_path):
+    """checkpoint_every = 1 rewrites the file after every host check; the file the
+    finished solve leaves says stopped, and resuming from it runs no more sweeps."""
+    sc, rule = CASES["C-periodic"]
+    path = str(tmp_path / "c.ckpt")
+    m = pvi.mdp_create(sc)
+    r = pvi.vi_solve(m, precision="fp64", stop_rule=rule, checkpoint=path, checkpoint_every=1,
+                     check_every=2)
+    v, sweeps, stopped = pvi.checkpoint_read(m, path)
+    assert (sweeps, stopped) == (r["sweeps_fp64"], True)
+    assert np.array_equal(v, pvi.value_get(m))
+    fresh = pvi.mdp_create(sc)
+    again = pvi.vi_solve(fresh, precision="fp64", stop_rule=rule, checkpoint=path, resume=True)
+    assert again["sweeps_fp64"] == r["sweeps_fp64"]
+    # no sweeps, only the policy extraction
+    assert again["logical_backups"] == r["logical_backups"] // (r["sweeps_fp64"] + 1)
+    assert np.array_equal(pvi.value_get(fresh), v)
+    assert np.array_equal(pvi.policy_get(fresh)[0], pvi.policy_get(m)[0])
+
+
+def test_fixed_sweeps_and_fp32_schedule(tmp_path):
+    sc = W.scenario_a(m=3, L=2, a_max=8, d_max=20)
+    path = str(tmp_path / "a.ckpt")
+    m = pvi.mdp_create(sc)
+    pvi.vi_solve(m, precision="fp64", fixed_sweeps=10, checkpoint=path, checkpoint_every=4)
+    assert pvi.checkpoint_read(m, path)[1:] == (10, False)
+    straight = pvi.mdp_create(sc)
+    pvi.vi_solve(straight, precision="fp64", fixed_sweeps=25)
+    fresh = pvi.mdp_create(sc)
+    r = pvi.vi_solve(fresh, precision="fp64", fixed_sweeps=25, checkpoint=path, resume=True)
+    assert r["sweeps_fp64"] == 25
+    assert np.array_equal(pvi.value_get(fresh), pvi.value_get(straight))
+    assert np.array_equal(pvi.policy_get(fresh)[0], pvi.policy_get(straight)[0])
+    with pytest.raises(pvi.PviError):                 # the file is past 5 sweeps
+        pvi.vi_solve(fresh, precision="fp64", fixed_sweeps=5, checkpoint=path, resume=True)
+    # FP32 schedule: the FP64 polish sweeps are checkpointed; the end file is the result
+    p32 = str(tmp_path / "a32.ckpt")
+    r = pvi.vi_solve(m, precision="fp32", checkpoint=p32, checkpoint_every=1)
+    v, sweeps, stopped = pvi.checkpoint_read(m, p32)
+    assert (sweeps, stopped) == (r["sweeps_fp64"], True)
+    assert np.array_equal(v, pvi.value_get(m))
+
+
+def test_other_descriptor_and_truncated_file(tmp_path):
+    sc, rule = CASES["A-span"]
+    path = str(tmp_path / "a.ckpt")
+    m = pvi.mdp_create(sc)
+    pvi.vi_solve(m, precision="fp64", max_sweeps=5, checkpoint=path, checkpoint_every=1,
+                 allow_not_converged=True)
+    other = pvi.mdp_create(dict(sc, gamma=0.95))
+    with pytest.raises(pvi.PviError, match="another MDP"):
+        pvi.vi_solve(other, precision="fp64", checkpoint=path, resume=True)
+    raw = open(path, "rb").read()
+    cut = str(tmp_path / "cut.ckpt")
+    open(cut, "wb").write(raw[:-8])
+    o = pvi.make_opts("fp64", 1e-4, 1000, 0, None, None, 0, False, sc, "span", cut, 0, True)
+    assert pvi._lib.vi_solve(m.handle, pvi.ctypes.byref(o), None) == pvi.PVI_E_IO
+    server = pvi.Server()
+    try:
+        arr = (pvi.ctypes.c_void_p * 1)(m.handle)
+        t = (pvi.ctypes.c_uint64 * 1)()
+        o = pvi.make_opts("fp64", 1e-4, 1000, 0, None, None, 0, False, sc, "span", path, 1)
+        assert pvi._lib.vi_batch_submit(server.handle, arr, pvi.ctypes.byref(o), 1, t) == \
+            pvi.PVI_E_INVALID
+        assert "checkpoint" in pvi._lib.pvi_last_error().decode()
+    finally:
+        server.close()
