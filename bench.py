@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving arrival rate per second (0: 0.7 x closed-loop rate)")
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--paper-checkpoints", action="store_true",
+                    help="paper workloads: also time an FP64 solve that writes a checkpoint "
+                         "file as often as the paper did (A every 100 sweeps, B and C "
+                         "every sweep)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a known-traffic "
                          "kernel for scaling HBM counters)")
@@ -274,6 +278,22 @@ def bench_single(args, pvi, W, cfg):
     print(json.dumps(line), flush=True)
 
 
+def checkpointed_solve(args, pvi, m, every, **kw):
+    """Wall time of one FP64 solve that writes a checkpoint file every `every` sweeps
+    (a host check after each), as the paper's wall times include; None unless asked."""
+    if not args.paper_checkpoints:
+        return None
+    path = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"pvi-bench-{os.getpid()}.ckpt")
+    t0 = time.perf_counter()
+    r = pvi.vi_solve(m, precision="fp64", checkpoint=path, checkpoint_every=every,
+                     check_every=every, **kw)
+    dt = time.perf_counter() - t0
+    size = os.path.getsize(path)
+    os.remove(path)
+    return {"solve_ms": dt * 1e3, "checkpoint_every": every, "sweeps_fp64": r["sweeps_fp64"],
+            "file_bytes": size}
+
+
 def bench_paper_a(args, pvi, W):
     """The paper's 32 scenario-A experiments (Appendix A settings, sup-norm stop with
     eps 1e-4): wall time of one full solve each, FP64 and the FP32 schedule, after one
@@ -294,6 +314,8 @@ def bench_paper_a(args, pvi, W):
             row[prec] = {"solve_ms": dt * 1e3, "sweeps_fp32": r["sweeps_fp32"],
                          "sweeps_fp64": r["sweeps_fp64"],
                          "backups_per_s": r["logical_backups"] / dt}
+        row["fp64_checkpointed"] = checkpointed_solve(args, pvi, m, 100, eps=1e-4,
+                                                      stop_rule="supnorm")
         pol, _ = pvi.policy_get(m)
         row["V_empty"] = float(pvi.value_get(m)[0])
         row["order_when_empty"] = int(pol[0])
@@ -336,6 +358,8 @@ def bench_paper_c(args, pvi, W):
                          "sweeps_fp64": r["sweeps_fp64"],
                          "backups_per_s": r["logical_backups"] / dt,
                          "backup_ms": list(r["backup_ms"])}
+        row["fp64_checkpointed"] = checkpointed_solve(args, pvi, m, 1, eps=1e-4,
+                                                      stop_rule="periodic")
         print(f"C m={mm} exp {exp}: {row['states']} states, fp64 "
               f"{row['fp64']['solve_ms']:.1f} ms ({row['fp64']['sweeps_fp64']} sweeps), fp32 "
               f"{row['fp32']['solve_ms']:.1f} ms", file=sys.stderr, flush=True)
@@ -371,6 +395,9 @@ def bench_paper_b(args, pvi, W):
                          "backups_per_s": r["logical_backups"] / dt,
                          "backup_ms": list(r["backup_ms"]),
                          "backup_launches": list(r["backup_launches"])}
+        row["fp64_checkpointed"] = checkpointed_solve(args, pvi, m, 1,
+                                                      **({"fixed_sweeps": fixed} if fixed
+                                                         else {}))
         print(f"B m={mm} exp {exp}: {row['states']} states, fp64 "
               f"{row['fp64']['solve_ms']:.1f} ms ({row['fp64']['sweeps_fp64']} sweeps), fp32 "
               f"{row['fp32']['solve_ms']:.1f} ms", file=sys.stderr, flush=True)
