@@ -112,14 +112,37 @@ __global__ __launch_bounds__(256) void c_stage_u_kernel(CDev p) {
     }
 }
 
+// Pointer into the constant address space: loads through it whose address is the
+// same for every lane go through the scalar cache.
+typedef const __attribute__((address_space(4))) double* ConstF64;
+
+// Rows r .. nr-1 of one lane's first merge, one row per template instance: term
+// (r, y) reads the slab at the lane's offsets for c(x_2 + y) and c(x_1 + r - y).
+template <typename VT, int RC, int r>
+__device__ __forceinline__ void c_merge2_rows(const double* slab, const int (&o2)[RC],
+                                              const int (&o1)[RC], ConstF64 w, int R, int nr,
+                                              int rfirst, VT* out, int64_t nblk) {
+    if constexpr (r < RC) {
+        if (r >= nr) return;
+        if (r >= rfirst) {
+            const ConstF64 wr = w + r * R;
+            double acc = 0.0;
+#pragma unroll
+            for (int y = 0; y <= r; ++y) acc = fma(wr[y], slab[o2[y] + o1[r - y]], acc);
+            out[(int64_t)r * nblk] = (VT)acc;
+        }
+        c_merge2_rows<VT, RC, r + 1>(slab, o2, o1, w, R, nr, rfirst, out, nblk);
+    }
+}
+
 // First merge (life class 2) straight from U.  One workgroup per (tau, y_m, digits
 // above 2): the R x R slab U[.., z_2, z_1] sits in LDS and each lane (x_2, x_1)
 // produces T_2 for every remaining count r:
-//   T_2(r) = sum_{y<=r} Bin(y; r, q_2) U(.., c(x_2 + y), c(x_1 + r - y)).
-template <typename VT>
+//   T_2(r) = sum_{y<=r} Bin(y; r, q_2) U(.., c(x_2 + y), c(x_1 + r - y)),
+// terms added in the order y = 0, 1, .., r, both sums unrolled up to RC >= R.
+template <typename VT, int RC>
 __global__ __launch_bounds__(1024) void c_merge2_kernel(CDev p, const void* in_, void* out_) {
     __shared__ double slab[32 * 32];
-    __shared__ double bq[32 * 32];
     if (!p.extract && p.ctl->stop) return;
     const int R = p.R, tid = threadIdx.x;
     const int tym = blockIdx.y, tau = tym / R, ym = tym - tau * R;
@@ -127,20 +150,40 @@ __global__ __launch_bounds__(1024) void c_merge2_kernel(CDev p, const void* in_,
     const int nr = min(R - ym, p.alim - ym + 1);  // r = 0 .. min(a_max, alim) - y_m
     if (nr <= 0) return;
     const VT* U = reinterpret_cast<const VT*>(in_) + ((int64_t)tau * R + ym) * p.nblk + hi * R * R;
-    for (int i = tid; i < R * R; i += blockDim.x) {
-        slab[i] = (double)U[i];
-        bq[i] = p.binq[(size_t)2 * R * R + i];
-    }
+    for (int i = tid; i < R * R; i += blockDim.x) slab[i] = (double)U[i];
     __syncthreads();
     if (tid >= R * R) return;
     const int x2 = tid / R, x1 = tid - x2 * R;
-    VT* T = reinterpret_cast<VT*>(out_);
-    const int64_t row0 = (int64_t)tau * p.npair + p.pair_base[ym];
-    for (int r = p.top_only ? nr - 1 : 0; r < nr; ++r) {
-        double acc = 0.0;
-        for (int y = 0; y <= r; ++y)
-            acc = fma(bq[r * R + y], slab[min(x2 + y, R - 1) * R + min(x1 + r - y, R - 1)], acc);
-        T[(row0 + r) * p.nblk + hi * R * R + tid] = (VT)acc;
+    int o2[RC], o1[RC];  // slab offsets of c(x_2 + y) rows and c(x_1 + k) columns
+#pragma unroll
+    for (int y = 0; y < RC; ++y) {
+        o2[y] = min(x2 + y, R - 1) * R;
+        o1[y] = min(x1 + y, R - 1);
+    }
+    const ConstF64 w = (ConstF64)(p.binq + (size_t)2 * R * R);
+    VT* T = reinterpret_cast<VT*>(out_) + ((int64_t)tau * p.npair + p.pair_base[ym]) * p.nblk +
+            hi * R * R + tid;
+    c_merge2_rows<VT, RC, 0>(slab, o2, o1, w, R, nr, p.top_only ? nr - 1 : 0, T, p.nblk);
+}
+
+// Rows r .. nr-1 of one lane's merge output (rows below rfirst skipped), one row per
+// template instance so that each row's sum has a compile-time length r + 1.
+template <typename VT, int LB, int RC, int r>
+__device__ __forceinline__ void c_merge_rows(const VT* slab, const int (&zoff)[RC], ConstF64 w,
+                                             int R, int nr, int rfirst, VT* out,
+                                             int64_t nblk) {
+    if constexpr (r < RC) {
+        if (r >= nr) return;
+        if (r >= rfirst) {
+            constexpr int RS = RC * LB;
+            const ConstF64 wr = w + r * R;
+            double acc = 0.0;
+#pragma unroll
+            for (int y = 0; y <= r; ++y)
+                acc = fma(wr[y], (double)slab[(r - y) * RS + zoff[y]], acc);
+            out[(int64_t)r * nblk] = (VT)acc;
+        }
+        c_merge_rows<VT, LB, RC, r + 1>(slab, zoff, w, R, nr, rfirst, out, nblk);
     }
 }
 
@@ -150,19 +193,21 @@ __global__ __launch_bounds__(1024) void c_merge2_kernel(CDev p, const void* in_,
 //   T_j(r) = sum_{y<=r} Bin(y; r, q_j) T_{j-1}(.., c(x_j + y), ..; r - y)
 // for every r.  Lanes with consecutive lo touch consecutive addresses; each lane
 // stages one (z_j, lo) column over all r', so no index division runs per element.
-// The sum over y is unrolled up to RC >= R, so each term is an LDS read at a
-// precomputed per-lane offset, a weight Bin(y; r, q_j) (staged in LDS, the same
-// for all lanes) and one multiply-add.  The grid
-// is one-dimensional and remapped so that each XCD takes a contiguous run of blocks:
-// neighbouring lo-blocks share cache lines, which then meet in one L2.
+// Both sums are unrolled at compile time up to RC >= R: rows of the slab are RC * LB
+// apart, so term (r, y) is an LDS read at the lane's offset for c(x_j + y) plus the
+// constant (r - y) RC LB, the reads of a row can all be in flight at once, and the
+// binomial weights, the same for every lane, come through the scalar cache.  Terms
+// are added in the order y = 0, 1, .., r.  The grid is one-dimensional and remapped
+// so that each XCD takes a contiguous run of blocks: neighbouring lo-blocks share
+// cache lines, which then meet in one L2.
 template <typename VT, int LB, int RC>
 __global__ __launch_bounds__(1024) void c_merge_kernel(CDev p, int j, const void* in_,
                                                        void* out_) {
     extern __shared__ __align__(16) unsigned char smem[];
     if (!p.extract && p.ctl->stop) return;
+    constexpr int RS = RC * LB;  // slab row stride
     const int R = p.R, tid = threadIdx.x;
-    VT* slab = reinterpret_cast<VT*>(smem);  // [r'][z][LB]
-    double* bq = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)R * R * LB);  // [r][y]
+    VT* slab = reinterpret_cast<VT*>(smem);  // [r'][z < RC][LB]
     // block decomposition in 32 bits (the launcher checks that the counts fit)
     const int nlo = (int)p.pow_r[j - 1];  // R^(j-1) values below digit j
     const int nlob = (nlo + LB - 1) / LB;
@@ -180,28 +225,26 @@ __global__ __launch_bounds__(1024) void c_merge_kernel(CDev p, int j, const void
     const bool lane_ok = xz < R && lo0 + l < nlo;
     const VT* in = reinterpret_cast<const VT*>(in_);
     if (xz < R) {
+        // every row's load is issued before the first LDS write waits for one
         const VT* src = in + row0 * p.nblk + base + (int64_t)xz * nlo + l;
-        for (int rr = 0; rr < nr; ++rr)
-            slab[(rr * R + xz) * LB + l] = lo0 + l < nlo ? src[(int64_t)rr * p.nblk] : VT(0);
+        const bool ok = lo0 + l < nlo;
+        VT v[RC];
+#pragma unroll
+        for (int rr = 0; rr < RC; ++rr)
+            v[rr] = ok && rr < nr ? src[(int64_t)rr * p.nblk] : VT(0);
+#pragma unroll
+        for (int rr = 0; rr < RC; ++rr)
+            if (rr < nr) slab[rr * RS + xz * LB + l] = v[rr];
     }
-    for (int i = tid; i < R * R; i += blockDim.x) bq[i] = p.binq[(size_t)j * R * R + i];
     __syncthreads();
     if (!lane_ok) return;
-    // term y of row r reads slab[r - y][c(x_j + y)][lo] at r * rstride + adj[y]
-    const int rstride = R * LB;
-    int adj[RC];
+    int zoff[RC];  // slab offset of column c(x_j + y) in row 0
 #pragma unroll
-    for (int y = 0; y < RC; ++y) adj[y] = min(xz + y, R - 1) * LB + l - y * rstride;
+    for (int y = 0; y < RC; ++y) zoff[y] = min(xz + y, R - 1) * LB + l;
+    // weights Bin(y; r, q_j) at r R + y
+    const ConstF64 w = (ConstF64)(p.binq + (size_t)j * R * R);
     VT* out = reinterpret_cast<VT*>(out_) + row0 * p.nblk + base + (int64_t)xz * nlo + l;
-    for (int r = p.top_only ? nr - 1 : 0; r < nr; ++r) {
-        const VT* sr = slab + r * rstride;
-        const double* w = bq + r * R;
-        double acc = 0.0;
-#pragma unroll
-        for (int y = 0; y < RC; ++y)
-            if (y <= r) acc = fma(w[y], (double)sr[adj[y]], acc);
-        out[(int64_t)r * p.nblk] = (VT)acc;
-    }
+    c_merge_rows<VT, LB, RC, 0>(slab, zoff, w, R, nr, p.top_only ? nr - 1 : 0, out, p.nblk);
 }
 
 // Q(tau, x, a) = -C_f [a > 0] + sum_y Bin(y; a, p_m) T_{m-1}(tau, y, x; a - y), then
@@ -269,9 +312,13 @@ __global__ __launch_bounds__(256) void c_final_kernel(CDev p, const void* tin) {
     }
 }
 
+// compile-time bound of the merge sums for R (the merge kernels' RC)
+static int c_rc_for(int R) { return R <= 8 ? 8 : R <= 16 ? 16 : R <= 24 ? 24 : 32; }
+
+// LDS of one merge workgroup: R rows of RC x lb slab values
 template <typename VT>
 static size_t c_lds_for(const CDev& p, int lb) {
-    return sizeof(VT) * (size_t)p.R * p.R * lb + sizeof(double) * p.R * p.R;
+    return sizeof(VT) * (size_t)p.R * c_rc_for(p.R) * lb;
 }
 
 template <typename VT>
@@ -333,8 +380,15 @@ static hipError_t launch_c_chain(const CDev& p, void* top, hipStream_t s) {
         }
         if (j == 2) {
             const int threads = ((p.R * p.R + 63) / 64) * 64;
-            hipLaunchKernelGGL((c_merge2_kernel<VT>), dim3((unsigned)(p.nblk / (p.R * p.R)), p.P * p.R),
-                               dim3(threads), 0, s, q, in, out);
+            const dim3 grid((unsigned)(p.nblk / (p.R * p.R)), p.P * p.R);
+            if (p.R <= 8)
+                hipLaunchKernelGGL((c_merge2_kernel<VT, 8>), grid, dim3(threads), 0, s, q, in, out);
+            else if (p.R <= 16)
+                hipLaunchKernelGGL((c_merge2_kernel<VT, 16>), grid, dim3(threads), 0, s, q, in, out);
+            else if (p.R <= 24)
+                hipLaunchKernelGGL((c_merge2_kernel<VT, 24>), grid, dim3(threads), 0, s, q, in, out);
+            else
+                hipLaunchKernelGGL((c_merge2_kernel<VT, 32>), grid, dim3(threads), 0, s, q, in, out);
         } else {
             // the tuned block width of this level, else the widest block of low digits
             // (up to 64 bytes per slab row) whose slab stays within 32 KB of LDS, so
