@@ -56,7 +56,8 @@
  *  - Scenario C times its merge kernels at each candidate block width at the first
  *    solve of a shape (R, m, weekdays) in a process and keeps the fastest; results do
  *    not depend on the choice.  PVI_TUNE=0 in the environment skips the timing (the
- *    LDS rule then chooses); PVI_TUNE_VERBOSE=1 prints the choices to stderr.
+ *    LDS rule then chooses); PVI_TUNE_VERBOSE=1 prints the choices to stderr;
+ *    PVI_C_BLOCK=4|8|12|16|32 fixes the width wherever it fits (for tests).
  */
 #ifndef PVI_H
 #define PVI_H

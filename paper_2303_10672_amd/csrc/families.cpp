@@ -265,6 +265,19 @@ std::map<TuneKey, TuneVal> g_tune;
 
 pvi_status tune_c(pvi_mdp* p) {
     std::memset(p->c_lb, 0, sizeof(p->c_lb));
+    // PVI_C_BLOCK=<width>: that block width at every merge level where it fits
+    const char* force = std::getenv("PVI_C_BLOCK");
+    if (force) {
+        const int w = std::atoi(force);
+        if (w != 4 && w != 8 && w != 12 && w != 16 && w != 32)
+            return fail(PVI_E_INVALID, "PVI_C_BLOCK must be 4, 8, 12, 16 or 32");
+        const int R = p->rad[0], rc = R <= 8 ? 8 : R <= 16 ? 16 : R <= 24 ? 24 : 32;
+        for (int a = 0; a < 2; ++a) {
+            const bool fits = (size_t)(a ? 4 : 8) * R * rc * w <= 65536 && R * w <= 1024;
+            for (int j = 3; j < 10; ++j) p->c_lb[a][j] = fits ? w : 0;
+        }
+        return PVI_OK;
+    }
     const char* env = std::getenv("PVI_TUNE");
     if ((env && std::strcmp(env, "0") == 0) || p->m < 4) return PVI_OK;
     const TuneKey key{p->rad[0], p->m, p->P};

@@ -435,7 +435,9 @@ static hipError_t launch_merge_rc(const CDev& p, int j, const void* in, void* ou
 template <typename VT>
 static hipError_t launch_merge_lb(const CDev& p, int j, const void* in, void* out, int lb,
                                   dim3 grid, int threads, size_t lds, hipStream_t s) {
+    if (lb == 32) return launch_merge_rc<VT, 32>(p, j, in, out, grid, threads, lds, s);
     if (lb == 16) return launch_merge_rc<VT, 16>(p, j, in, out, grid, threads, lds, s);
+    if (lb == 12) return launch_merge_rc<VT, 12>(p, j, in, out, grid, threads, lds, s);
     if (lb == 8) return launch_merge_rc<VT, 8>(p, j, in, out, grid, threads, lds, s);
     return launch_merge_rc<VT, 4>(p, j, in, out, grid, threads, lds, s);
 }
@@ -466,7 +468,7 @@ static hipError_t tune_levels(const CDev& p, hipStream_t s, int32_t* lb_out) {
     }
     for (int j = 3; j <= p.m - 1 && j < 10 && e == hipSuccess; ++j) {
         float best = 1e30f;
-        for (int lb : {4, 8, 16}) {
+        for (int lb : {4, 8, 12, 16, 32}) {
             if (c_lds_for<VT>(p, lb) > 65536 || p.R * lb > 1024) continue;
             if ((e = launch_merge_once<VT>(p, j, lb, s)) != hipSuccess) break;  // warm-up
             if ((e = hipEventRecord(e0, s)) != hipSuccess) break;

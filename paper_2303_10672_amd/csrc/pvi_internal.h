@@ -216,7 +216,7 @@ hipError_t launch_to_f32(const double* v64, float* v32, double c, int64_t n, hip
 hipError_t launch_fill(double* v, double value, int64_t n, hipStream_t s);
 // kernels_c.hip
 hipError_t launch_backup_c(const CDev& p, int storage_fp32, int extract, hipStream_t s);
-// Time the merge kernels of levels 3..m-1 at each block width that fits (4, 8, 16 low
+// Time the merge kernels of levels 3..m-1 at each block width that fits (4, 8, 12, 16, 32 low
 // digits per workgroup) on the handle's own tables, and write the fastest into lb.
 hipError_t tune_c_merge(const CDev& p, hipStream_t s, int32_t lb[2][10]);
 // kernels_b.hip
