@@ -115,6 +115,7 @@ __global__ __launch_bounds__(256) void c_stage_u_kernel(CDev p) {
 // Pointer into the constant address space: loads through it whose address is the
 // same for every lane go through the scalar cache.
 typedef const __attribute__((address_space(4))) double* ConstF64;
+typedef const __attribute__((address_space(4))) int32_t* ConstI32;
 
 // Rows r .. nr-1 of one lane's first merge, one row per template instance: term
 // (r, y) reads the slab at the lane's offsets for c(x_2 + y) and c(x_1 + r - y).
@@ -247,16 +248,42 @@ __global__ __launch_bounds__(1024) void c_merge_kernel(CDev p, int j, const void
     c_merge_rows<VT, LB, RC, 0>(slab, zoff, w, R, nr, p.top_only ? nr - 1 : 0, out, p.nblk);
 }
 
+// Orders a .. R-1 of one state's final sum (m >= 3), one order per template instance so
+// that its a + 1 table reads can all be in flight: Q(a) = -C_f [a > 0] +
+// sum_{y<=a} Bin(y; a, p_m) T(row(y) + a - y, D), then the running best, second and
+// argmax in order of a (the plain loop's order and arithmetic).
+template <typename VT, int RC, int a>
+__device__ __forceinline__ void c_final_orders(const VT* T, ConstF64 bm, ConstI32 pb,
+                                               int64_t rowbase, int64_t nblk, int64_t D,
+                                               int R, double cfixed, double& best,
+                                               double& second, int& arg) {
+    if constexpr (a < RC) {
+        if (a >= R) return;
+        const ConstF64 w = bm + a * R;
+        double acc = 0.0;
+#pragma unroll
+        for (int y = 0; y <= a; ++y)
+            acc = fma(w[y], (double)T[(rowbase + pb[y] + (a - y)) * nblk + D], acc);
+        const double q = (a > 0 ? -cfixed : 0.0) + acc;
+        if (q > best) {
+            second = best;
+            best = q;
+            arg = a;
+        } else if (q > second) {
+            second = q;
+        }
+        c_final_orders<VT, RC, a + 1>(T, bm, pb, rowbase, nblk, D, R, cfixed, best, second,
+                                      arg);
+    }
+}
+
 // Q(tau, x, a) = -C_f [a > 0] + sum_y Bin(y; a, p_m) T_{m-1}(tau, y, x; a - y), then
 // the max over a.  One lane per state.
-template <typename VT, bool EXTRACT>
+template <typename VT, bool EXTRACT, int RC>
 __global__ __launch_bounds__(256) void c_final_kernel(CDev p, const void* tin) {
     __shared__ double red[64];
-    __shared__ double bm[32 * 32];
     if (!EXTRACT && p.ctl->stop) return;
     const int R = p.R;
-    for (int i = threadIdx.x; i < R * R; i += blockDim.x) bm[i] = p.binm[i];
-    __syncthreads();
     const int tau = blockIdx.y;
     const int64_t D = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
@@ -264,28 +291,27 @@ __global__ __launch_bounds__(256) void c_final_kernel(CDev p, const void* tin) {
         const VT* T = reinterpret_cast<const VT*>(tin);
         double best = -DBL_MAX, second = -DBL_MAX;
         int arg = 0;
-        for (int a = 0; a < R; ++a) {
-            double acc = 0.0;
-            for (int y = 0; y <= a; ++y) {
-                double t;
-                if (p.m == 2) {
-                    // no middle life classes: T_1 is U with digit 1 capped
+        if (p.m == 2) {
+            // no middle life classes: T_1 is U with digit 1 capped
+            for (int a = 0; a < R; ++a) {
+                double acc = 0.0;
+                for (int y = 0; y <= a; ++y) {
                     const VT* U = T + ((int64_t)tau * R + y) * p.nblk;
-                    t = (double)U[min((int)D + (a - y), R - 1)];
-                } else {
-                    const int64_t row = (int64_t)tau * p.npair + p.pair_base[y] + (a - y);
-                    t = (double)T[row * p.nblk + D];
+                    acc = fma(p.binm[a * R + y], (double)U[min((int)D + (a - y), R - 1)], acc);
                 }
-                acc = fma(bm[a * R + y], t, acc);
+                const double q = (a > 0 ? -p.cfixed : 0.0) + acc;
+                if (q > best) {
+                    second = best;
+                    best = q;
+                    arg = a;
+                } else if (q > second) {
+                    second = q;
+                }
             }
-            const double q = (a > 0 ? -p.cfixed : 0.0) + acc;
-            if (q > best) {
-                second = best;
-                best = q;
-                arg = a;
-            } else if (q > second) {
-                second = q;
-            }
+        } else {
+            c_final_orders<VT, RC, 0>(T, (ConstF64)p.binm, (ConstI32)p.pair_base,
+                                      (int64_t)tau * p.npair, p.nblk, D, R, p.cfixed, best,
+                                      second, arg);
         }
         const int64_t s = (int64_t)tau * p.nblk + D;
         if (EXTRACT) {
@@ -359,7 +385,15 @@ static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
         }
         tin = p.tf;
     }
-    hipLaunchKernelGGL((c_final_kernel<VT, EXTRACT>), dim3(gx, p.P), dim3(256), 0, s, p, tin);
+    const dim3 fg(gx, p.P);
+    if (p.R <= 8)
+        hipLaunchKernelGGL((c_final_kernel<VT, EXTRACT, 8>), fg, dim3(256), 0, s, p, tin);
+    else if (p.R <= 16)
+        hipLaunchKernelGGL((c_final_kernel<VT, EXTRACT, 16>), fg, dim3(256), 0, s, p, tin);
+    else if (p.R <= 24)
+        hipLaunchKernelGGL((c_final_kernel<VT, EXTRACT, 24>), fg, dim3(256), 0, s, p, tin);
+    else
+        hipLaunchKernelGGL((c_final_kernel<VT, EXTRACT, 32>), fg, dim3(256), 0, s, p, tin);
     return hipGetLastError();
 }
 
