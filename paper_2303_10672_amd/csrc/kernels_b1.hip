@@ -160,8 +160,13 @@ __global__ __launch_bounds__(256) void b1_final_kernel(B1Dev p) {
         wf[i] = p.fa[i];
         wg[i] = p.ga[i];
     }
-    const int xb = blockIdx.y;
-    const int xa = blockIdx.x * blockDim.x + threadIdx.x;
+    // one-dimensional grid, remapped so each XCD takes contiguous runs of x_b: the
+    // workgroups of one x_b read the same W slice and, for equal I_b, the same Y rows,
+    // which then meet in that XCD's L2
+    const int gx = (p.NA + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int xb = lid / gx, bx = lid - xb * gx;
+    const int xa = bx * blockDim.x + threadIdx.x;
     const bool ok = xa < p.NA;
     const Digits da = digits_of(ok ? xa : 0, p.Ra, p.m);
     const Digits db = digits_of(xb, p.Rb, p.m);
@@ -234,7 +239,7 @@ __global__ __launch_bounds__(256) void b1_final_kernel(B1Dev p) {
     if (EXTRACT) return;
     block_reduce4(dmx, dmn, vmx, vmn, red);
     if (threadIdx.x == 0) {
-        double* pp = p.partials + 4 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x);
+        double* pp = p.partials + 4 * ((size_t)xb * gx + bx);
         pp[0] = dmx;
         pp[1] = dmn;
         pp[2] = vmx;
@@ -266,8 +271,9 @@ static hipError_t launch_b1_t(const B1Dev& p, hipStream_t s) {
     const unsigned gx = (unsigned)((p.NA + 255) / 256);
     hipLaunchKernelGGL((b1_stage_y_kernel<VT>), dim3(gx, nact), dim3(256), ly, s, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((b1_final_kernel<VT, EXTRACT>), dim3(gx, (unsigned)p.NB), dim3(256), lf, s,
-                       p);
+    if ((int64_t)gx * p.NB > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((b1_final_kernel<VT, EXTRACT>), dim3(gx * (unsigned)p.NB), dim3(256), lf,
+                       s, p);
     return hipGetLastError();
 }
 
