@@ -102,6 +102,9 @@ namespace pvi {
 pvi_status ensure_device(pvi_mdp* p);
 void free_device(pvi_mdp* p);
 pvi_status park_results(pvi_mdp* p);
+// vi_solve with a switch for the captured sweep graphs (off: every sweep launched
+// directly)
+pvi_status solve_impl(pvi_mdp* p, const pvi_solve_opts* opts, pvi_result* res, bool graphs);
 size_t device_bytes(const pvi_mdp* p);
 pvi::ADev make_adev(const pvi_mdp* p);
 }  // namespace pvi

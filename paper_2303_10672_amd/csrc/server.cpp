@@ -123,7 +123,9 @@ void large_worker(pvi_server* S) {
         o.v0 = r->v0.empty() ? nullptr : r->v0.data();
         pvi_result res{};
         const bool fresh = !r->mdp->dev.ready;
-        pvi_status st = vi_solve(r->mdp, &o, &res);
+        // direct launches: two workers solve at once on their own streams, and
+        // captured graphs are kept to single-caller solves
+        pvi_status st = pvi::solve_impl(r->mdp, &o, &res, false);
         // a handle this request made resident returns its HBM with the results in
         // host memory, so finished requests never block the admission of new ones
         if (fresh && (st == PVI_OK || st == PVI_E_NOT_CONVERGED)) {

@@ -134,6 +134,7 @@ struct Phase {
     int ring = 2;        // FP64 value tables cycled through (period + 1 for the periodic rule)
     int period = 0;      // > 0: run the periodic test after every sweep from this many on
     int hist0 = 0;       // earlier sweeps whose tables sit in the ring (a resumed solve)
+    bool graphs = true;  // replay captured sweep graphs where the loop allows it
     double gamma = 0.0, thr = 0.0;
     // checkpoints of FP64 sweeps: file, interval, sweeps done before the phase, rule
     const char* ckpt = nullptr;
@@ -253,7 +254,7 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
     }
     // graphs serve the plain ping-pong loop; timed runs and the periodic rule (whose
     // value tables rotate through a longer ring) launch directly
-    const bool graphs = !ph.time && ph.period == 0 && ph.ring == 2;
+    const bool graphs = ph.graphs && !ph.time && ph.period == 0 && ph.ring == 2;
     while (launched < limit) {
         int n = std::min(k, limit - launched);
         const int before = d.h_ctl->sweeps;
@@ -371,6 +372,15 @@ using namespace pvi;
 extern "C" {
 
 pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) {
+    return pvi::solve_impl(p, opts_in, res, true);
+}
+
+}  // extern "C"
+
+// The solve behind vi_solve; the request server passes graphs = false so that its
+// concurrent workers launch every sweep directly.
+pvi_status pvi::solve_impl(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res,
+                           bool graphs) {
     if (!p || !opts_in) return fail(PVI_E_INVALID, "vi_solve: NULL argument");
     // callers built against the layout that ended at `time_kernels` are accepted;
     // fields past their struct_size read as zero
@@ -455,6 +465,7 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
         // about a cycle or two of them: the FP32 phase is a short warm start
         ph.max_sweeps = periodic ? std::min(max_sweeps, 2 * period) : max_sweeps;
         ph.kmax = kmax;
+        ph.graphs = graphs;
         ph.time = o->time_kernels != 0;
         if ((st = run_phase(p, ph, s, o32)) != PVI_OK) return st;
         PVI_HIP(launch_to_f64(d.v32[o32.sweeps & 1], d.v64[0], d.ctl, p->ns, s));
@@ -466,6 +477,7 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
         ph.fixed = fp32 ? 0 : (o->fixed_sweeps > 0 ? o->fixed_sweeps - k0 : 0);
         ph.max_sweeps = max_sweeps - k0;
         ph.kmax = kmax;
+        ph.graphs = graphs;
         ph.k0 = fp32 ? 1 : 4;
         ph.time = o->time_kernels != 0;
         if (periodic) {
@@ -522,6 +534,8 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
     if (!converged) return fail(PVI_E_NOT_CONVERGED, "vi_solve: max_sweeps reached");
     return PVI_OK;
 }
+
+extern "C" {
 
 pvi_status vi_backup(pvi_mdp* p, int32_t precision, const double* v_in, double* v_out,
                      int32_t* policy, double* q_gap) {
