@@ -542,10 +542,15 @@ def main():
     traffic = (meas[0] + meas[1]) if meas else None
     traffic_detail = None
     if meas:
+        # the measured bytes over the same average launch time: the HBM rate the kernel
+        # really draws, against the same peak
+        measured_gbs = traffic / avg_kernel_s / 1e9
         traffic_detail = {"unit": "bytes per launch", "fetch": meas[0], "write": meas[1],
                           "source": os.path.relpath(TRAFFIC_PROFILE,
                                                     os.path.dirname(os.path.abspath(__file__))),
-                          "compulsory": 16.0 * m.n_states}
+                          "compulsory": 16.0 * m.n_states,
+                          "measured_gbs": measured_gbs,
+                          "measured_frac": measured_gbs / HBM_PEAK_GBS}
     out = {
         "metric": METRIC,
         "value": value,
