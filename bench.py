@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="config1", choices=["config1", "batch", "serving",
+    ap.add_argument("--workload", default="config1", choices=["config1", "batch", "serving", "oracle",
                                                                "config2", "config3",
                                                                "paper-a", "paper-b", "paper-c", "rollouts"],
                     help="config1 (default, the headline), batch (many small solves: "
@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving arrival rate per second (0: 0.7 x closed-loop rate)")
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--oracle-threads", type=int, default=0,
+                    help="workload oracle: OpenMP threads of the oracle (0 = all)")
     ap.add_argument("--paper-checkpoints", action="store_true",
                     help="paper workloads: also time an FP64 solve that writes a checkpoint "
                          "file as often as the paper did (A every 100 sweeps, B and C "
@@ -123,6 +125,44 @@ def cpu_baseline(sc, target_s):
             "kind": "oracle",
             "sample": f"one FP64 backup (all 21 actions x 61 demand outcomes) of {len(idx)} "
                       f"of the {o.n_states} states, {dt:.1f} s"}
+
+
+def bench_oracle(args):
+    """The FP64 CPU oracle alone (no GPU): full solves of config 0 (p50/p99 over 20)
+    and the config-1 backup sample of cpu_baseline, at --oracle-threads OpenMP threads,
+    with the host's processor."""
+    import numpy as np
+    if args.oracle_threads > 0:
+        os.environ["OMP_NUM_THREADS"] = str(args.oracle_threads)  # before the oracle loads
+    from oracle.oracle import Oracle
+    import workloads as W
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    o = Oracle(W.config0())
+    lat = []
+    for _ in range(20):
+        t0 = time.perf_counter()
+        r = o.solve()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    base = cpu_baseline(W.config1(), args.cpu_seconds)
+    line = {"metric": "oracle FP64 backups/s (config 1 sample) and config-0 solve latency",
+            "value": base["value"], "unit": "backups/s", "n_gpus": 0,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "CPU oracle: config 0 full solves, config 1 backup sample"},
+            "host": {"cpu": cpu, "nproc": os.cpu_count(),
+                     "affinity": len(os.sched_getaffinity(0)),
+                     "omp_threads": os.environ.get("OMP_NUM_THREADS")},
+            "config0_solve_ms": {"p50": float(np.percentile(lat, 50)),
+                                 "p99": float(np.percentile(lat, 99)),
+                                 "sweeps": r["sweeps"]},
+            "config1_sample": base}
+    print(json.dumps(line), flush=True)
 
 
 def bench_batch(args, pvi, W):
@@ -485,6 +525,8 @@ def main():
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "oracle":
+        return bench_oracle(args)
     import torch
     from paper_2303_10672_amd import pvi
     import workloads as W
