@@ -3,7 +3,7 @@
 Tolerances (normwise, relative to max |V| of the oracle):
   FP64 backup       1e-12  (same arithmetic up to summation order)
   FP32 storage      1e-6   per sweep (FP32 rounding of V plus FP32 weights)
-  converged V       1e-5   (the benchmark spec's bound), reported per config
+  converged V       1e-5   (max-abs relative error of the FP32 schedule), per config
 Policies must match wherever the oracle's best-minus-second Q gap exceeds 1e-6
 (1e-9 for single FP64 backups, where both sides see the same V).
 """
