@@ -211,8 +211,11 @@ typedef struct pvi_server pvi_server;
 
 /* Validate a descriptor and build its tables on the host (demand PMFs, expected
  * one-day rewards, arrival and substitution probabilities).  No device memory is
- * taken until the first solve.  Errors: PVI_E_INVALID (bad descriptor: sizes,
- * probabilities, gamma, unsupported family/size combination), PVI_E_NOMEM. */
+ * taken until the first solve.  At most 2^31 states, except scenario C (at most
+ * 2^40): beyond 2^31 its handle serves heuristic policy_rollouts and
+ * heuristic_search only, and solves, single backups, table policies and server
+ * requests on it return PVI_E_INVALID.  Errors: PVI_E_INVALID (bad descriptor:
+ * sizes, probabilities, gamma, unsupported family/size combination), PVI_E_NOMEM. */
 pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out);
 
 /* Free host and device memory of a handle.  NULL is accepted. */

@@ -186,6 +186,8 @@ std::string family_support_msg(const pvi_mdp* p) {
         return "ok";
     }
     if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
+        if (p->ns > (int64_t(1) << 31))
+            return "more than 2^31 states: this scenario-C handle serves heuristic rollouts only";
         if (p->m > 9) return "scenario C needs m <= 9 on the GPU";
         const size_t lds = sizeof(double) * ((size_t)p->c_lpmax + 3 * (size_t)p->c_tab);
         if (lds > 65536) return "scenario C demand table exceeds LDS";

@@ -562,12 +562,18 @@ pvi_status mdp_create(const pvi_mdp_desc* desc, pvi_mdp** out) {
         p->radix[0] = P;
         for (int i = 1; i < d.m; ++i) p->radix[i] = p->rad[0];
     }
+    // scenario C builds no host table that grows with the states, so it accepts up
+    // to 2^40 of them; beyond 2^31 its handle serves heuristic rollouts only
+    const int64_t cap = d.family == PVI_FAMILY_RUL_WEEKDAY ? (int64_t(1) << 40)
+                                                           : (int64_t(1) << 31);
     p->ns = 1;
     for (int i = 0; i < p->ndig; ++i) {
         p->ns *= p->radix[i];
-        if (p->ns > (int64_t(1) << 31)) {
+        if (p->ns > cap) {
             delete p;
-            return fail(PVI_E_INVALID, "mdp_create: more than 2^31 states");
+            return fail(PVI_E_INVALID, d.family == PVI_FAMILY_RUL_WEEKDAY
+                                           ? "mdp_create: more than 2^40 states"
+                                           : "mdp_create: more than 2^31 states");
         }
     }
     p->na = nprod == 2 ? p->rad[0] * p->rad[1] : p->rad[0];

@@ -84,6 +84,8 @@ pvi_status run_rollouts(pvi_mdp* p, const pvi_rollout_opts* o, double* stats, do
         return fail(PVI_E_INVALID, w + ": start_state out of range");
     if (o->kind != PVI_POLICY_TABLE && !o->params)
         return fail(PVI_E_INVALID, w + ": a heuristic policy needs params");
+    if (o->kind == PVI_POLICY_TABLE && p->ns > (int64_t(1) << 31))
+        return fail(PVI_E_INVALID, w + ": a table policy needs at most 2^31 states");
     if (p->m > PVI_MAX_LIFE || (p->family == PVI_FAMILY_LEADTIME && p->L - 1 > 11))
         return fail(PVI_E_INVALID, w + ": state too long for the simulator");
     // Heuristic orders are not capped (scenario C's are), so a parameter bounds the

@@ -276,3 +276,27 @@ def test_checkpoint_options_are_checked_before_the_device(tmp_path):
         pvi.checkpoint_read(m, missing)
     with pytest.raises(pvi.PviError):
         pvi.checkpoint_read(m, str(other))
+
+
+def test_scenario_c_beyond_2_31_states_serves_heuristic_rollouts_only():
+    """Scenario C at m = 8 (12,607,619,787 states) is created for rollouts of
+    heuristics; a solve, a single backup or a table policy on it is refused before the
+    device, a heuristic rollout reaches the device (absent here).  Other families stay
+    limited to 2^31 states."""
+    m = pvi.mdp_create(W.scenario_c_paper(8, 1))
+    assert m.n_states == 7 * 21 ** 7
+    o = pvi.make_opts("fp64", 1e-4, 1000, 0, None, None, 0, False, m.sc, "periodic")
+    assert pvi._lib.vi_solve(m.handle, ctypes.byref(o), None) == pvi.PVI_E_INVALID
+    assert "heuristic rollouts only" in pvi._lib.pvi_last_error().decode()
+    st = np.zeros(8)
+    null = ctypes.POINTER(ctypes.c_double)()
+    prm = [[8, 19, 8, 15, 8, 18, 7, 18, 8, 14, 3, 13, 4, 16]]
+    ro, keep = pvi._rollout_opts(m, "s_S", None, prm, 10, 5, 20, 0, 0, None)
+    assert pvi._lib.policy_rollouts(m.handle, ctypes.byref(ro), pvi._dptr(st), null, null) == \
+        pvi.PVI_E_DEVICE
+    ro, keep = pvi._rollout_opts(m, "table", None, None, 10, 5, 20, 0, 0, None)
+    assert pvi._lib.policy_rollouts(m.handle, ctypes.byref(ro), pvi._dptr(st), null, null) == \
+        pvi.PVI_E_INVALID
+    assert "2^31" in pvi._lib.pvi_last_error().decode()
+    with pytest.raises(pvi.PviError, match="2\\^31"):
+        pvi.mdp_create(W.scenario_a(m=5, L=4, a_max=20, d_max=30))   # 21^8 states

@@ -13,6 +13,7 @@ from .scenarios import (  # noqa: F401
     PAPER_A_EXPERIMENTS,
     scenario_c_paper,
     PAPER_C_EXPERIMENTS,
+    PAPER_C_RUL_LARGE,
     scenario_b1,
     scenario_b_paper,
     PAPER_B_EXPERIMENTS,

@@ -31,7 +31,8 @@ import numpy as np
 
 __all__ = [
     "scenario_a", "scenario_b", "scenario_c", "scenario_a_paper", "PAPER_A_EXPERIMENTS",
-    "scenario_c_paper", "PAPER_C_EXPERIMENTS", "scenario_b1", "scenario_b_paper",
+    "scenario_c_paper", "PAPER_C_EXPERIMENTS", "PAPER_C_RUL_LARGE", "scenario_b1",
+    "scenario_b_paper",
     "PAPER_B_EXPERIMENTS",
     "config0", "config1", "config2",
     "config3", "config_by_index", "serving_mix", "random_values", "sample_indices",
@@ -166,6 +167,12 @@ PAPER_C_RUL = {
     (5, 2): ([1.9, 3.1, 3.1, 2.5], [-0.03, -0.06, -0.03, -0.09]),
 }
 PAPER_C_EXPERIMENTS = sorted(PAPER_C_RUL)
+# m = 8 (12,607,619,787 states): the paper fits the (s, S) heuristic only
+PAPER_C_RUL_LARGE = {
+    (8, 1): ([0.8, 1.4, 1.9, 2.3, 1.7, 1.2, 0.8], [0.0] * 7),
+    (8, 2): ([0.8, 1.4, 1.9, 2.3, 1.7, 1.2, 0.8],
+             [-0.03, -0.04, -0.05, -0.06, -0.07, -0.08, -0.09]),
+}
 # weekday negative-binomial demand, Monday (tau = 0) to Sunday: successes n, mean delta
 PAPER_C_DEMAND_N = [3.5, 11.0, 7.2, 11.1, 5.9, 5.5, 2.2]
 PAPER_C_DEMAND_MEAN = [5.7, 6.9, 6.5, 6.2, 5.8, 3.3, 3.4]
@@ -175,8 +182,9 @@ def scenario_c_paper(m, exp):
     """Scenario C with the settings the paper fixes for all its experiments (Appendix C
     common-settings, weekday-demand and useful-life tables): demand truncated at 20,
     orders and stock of each remaining life up to 20, C_f 10, C_h 1, C_s 20, C_w 5,
-    gamma 0.95, eps 1e-4.  The paper stops these solves with its periodic test."""
-    c0, c1 = PAPER_C_RUL[(m, exp)]
+    gamma 0.95, eps 1e-4.  The paper stops these solves with its periodic test; at
+    m = 8 (PAPER_C_RUL_LARGE) it only fits and evaluates the (s, S) heuristic."""
+    c0, c1 = PAPER_C_RUL[(m, exp)] if (m, exp) in PAPER_C_RUL else PAPER_C_RUL_LARGE[(m, exp)]
     return scenario_c(m=m, a_max=20, d_max=20, n=PAPER_C_DEMAND_N,
                       means=PAPER_C_DEMAND_MEAN, c0=[0.0] + list(c0), c1=[0.0] + list(c1),
                       costs=_costs(fixed=10.0, hold=1.0, short=20.0, waste=5.0),
