@@ -465,12 +465,19 @@ def bench_rollouts(args, pvi, W):
          [[lo, hi] * 7 for lo in range(0, 21, 2) for hi in range(lo + 1, 21, 2)]),
         ("B two products (config 2 shape, 50,625 states)", W.config2(), "span",
          "mod_base_stock", [[a, b] for a in range(0, 29) for b in range(0, 29)]),
+        # m = 8: 12,607,619,787 states, no value iteration; the paper's (s, S) fit first
+        ("C m=8 exp 1 (12,607,619,787 states, heuristics only)", W.scenario_c_paper(8, 1),
+         None, "s_S", [[8, 19, 8, 15, 8, 18, 7, 18, 8, 14, 3, 13, 4, 16]] +
+         [[lo, hi] * 7 for lo in range(0, 21, 2) for hi in range(lo + 1, 21, 2)]),
     ]
     for label, sc, rule, kind, grid in cases:
         m = pvi.mdp_create(sc)
-        pvi.vi_solve(m, precision="fp64", eps=sc["eps"], stop_rule=rule)
+        if rule is not None:
+            pvi.vi_solve(m, precision="fp64", eps=sc["eps"], stop_rule=rule)
         row = {"workload": label}
-        for what, kw in (("vi_policy", {}), (kind + "_grid", {"policy": kind, "params": grid})):
+        todo = ([("vi_policy", {})] if rule is not None else []) + \
+            [(kind + "_grid", {"policy": kind, "params": grid})]
+        for what, kw in todo:
             pvi.policy_rollouts(m, n_rollouts=1000, per_rollout=False, **kw)  # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
