@@ -113,7 +113,11 @@ __device__ __forceinline__ void wave_sync() {
 
 // Value staged for the padding actions R <= a < RMAX: so negative that their Q
 // never wins the max, small enough that weighted sums of it (total weight <= 1)
-// stay finite.  With it the action loops need no bound check.
+// stay finite.  With it the action loops need no bound check.  Variants compiled
+// for one exact action count (RC = R) compute no padded action at all: they stage
+// the same RMAX-wide rows but keep running sums only for the R real actions, which
+// frees registers and skips the padded multiply-adds; the maxima are over the same
+// actions, so their results are identical.
 template <typename VT>
 __device__ constexpr VT kPadValue = VT(-1e30);
 template <>
@@ -140,7 +144,7 @@ __device__ constexpr double kPadValue<double> = -1e300;
 // registers while the current one is used.  The single-point state (N = 0, b = 0)
 // takes S[0] for every demand.  All actions of a state live in one lane, so the max
 // needs no exchange.  Weights are staged premultiplied by gamma.
-template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
+template <typename VT, bool KAHAN, int RMAX, bool EXTRACT, int RC>
 __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
     Ctl* ctl = p.ctl;
     if (!EXTRACT && ctl->stop) return;
@@ -290,11 +294,12 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
         double best = -DBL_MAX, second = -DBL_MAX;
         int arg = 0;
 #pragma unroll
-        for (int q = 0; q < RMAX / W; ++q) {
+        for (int q = 0; q < (RC + W - 1) / W; ++q) {
             const VV s0 = row0[q];
 #pragma unroll
             for (int e = 0; e < W; ++e) {
                 const int a = q * W + e;
+                if (a >= RC) break;
                 const double qv = fma(gm, (double)lane_of<VT, W>(s0, e), -cv * a);
                 if (EXTRACT)
                     take(qv, a, best, second, arg);
@@ -309,16 +314,17 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
     const int u1 = n0 + l, u2 = u1 + R;
     // start from the j = 0 term G(u) S[0] (and, with FP64 accumulation, the order
     // cost, which the difference D does not carry)
-    Acc<VT, KAHAN> A1[RMAX], D[RMAX];
+    Acc<VT, KAHAN> A1[RC], D[RC];
     {
         const double g1 = sG[u1], g2 = sG[u2];
         const AW gd = (AW)(g2 - g1);
 #pragma unroll
-        for (int q = 0; q < RMAX / W; ++q) {
+        for (int q = 0; q < (RC + W - 1) / W; ++q) {
             const VV s0 = row0[q];
 #pragma unroll
             for (int e = 0; e < W; ++e) {
                 const int a = q * W + e;
+                if (a >= RC) break;
                 const VT sv = lane_of<VT, W>(s0, e);
                 if constexpr (KAHAN)
                     A1[a].add((AW)g1, sv);
@@ -379,10 +385,11 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
         AW w1, wd;
         weights(N, w1, wd);
 #pragma unroll
-        for (int q = 0; q < RMAX / W; ++q) {
+        for (int q = 0; q < (RC + W - 1) / W; ++q) {
             const VV sq = rN[q];
 #pragma unroll
             for (int e = 0; e < W; ++e) {
+                if (q * W + e >= RC) break;
                 const VT svt = lane_of<VT, W>(sq, e);
                 A1[q * W + e].add(w1, svt);
                 D[q * W + e].add(wd, svt);
@@ -408,11 +415,12 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
         int arg = 0;
         double bq[4] = {-DBL_MAX, -DBL_MAX, -DBL_MAX, -DBL_MAX};
 #pragma unroll
-        for (int q = 0; q < RMAX / W; ++q) {
+        for (int q = 0; q < (RC + W - 1) / W; ++q) {
             const VV sq = rN[q];
 #pragma unroll
             for (int e = 0; e < W; ++e) {
                 const int a = q * W + e;
+                if (a >= RC) break;
                 const VT svt = lane_of<VT, W>(sq, e);
                 const double sv = (double)svt;
                 const double run = fma(msel, D[a].value(), A1[a].value());
@@ -458,17 +466,17 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
 // Two entry points of one body: the first asks for two wavefronts per SIMD (its
 // registers fit in 256), the second has the whole register file for the variants
 // that would spill at that budget (RMAX = 32, FP32 compensated sums at RMAX >= 16).
-template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
+template <typename VT, bool KAHAN, int RMAX, bool EXTRACT, int RC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void
 backup_a_kernel(ADev p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    backup_a_body<VT, KAHAN, RMAX, EXTRACT>(p, smem);
+    backup_a_body<VT, KAHAN, RMAX, EXTRACT, RC>(p, smem);
 }
 
-template <typename VT, bool KAHAN, int RMAX, bool EXTRACT>
+template <typename VT, bool KAHAN, int RMAX, bool EXTRACT, int RC>
 __global__ __launch_bounds__(64) void backup_a_wide_kernel(ADev p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    backup_a_body<VT, KAHAN, RMAX, EXTRACT>(p, smem);
+    backup_a_body<VT, KAHAN, RMAX, EXTRACT, RC>(p, smem);
 }
 
 // Single-workgroup reduction of the per-tile partials and the stopping rule.
@@ -510,7 +518,7 @@ __global__ void to_f32_kernel(const double* v64, float* v32, double c, int64_t n
 
 // ------------------------------------------------------------------ launchers
 
-template <typename VT, bool KAHAN, bool EXTRACT, int RMAX>
+template <typename VT, bool KAHAN, bool EXTRACT, int RMAX, int RC = RMAX>
 static hipError_t launch_a_r(const ADev& p, hipStream_t s) {
     const int lp_max = (p.m >= 2 ? (p.m - 2) * (p.R - 1) : 0) + p.r2;
     // lanes: G tiles of R lanes; staging: RMAX / 8 action slices of G x CH points
@@ -524,16 +532,20 @@ static hipError_t launch_a_r(const ADev& p, hipStream_t s) {
     if (p.tab < 2 * p.R + lp_max + 1 || p.tab < p.dmax + 2) return hipErrorInvalidValue;
     constexpr bool wide = RMAX == 32 || (KAHAN && RMAX >= 16);
     if constexpr (wide)
-        hipLaunchKernelGGL((backup_a_wide_kernel<VT, KAHAN, RMAX, EXTRACT>), dim3(p.ngroups),
+        hipLaunchKernelGGL((backup_a_wide_kernel<VT, KAHAN, RMAX, EXTRACT, RC>), dim3(p.ngroups),
                            dim3(64), bytes, s, p);
     else
-        hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT>), dim3(p.ngroups),
+        hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT, RC>), dim3(p.ngroups),
                            dim3(64), bytes, s, p);
     return hipGetLastError();
 }
 
 template <typename VT, bool KAHAN, bool EXTRACT>
 static hipError_t launch_a_t(const ADev& p, hipStream_t s) {
+    // exact action counts of the paper's scenario A (order cap 10) and of the
+    // order cap 20 instances; at R = 11 the FP64 variant fits three wavefronts per SIMD
+    if (p.R == 11) return launch_a_r<VT, KAHAN, EXTRACT, 16, 11>(p, s);
+    if (p.R == 21) return launch_a_r<VT, KAHAN, EXTRACT, 24, 21>(p, s);
     if (p.R <= 8) return launch_a_r<VT, KAHAN, EXTRACT, 8>(p, s);
     if (p.R <= 16) return launch_a_r<VT, KAHAN, EXTRACT, 16>(p, s);
     if (p.R <= 24) return launch_a_r<VT, KAHAN, EXTRACT, 24>(p, s);

@@ -29,6 +29,10 @@ SMALL = [
     W.scenario_a(m=2, L=1, a_max=31, d_max=40),   # 32 actions: the widest kernel
     W.scenario_a(m=3, L=1, a_max=25, d_max=33,
                  demand={"kind": "negbin", "mean": [6.0], "n": [3.0]}),
+    # the two action counts with exact-count kernels (no padded actions computed)
+    W.scenario_a(m=3, L=1, a_max=20, d_max=30,
+                 demand={"kind": "gamma", "mean": [4.0], "cv": [1.5]}),
+    W.scenario_a(m=3, L=2, a_max=10, d_max=20),
 ]
 IDS = [f"m{s['m']}L{s['L']}R{s['a_max'][0] + 1}D{s['d_max'][0]}" for s in SMALL]
 
