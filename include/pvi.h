@@ -58,6 +58,10 @@
  *    not depend on the choice.  PVI_TUNE=0 in the environment skips the timing (the
  *    LDS rule then chooses); PVI_TUNE_VERBOSE=1 prints the choices to stderr;
  *    PVI_C_BLOCK=4|8|12|16|32 fixes the width wherever it fits (for tests).
+ *  - Scenario A (FIFO) packs floor(64 / R) tiles into a wavefront, or 2 when that
+ *    would leave fewer wavefronts than the device has SIMDs; results do not depend
+ *    on the choice.  PVI_A_GROUP=<G>, 1 <= G <= floor(64 / R), read by mdp_create,
+ *    fixes it (for tests).
  */
 #ifndef PVI_H
 #define PVI_H

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -110,13 +111,22 @@ static void build_a_tables(pvi_mdp* p) {
     // grouped per block of G in-transit vectors and, inside one digit sum, by
     // (X_m..X_3) then in-transit vector, so a full group is one (X_m..X_3) over G
     // in-transit vectors.
-    p->a_G = std::min(16, std::max(1, 64 / R));
+    // When full groups would give fewer wavefronts than the chip has SIMDs (1,024),
+    // two tiles per wavefront are faster: more wavefronts, and each stages longer
+    // chunks of its path.  Results do not depend on G (each lane's arithmetic is its
+    // own tile's).  PVI_A_GROUP=<G> (1 .. floor(64 / R)) fixes G, for tests.
+    const int64_t nzt = p->m >= 2 ? (int64_t)ipow_i(R, p->m - 2) : 1;
+    const int gmax = std::min(16, std::max(1, 64 / R));
+    p->a_G = nh * nzt / gmax < 1024 ? std::min(gmax, 2) : gmax;
+    if (const char* force = std::getenv("PVI_A_GROUP")) {
+        const int g = std::atoi(force);
+        if (g >= 1 && g <= gmax) p->a_G = g;
+    }
     // the kernel pads the actions to RMAX = 8, 16, 24 or 32 and stages each path
     // point with RMAX / 8 lanes of 8 actions: CH points per chunk fill <= 64 lanes
     const int rmax = R <= 8 ? 8 : R <= 16 ? 16 : R <= 24 ? 24 : 32;
     p->a_CH = std::max(1, 64 / ((rmax / 8) * p->a_G));
     const int G = p->a_G;
-    const int64_t nzt = p->m >= 2 ? (int64_t)ipow_i(R, p->m - 2) : 1;
     std::vector<int> zsum(nzt, 0);
     for (int64_t z = 0; z < nzt; ++z) {
         int64_t t = z;

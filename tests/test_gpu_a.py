@@ -55,6 +55,33 @@ def test_one_backup_fp64(sc):
         assert np.allclose(gapg[clear], gapo[clear], rtol=1e-8, atol=1e-8)
 
 
+@pytest.mark.parametrize("sc", SMALL, ids=IDS)
+def test_tiles_per_wavefront_do_not_change_results(sc, monkeypatch):
+    """Small instances run with two tiles per wavefront; the full floor(64 / R) tiles
+    (the grouping of large instances, with short groups padded) must give the same
+    bits: one FP64 and one FP32 backup, and a converged solve with its policy."""
+    o = Oracle(sc)
+    V = W.random_values(o.n_states, seed=4)
+    runs = []
+    for force in (None, str(max(1, min(16, 64 // (sc["a_max"][0] + 1))))):
+        if force is None:
+            monkeypatch.delenv("PVI_A_GROUP", raising=False)
+        else:
+            monkeypatch.setenv("PVI_A_GROUP", force)
+        m = pvi.mdp_create(sc)
+        monkeypatch.delenv("PVI_A_GROUP", raising=False)
+        b64 = pvi.vi_backup(m, V, "fp64")
+        b32 = pvi.vi_backup(m, V, "fp32")
+        res = pvi.vi_solve(m, precision="fp64")
+        runs.append((b64, b32, res["sweeps_fp64"], pvi.value_get(m), pvi.policy_get(m)))
+    (a64, a32, asw, aV, ap), (g64, g32, gsw, gV, gp) = runs
+    for x, y in zip(a64 + a32, g64 + g32):
+        assert np.array_equal(x, y)
+    assert asw == gsw and np.array_equal(aV, gV)
+    assert np.array_equal(ap[0], gp[0]) and np.array_equal(ap[1], gp[1])
+    assert relerr(a64[0], o.sweep(V)[0]) < 1e-12
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp32_wide"])
 @pytest.mark.parametrize("sc", SMALL, ids=IDS)
 def test_one_backup_fp32(sc, prec):
