@@ -565,7 +565,11 @@ hipError_t launch_backup_a(const ADev& p, int storage_fp32, int acc_kahan, int e
 
 hipError_t launch_span(Ctl* ctl, const double* partials, int tiles, int storage_fp32,
                        int fixed, double gamma, hipStream_t s) {
-    hipLaunchKernelGGL(span_kernel, dim3(1), dim3(1024), 0, s, ctl, partials, tiles,
+    // a block no wider than the partials need (whole wavefronts, at most 1024): small
+    // instances then pay for one wavefront, not sixteen; max and min are exact, so
+    // the block width does not change the result
+    const int threads = tiles >= 1024 ? 1024 : tiles <= 64 ? 64 : (tiles + 63) / 64 * 64;
+    hipLaunchKernelGGL(span_kernel, dim3(1), dim3(threads), 0, s, ctl, partials, tiles,
                        storage_fp32, fixed, gamma);
     return hipGetLastError();
 }
