@@ -64,8 +64,10 @@ hipError_t launch_periodic_check(Ctl* ctl, const PeriodicArgs& a, double* partia
     hipLaunchKernelGGL(periodic_partial_kernel, dim3(blocks), dim3(256), 0, s, ctl, a, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(periodic_reduce_kernel, dim3(1), dim3(1024), 0, s, ctl, partials, blocks,
-                       a.thr);
+    // one wavefront per 64 partials, at most 1024 threads (max and min are exact)
+    const int threads = blocks >= 1024 ? 1024 : blocks <= 64 ? 64 : (blocks + 63) / 64 * 64;
+    hipLaunchKernelGGL(periodic_reduce_kernel, dim3(1), dim3(threads), 0, s, ctl, partials,
+                       blocks, a.thr);
     return hipGetLastError();
 }
 
