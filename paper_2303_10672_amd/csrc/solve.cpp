@@ -242,7 +242,7 @@ pvi_status sweep_graph(pvi_mdp* p, const Phase& ph, hipStream_t s, hipGraphExec_
 pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) {
     auto& d = p->dev;
     int launched = 0, k = ph.k0;
-    double prev_span = -1.0;
+    double prev_span = -1.0, prev_crit = -1.0;
     int prev_sweeps = 0, last_ckpt = 0;
     const int limit = ph.fixed > 0 ? ph.fixed : ph.max_sweeps;
     if (ph.time && (int)d.ev.size() < 2 * ph.kmax) {
@@ -313,20 +313,30 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
             if (st != PVI_OK) return st;
             last_ckpt = h.sweeps;
         }
-        // size the next batch from the observed contraction of the span
+        // size the next batch from the observed contraction of what the stopping rule
+        // tests: max |V' - V| for the sup-norm rule, else the span (which, under
+        // discounting, falls below the threshold long before the sup-norm does); the
+        // FP32 phase also ends at the span floor
+        const double crit = h.rule == 1 ? std::max(std::fabs(h.dmax), std::fabs(h.dmin)) : h.span;
+        const int gap = h.sweeps - prev_sweeps;
         if (ph.fixed > 0) {
             k = std::min(ph.kmax, 2 * k);
-        } else if (prev_span > 0.0 && h.span > 0.0 && h.span < prev_span &&
-                   h.sweeps > prev_sweeps) {
-            const double rate = std::pow(h.span / prev_span, 1.0 / (h.sweeps - prev_sweeps));
-            double target = h.thr;
-            if (ph.fp32) target = std::max(target, h.floor32 * h.vabs);
-            const double need = rate < 1.0 ? std::log(target / h.span) / std::log(rate) : ph.kmax;
+        } else if (prev_crit > 0.0 && crit > 0.0 && crit < prev_crit && gap > 0) {
+            const double rate = std::pow(crit / prev_crit, 1.0 / gap);
+            // a threshold <= 0 never stops the solve: full batches
+            double need =
+                rate < 1.0 && h.thr > 0.0 ? std::log(h.thr / crit) / std::log(rate) : ph.kmax;
+            if (ph.fp32 && prev_span > 0.0 && h.span > 0.0 && h.span < prev_span) {
+                const double rs = std::pow(h.span / prev_span, 1.0 / gap);
+                if (rs < 1.0)
+                    need = std::min(need, std::log(h.floor32 * h.vabs / h.span) / std::log(rs));
+            }
             k = (int)std::min<double>(ph.kmax, std::max(1.0, std::ceil(need)));
         } else {
             k = std::min(ph.kmax, 2 * k);
         }
         prev_span = h.span;
+        prev_crit = crit;
         prev_sweeps = h.sweeps;
     }
     out.sweeps = d.h_ctl->sweeps;
