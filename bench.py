@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving arrival rate per second (0: 0.7 x closed-loop rate)")
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--late-s", type=int, default=120,
+                    help="serving: end the run, naming the request, when one ticket is "
+                         "not done after this many seconds")
     ap.add_argument("--oracle-threads", type=int, default=0,
                     help="workload oracle: OpenMP threads of the oracle (0 = all)")
     ap.add_argument("--paper-checkpoints", action="store_true",
@@ -209,6 +212,39 @@ def bench_batch(args, pvi, W):
     print(json.dumps(line), flush=True)
 
 
+def describe(sc):
+    """Request class of a serving-mix scenario, for progress and late-ticket lines."""
+    if sc["family"] == "C":
+        return f"C m={sc['m']} order cap {sc['a_max'][0]}"
+    return f"A m={sc['m']} L={sc['L']} order cap {sc['a_max'][0]}"
+
+
+def wait_tickets(pvi, srv, tickets, scs, label, late_s):
+    """Wait for tickets in submission order, printing progress every 10.  A ticket
+    not done after each 10 s is named with its server state (queued or running, the
+    worker, sweeps so far); after late_s seconds the run is ended with that report
+    (os._exit: a stuck solve would otherwise block the server's shutdown)."""
+    status = []
+    for i, t in enumerate(tickets):
+        waited = 0
+        while True:
+            st, r = srv.wait(t, timeout_us=10_000_000)
+            if st != pvi.PVI_E_NOT_READY:
+                break
+            waited += 10
+            info = srv.ticket_info(t)
+            msg = (f"late: request {i + 1} (ticket {t}, {describe(scs[i])}) not done after "
+                   f"{waited} s: {info}")
+            print(msg, file=sys.stderr, flush=True)
+            if waited >= late_s:
+                print(json.dumps({"error": msg}), flush=True)
+                os._exit(3)
+        status.append((st, r))
+        if (i + 1) % 10 == 0 or i + 1 == len(tickets):
+            print(f"{label}: {i + 1}/{len(tickets)} requests done", file=sys.stderr, flush=True)
+    return status
+
+
 def bench_serving(args, pvi, W):
     """The request mix through the server: arrivals on a clock, p50/p99 latency."""
     import threading
@@ -227,11 +263,7 @@ def bench_serving(args, pvi, W):
     t0 = time.perf_counter()
     ts = [srv.submit([pvi.mdp_create(sc)], precision="fp32", stop_rule=rule(sc))[0]
           for sc in pre]
-    for i, t in enumerate(ts):
-        srv.wait(t)
-        if (i + 1) % 10 == 0 or i + 1 == len(ts):
-            print(f"closed-loop pre-run: {i + 1}/{len(ts)} requests done", file=sys.stderr,
-                  flush=True)
+    wait_tickets(pvi, srv, ts, pre, "closed-loop pre-run", args.late_s)
     sat = len(pre) / (time.perf_counter() - t0)
     srv.close()
     rate = args.rate if args.rate > 0 else 0.7 * sat
@@ -254,11 +286,7 @@ def bench_serving(args, pvi, W):
     th = threading.Thread(target=submitter)
     th.start()
     th.join()
-    status = []
-    for i, t in enumerate(tickets):
-        status.append(srv.wait(t))
-        if (i + 1) % 10 == 0 or i + 1 == len(tickets):
-            print(f"served: {i + 1}/{len(tickets)} requests done", file=sys.stderr, flush=True)
+    status = wait_tickets(pvi, srv, tickets, scs, "served", args.late_s)
     wall = time.perf_counter() - start
     st = srv.stats()
     srv.close()

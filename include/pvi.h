@@ -284,7 +284,12 @@ pvi_status policy_get_device(const pvi_mdp* mdp, int32_t* d_policy, void* stream
  * results stay in its pvi_mdp handle, which the caller keeps alive until the
  * ticket completes.  A handle that had no device state when its request started
  * gets its results in host memory and its device buffers freed once the solve
- * ends (policy_get, value_get and policy_get_device read them from there). */
+ * ends (policy_get, value_get and policy_get_device read them from there).
+ * A request waiting for device memory re-reads the free memory at least every
+ * 2 ms, so memory freed outside the server (a client's mdp_destroy) admits it
+ * without any server call.  With PVI_SERVER_LOG=<path> in the environment at
+ * pvi_server_create, the server appends one line per request event (submit,
+ * start, done, busy, cancel: time in ms, ticket, class, worker, bytes, status). */
 pvi_status pvi_server_create(int64_t hbm_budget_bytes, int32_t small_batch,
                              pvi_server** out);
 pvi_status pvi_server_destroy(pvi_server* server);
@@ -293,6 +298,19 @@ pvi_status vi_batch_submit(pvi_server* server, pvi_mdp* const* mdps,
 pvi_status vi_poll(pvi_server* server, uint64_t ticket, pvi_result* res);
 pvi_status vi_wait(pvi_server* server, uint64_t ticket, int64_t timeout_us,
                    pvi_result* res);
+/* State of a ticket, for progress reports and diagnosis of slow requests.
+ * Times are milliseconds since pvi_server_create (-1 before the event). */
+typedef struct pvi_ticket_info {
+    int32_t state;        /* 0 queued, 1 running, 2 done */
+    int32_t small;        /* 1: batched small-instance path, 0: sweep loop */
+    int32_t worker;       /* server worker that took it; -1 while queued */
+    int32_t sweeps;       /* sweep-loop requests: sweeps completed at the last host check */
+    int32_t status;       /* pvi_status once done, else PVI_E_NOT_READY */
+    int32_t reserved;
+    int64_t bytes;        /* device bytes a sweep-loop request holds while it runs */
+    double t_submit_ms, t_start_ms, t_done_ms;
+} pvi_ticket_info;
+pvi_status vi_ticket_info(pvi_server* server, uint64_t ticket, pvi_ticket_info* out);
 /* Latency statistics over completed tickets (milliseconds, submit to done). */
 pvi_status pvi_server_stats(pvi_server* server, double* p50_ms, double* p99_ms,
                             int64_t* completed);

@@ -103,8 +103,10 @@ pvi_status ensure_device(pvi_mdp* p);
 void free_device(pvi_mdp* p);
 pvi_status park_results(pvi_mdp* p);
 // vi_solve with a switch for the captured sweep graphs (off: every sweep launched
-// directly)
-pvi_status solve_impl(pvi_mdp* p, const pvi_solve_opts* opts, pvi_result* res, bool graphs);
+// directly) and an optional progress counter (sweeps completed, stored at every
+// host check)
+pvi_status solve_impl(pvi_mdp* p, const pvi_solve_opts* opts, pvi_result* res, bool graphs,
+                      std::atomic<int>* progress);
 size_t device_bytes(const pvi_mdp* p);
 pvi::ADev make_adev(const pvi_mdp* p);
 }  // namespace pvi

@@ -17,34 +17,30 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
-#include <condition_variable>
 #include <cstddef>
+#include <cstdlib>
 #include <cstring>
-#include <deque>
 #include <memory>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "families.h"
 #include "mdp.h"
+#include "server_core.h"
 
 namespace {
 
 using clk = std::chrono::steady_clock;
+using pvi::srv::Job;
 
-struct Request {
-    uint64_t ticket = 0;
+struct Request : Job {
     pvi_mdp* mdp = nullptr;
     pvi_solve_opts opts{};
     std::vector<double> v0;
-    clk::time_point t_submit;
-    bool small = false;
-    int64_t bytes = 0;
-    int done = 0;
-    pvi_status status = PVI_OK;
     pvi_result res{};
+    std::atomic<int> sweeps{0};  // large requests: sweeps completed so far
 };
 
 constexpr int kSmallMaxLds = 60 * 1024;
@@ -64,85 +60,47 @@ bool is_small(const pvi_mdp* p, const pvi_solve_opts& o) {
 }  // namespace
 
 struct pvi_server {
-    std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<Request*> small_q, large_q;
-    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
-    std::vector<double> latency_ms;
-    uint64_t next_ticket = 1;
-    int64_t budget = 0, used = 0;
+    std::unique_ptr<pvi::srv::Core> core;
     int small_batch = 256;
     int device = 0;
-    bool stop = false;
     std::vector<std::thread> workers;
 };
 
 namespace {
 
-void finish(pvi_server* S, Request* r) {
-    const double ms =
-        std::chrono::duration<double, std::milli>(clk::now() - r->t_submit).count();
-    r->res.wall_ms = ms;
-    r->res.status = r->status;
-    r->done = 1;
-    S->latency_ms.push_back(ms);
-}
-
-void large_worker(pvi_server* S) {
+void large_worker(pvi_server* S, int w) {
     (void)hipSetDevice(S->device);
-    hipStream_t stream;
-    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return;
+    hipStream_t stream = nullptr;
+    const bool have_stream = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+    auto free_bytes = [] {
+        size_t fr = 0, tot = 0;
+        return hipMemGetInfo(&fr, &tot) == hipSuccess ? (int64_t)fr : (int64_t)0;
+    };
     for (;;) {
-        Request* r = nullptr;
-        {
-            std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [&] {
-                if (S->stop) return true;
-                if (S->large_q.empty()) return false;
-                Request* f = S->large_q.front();
-                if (f->bytes > S->budget) return true;  // can never fit: complete as BUSY
-                size_t fr = 0, tot = 0;
-                if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
-                return S->used + f->bytes <= S->budget &&
-                       (f->mdp->dev.ready || (int64_t)fr > f->bytes + (64 << 20));
-            });
-            if (S->stop && S->large_q.empty()) break;
-            if (S->large_q.empty()) continue;
-            r = S->large_q.front();
-            S->large_q.pop_front();
-            if (r->bytes > S->budget) {
-                r->status = PVI_E_BUSY;
-                finish(S, r);
-                S->cv_done.notify_all();
-                continue;
+        Job* j = S->core->next_large(w, free_bytes, PVI_E_BUSY);
+        if (!j) break;
+        auto* r = static_cast<Request*>(j);
+        pvi_status st = PVI_E_DEVICE;
+        if (have_stream) {
+            pvi_solve_opts o = r->opts;
+            o.stream = stream;
+            o.v0 = r->v0.empty() ? nullptr : r->v0.data();
+            const bool fresh = !r->mdp->dev.ready;
+            // direct launches: two workers solve at once on their own streams, and
+            // captured graphs are kept to single-caller solves
+            st = pvi::solve_impl(r->mdp, &o, &r->res, false, &r->sweeps);
+            // a handle this request made resident returns its HBM with the results
+            // in host memory, so finished requests never block the admission of
+            // new ones
+            if (fresh && (st == PVI_OK || st == PVI_E_NOT_CONVERGED)) {
+                const pvi_status ps = pvi::park_results(r->mdp);
+                if (ps != PVI_OK) st = ps;
             }
-            S->used += r->bytes;
         }
-        pvi_solve_opts o = r->opts;
-        o.stream = stream;
-        o.v0 = r->v0.empty() ? nullptr : r->v0.data();
-        pvi_result res{};
-        const bool fresh = !r->mdp->dev.ready;
-        // direct launches: two workers solve at once on their own streams, and
-        // captured graphs are kept to single-caller solves
-        pvi_status st = pvi::solve_impl(r->mdp, &o, &res, false);
-        // a handle this request made resident returns its HBM with the results in
-        // host memory, so finished requests never block the admission of new ones
-        if (fresh && (st == PVI_OK || st == PVI_E_NOT_CONVERGED)) {
-            const pvi_status ps = pvi::park_results(r->mdp);
-            if (ps != PVI_OK) st = ps;
-        }
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->used -= r->bytes;
-            r->res = res;
-            r->status = st;
-            finish(S, r);
-        }
-        S->cv_done.notify_all();
-        S->cv_work.notify_all();
+        r->res.status = st;
+        S->core->complete(r, st);
     }
-    (void)hipStreamDestroy(stream);
+    if (have_stream) (void)hipStreamDestroy(stream);
 }
 
 // Device arena of one batch worker: items, per-instance tables and outputs.
@@ -152,7 +110,7 @@ struct Arena {
     char* h = nullptr;  // pinned staging copy
 };
 
-void small_worker(pvi_server* S) {
+void small_worker(pvi_server* S, int w) {
     (void)hipSetDevice(S->device);
     hipStream_t stream;
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return;
@@ -169,17 +127,14 @@ void small_worker(pvi_server* S) {
             ar = Arena{};
         }
     }
+    std::vector<Job*> jobs;
     for (;;) {
-        std::vector<Request*> batch;
-        {
-            std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [&] { return S->stop || !S->small_q.empty(); });
-            if (S->stop && S->small_q.empty()) break;
-            while (!S->small_q.empty() && (int)batch.size() < S->small_batch) {
-                batch.push_back(S->small_q.front());
-                S->small_q.pop_front();
-            }
+        if (S->core->next_small(w, S->small_batch, -1, jobs) == 0) {
+            if (S->core->stopping()) break;
+            continue;
         }
+        std::vector<Request*> batch;
+        for (Job* j : jobs) batch.push_back(static_cast<Request*>(j));
         // layout: items | per instance: tables, V, gap, policy, stats (8-byte aligned)
         const int n = (int)batch.size();
         size_t off = sizeof(pvi::BatchItem) * n;
@@ -297,18 +252,15 @@ void small_worker(pvi_server* S) {
                     const int64_t sw = res.sweeps_fp32 + res.sweeps_fp64 + 1;
                     res.logical_backups = p->logical_per_sweep * sw;
                     res.executed_terms = p->executed_per_sweep * sw;
-                    r->status = stt[5] == 0.0 ? PVI_OK : PVI_E_NOT_CONVERGED;
+                    res.status = stt[5] == 0.0 ? PVI_OK : PVI_E_NOT_CONVERGED;
                 }
             }
         }
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            for (Request* r : batch) {
-                if (st != PVI_OK) r->status = st;
-                finish(S, r);
-            }
+        for (Request* r : batch) {
+            const pvi_status rs = st != PVI_OK ? st : (pvi_status)r->res.status;
+            r->res.status = rs;
+            S->core->complete(r, rs);
         }
-        S->cv_done.notify_all();
     }
     if (ar.d) (void)hipFree(ar.d);
     if (ar.h) (void)hipHostFree(ar.h);
@@ -328,39 +280,28 @@ pvi_status pvi_server_create(int64_t hbm_budget_bytes, int32_t small_batch, pvi_
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n == 0)
         return fail(PVI_E_DEVICE, "no HIP device available (this library has no CPU path)");
-    auto* S = new pvi_server();
-    (void)hipGetDevice(&S->device);
+    int device = 0;
+    (void)hipGetDevice(&device);
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
-        delete S;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess)
         return fail(PVI_E_DEVICE, "hipMemGetInfo failed");
-    }
-    S->budget = hbm_budget_bytes > 0 ? hbm_budget_bytes : (int64_t)(0.8 * (double)fr);
+    pvi::srv::Config cfg;
+    cfg.budget = hbm_budget_bytes > 0 ? hbm_budget_bytes : (int64_t)(0.8 * (double)fr);
+    cfg.log_path = std::getenv("PVI_SERVER_LOG");
+    auto* S = new pvi_server();
+    S->device = device;
+    S->core = std::make_unique<pvi::srv::Core>(cfg);
     S->small_batch = small_batch > 0 ? small_batch : 256;
-    for (int i = 0; i < 2; ++i) S->workers.emplace_back(small_worker, S);
-    for (int i = 0; i < 2; ++i) S->workers.emplace_back(large_worker, S);
+    for (int i = 0; i < 2; ++i) S->workers.emplace_back(small_worker, S, i);
+    for (int i = 0; i < 2; ++i) S->workers.emplace_back(large_worker, S, 2 + i);
     *out = S;
     return PVI_OK;
 }
 
 pvi_status pvi_server_destroy(pvi_server* S) {
     if (!S) return PVI_OK;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->stop = true;
-        // requests that have not started are cancelled
-        for (Request* r : S->small_q) {
-            r->status = PVI_E_CANCELLED;
-            finish(S, r);
-        }
-        for (Request* r : S->large_q) {
-            r->status = PVI_E_CANCELLED;
-            finish(S, r);
-        }
-        S->small_q.clear();
-        S->large_q.clear();
-    }
-    S->cv_work.notify_all();
+    // requests that have not started are cancelled; running ones finish
+    S->core->shutdown(PVI_E_CANCELLED);
     for (auto& t : S->workers) t.join();
     delete S;
     return PVI_OK;
@@ -390,85 +331,76 @@ pvi_status vi_batch_submit(pvi_server* S, pvi_mdp* const* mdps, const pvi_solve_
     }
     if (!(opts->eps > 0.0) || (opts->max_sweeps <= 0 && opts->fixed_sweeps <= 0))
         return fail(PVI_E_INVALID, "vi_batch_submit: bad options");
-    const auto now = clk::now();
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        if (S->stop) return fail(PVI_E_CANCELLED, "vi_batch_submit: server is shutting down");
-        for (int i = 0; i < n; ++i) {
-            auto r = std::make_unique<Request>();
-            r->ticket = S->next_ticket++;
-            r->mdp = mdps[i];
-            r->opts = *opts;
-            r->opts.stream = nullptr;
-            if (opts->v0) r->v0.assign(opts->v0, opts->v0 + mdps[i]->ns);
-            r->t_submit = now;
-            r->small = S->small_batch > 0 && is_small(mdps[i], *opts);
-            r->bytes = r->small ? 0 : (int64_t)pvi::device_bytes(mdps[i]);
-            tickets[i] = r->ticket;
-            (r->small ? S->small_q : S->large_q).push_back(r.get());
-            S->reqs[r->ticket] = std::move(r);
-        }
+    std::vector<std::unique_ptr<Job>> jobs;
+    jobs.reserve(n);
+    for (int i = 0; i < n; ++i) {
+        auto r = std::make_unique<Request>();
+        r->mdp = mdps[i];
+        r->opts = *opts;
+        r->opts.stream = nullptr;
+        if (opts->v0) r->v0.assign(opts->v0, opts->v0 + mdps[i]->ns);
+        r->small = S->small_batch > 0 && is_small(mdps[i], *opts);
+        r->bytes = r->small ? 0 : (int64_t)pvi::device_bytes(mdps[i]);
+        r->resident = mdps[i]->dev.ready;
+        jobs.push_back(std::move(r));
     }
-    S->cv_work.notify_all();
+    if (!S->core->submit(jobs, tickets))
+        return fail(PVI_E_CANCELLED, "vi_batch_submit: server is shutting down");
     return PVI_OK;
 }
 
-static pvi_status ticket_result(pvi_server* S, uint64_t ticket, pvi_result* res, bool* done) {
-    auto it = S->reqs.find(ticket);
-    if (it == S->reqs.end()) return fail(PVI_E_INVALID, "unknown ticket");
-    Request* r = it->second.get();
-    *done = r->done != 0;
-    if (*done && res) *res = r->res;
-    return PVI_OK;
+// A finished request's result; wall_ms is its latency (submit to done).
+static void copy_result(const Request* q, pvi_result* res) {
+    if (!res) return;
+    *res = q->res;
+    res->status = q->status;
+    res->wall_ms = std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count();
 }
 
 pvi_status vi_poll(pvi_server* S, uint64_t ticket, pvi_result* res) {
     if (!S) return fail(PVI_E_INVALID, "vi_poll: NULL server");
-    std::lock_guard<std::mutex> lk(S->mu);
-    bool done = false;
-    pvi_status st = ticket_result(S, ticket, res, &done);
-    if (st != PVI_OK) return st;
-    if (!done) return PVI_E_NOT_READY;
-    return S->reqs[ticket]->status;
+    Job* j = nullptr;
+    const int r = S->core->poll(ticket, &j);
+    if (r < 0) return fail(PVI_E_INVALID, "vi_poll: unknown ticket");
+    if (r == 0) return PVI_E_NOT_READY;
+    auto* q = static_cast<Request*>(j);
+    copy_result(q, res);
+    return (pvi_status)q->status;
 }
 
 pvi_status vi_wait(pvi_server* S, uint64_t ticket, int64_t timeout_us, pvi_result* res) {
     if (!S) return fail(PVI_E_INVALID, "vi_wait: NULL server");
-    std::unique_lock<std::mutex> lk(S->mu);
-    auto it = S->reqs.find(ticket);
-    if (it == S->reqs.end()) return fail(PVI_E_INVALID, "vi_wait: unknown ticket");
-    Request* r = it->second.get();
-    auto ready = [&] { return r->done != 0; };
-    if (timeout_us < 0) {
-        S->cv_done.wait(lk, ready);
-    } else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
-        return PVI_E_NOT_READY;
-    }
-    if (res) *res = r->res;
-    return r->status;
+    Job* j = nullptr;
+    const int r = S->core->wait(ticket, timeout_us, &j);
+    if (r < 0) return fail(PVI_E_INVALID, "vi_wait: unknown ticket");
+    if (r == 0) return PVI_E_NOT_READY;
+    auto* q = static_cast<Request*>(j);
+    copy_result(q, res);
+    return (pvi_status)q->status;
+}
+
+pvi_status vi_ticket_info(pvi_server* S, uint64_t ticket, pvi_ticket_info* out) {
+    if (!S || !out) return fail(PVI_E_INVALID, "vi_ticket_info: NULL argument");
+    const bool known = S->core->visit(ticket, [&](const Job& j) {
+        const auto& q = static_cast<const Request&>(j);
+        std::memset(out, 0, sizeof(*out));
+        out->state = j.state;
+        out->small = j.small ? 1 : 0;
+        out->worker = j.worker;
+        out->sweeps = q.sweeps.load();
+        out->status = j.state == pvi::srv::kDone ? j.status : PVI_E_NOT_READY;
+        out->bytes = j.bytes;
+        out->t_submit_ms = S->core->ms_since_start(j.t_submit);
+        out->t_start_ms = j.state >= pvi::srv::kRunning ? S->core->ms_since_start(j.t_start) : -1.0;
+        out->t_done_ms = j.state == pvi::srv::kDone ? S->core->ms_since_start(j.t_done) : -1.0;
+    });
+    if (!known) return fail(PVI_E_INVALID, "vi_ticket_info: unknown ticket");
+    return PVI_OK;
 }
 
 pvi_status pvi_server_stats(pvi_server* S, double* p50, double* p99, int64_t* completed) {
     if (!S) return fail(PVI_E_INVALID, "pvi_server_stats: NULL server");
-    std::vector<double> v;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        v = S->latency_ms;
-    }
-    if (completed) *completed = (int64_t)v.size();
-    if (v.empty()) {
-        if (p50) *p50 = 0.0;
-        if (p99) *p99 = 0.0;
-        return PVI_OK;
-    }
-    std::sort(v.begin(), v.end());
-    auto q = [&](double f) {
-        const double k = f * (v.size() - 1);
-        const size_t lo = (size_t)k, hi = std::min(lo + 1, v.size() - 1);
-        return v[lo] + (v[hi] - v[lo]) * (k - lo);
-    };
-    if (p50) *p50 = q(0.5);
-    if (p99) *p99 = q(0.99);
+    S->core->stats(p50, p99, completed);
     return PVI_OK;
 }
 

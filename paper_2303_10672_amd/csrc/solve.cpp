@@ -2,6 +2,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
@@ -139,6 +140,10 @@ struct Phase {
     // checkpoints of FP64 sweeps: file, interval, sweeps done before the phase, rule
     const char* ckpt = nullptr;
     int ckpt_every = 0, sweeps0 = 0, rule = 0;
+    // progress report: sweeps of the solve completed so far (earlier phases' plus
+    // this one's), stored at every host check
+    std::atomic<int>* progress = nullptr;
+    int progress_base = 0;
 };
 
 struct PhaseOut {
@@ -295,6 +300,7 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
         PVI_HIP(hipMemcpyAsync(d.h_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         PVI_HIP(hipStreamSynchronize(s));
         const Ctl& h = *d.h_ctl;
+        if (ph.progress) ph.progress->store(ph.progress_base + h.sweeps);
         if (ph.time) {
             const int real = std::min(n, h.sweeps - before);  // launches that did work
             for (int i = 0; i < real; ++i) {
@@ -382,7 +388,7 @@ using namespace pvi;
 extern "C" {
 
 pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) {
-    return pvi::solve_impl(p, opts_in, res, true);
+    return pvi::solve_impl(p, opts_in, res, true, nullptr);
 }
 
 }  // extern "C"
@@ -390,7 +396,7 @@ pvi_status vi_solve(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res) 
 // The solve behind vi_solve; the request server passes graphs = false so that its
 // concurrent workers launch every sweep directly.
 pvi_status pvi::solve_impl(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result* res,
-                           bool graphs) {
+                           bool graphs, std::atomic<int>* progress) {
     if (!p || !opts_in) return fail(PVI_E_INVALID, "vi_solve: NULL argument");
     // callers built against the layout that ended at `time_kernels` are accepted;
     // fields past their struct_size read as zero
@@ -477,6 +483,7 @@ pvi_status pvi::solve_impl(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result
         ph.kmax = kmax;
         ph.graphs = graphs;
         ph.time = o->time_kernels != 0;
+        ph.progress = progress;
         if ((st = run_phase(p, ph, s, o32)) != PVI_OK) return st;
         PVI_HIP(launch_to_f64(d.v32[o32.sweeps & 1], d.v64[0], d.ctl, p->ns, s));
     }
@@ -497,6 +504,8 @@ pvi_status pvi::solve_impl(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result
             ph.thr = thr;
         }
         ph.hist0 = hist0;
+        ph.progress = progress;
+        ph.progress_base = o32.sweeps;
         ph.ckpt = o->checkpoint_every > 0 ? o->checkpoint_path : nullptr;
         ph.ckpt_every = o->checkpoint_every;
         ph.sweeps0 = k0;

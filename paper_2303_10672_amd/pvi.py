@@ -87,6 +87,15 @@ POLICY_KIND = {"table": 0, "base_stock": 1, "mod_base_stock": 2, "s_S": 3}
 POLICY_PARAMS = 16
 
 
+class TicketInfo(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int32), ("small", ctypes.c_int32), ("worker", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("bytes", ctypes.c_int64), ("t_submit_ms", ctypes.c_double),
+        ("t_start_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+    ]
+
+
 class RolloutOpts(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32), ("kind", ctypes.c_int32),
@@ -135,6 +144,7 @@ def load():
         "vi_poll": (i32, [vp, ctypes.c_uint64, _P(Result)]),
         "vi_wait": (i32, [vp, ctypes.c_uint64, i64, _P(Result)]),
         "pvi_server_stats": (i32, [vp, dp, dp, _P(i64)]),
+        "vi_ticket_info": (i32, [vp, ctypes.c_uint64, _P(TicketInfo)]),
         "policy_rollouts": (i32, [vp, _P(RolloutOpts), dp, dp, dp]),
         "heuristic_search": (i32, [vp, _P(RolloutOpts), dp, _P(i32)]),
         "pvi_last_error": (ctypes.c_char_p, []),
@@ -396,6 +406,16 @@ class Server:
         r = Result()
         st = _lib.vi_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_us), ctypes.byref(r))
         return st, r.to_dict()
+
+    def ticket_info(self, ticket):
+        """vi_ticket_info: state (queued/running/done), path, worker, sweeps so far, times."""
+        i = TicketInfo()
+        _check(_lib.vi_ticket_info(self.handle, ctypes.c_uint64(ticket), ctypes.byref(i)),
+               "vi_ticket_info")
+        return {"state": ("queued", "running", "done")[i.state], "small": bool(i.small),
+                "worker": i.worker, "sweeps": i.sweeps, "status": i.status, "bytes": i.bytes,
+                "t_submit_ms": i.t_submit_ms, "t_start_ms": i.t_start_ms,
+                "t_done_ms": i.t_done_ms}
 
     def stats(self):
         p50, p99 = ctypes.c_double(), ctypes.c_double()

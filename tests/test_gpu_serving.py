@@ -145,3 +145,26 @@ def test_finished_requests_return_their_memory():
     r = pvi.policy_rollouts(handles[0], n_rollouts=64, seed=3)
     g = pvi.policy_rollouts(ref, n_rollouts=64, seed=3)
     assert np.array_equal(r["ret"], g["ret"])
+
+
+def test_ticket_info_and_event_log(tmp_path, monkeypatch):
+    """vi_ticket_info reports a request's path, worker and progress; with
+    PVI_SERVER_LOG set the server writes one line per submit, start and done."""
+    log = tmp_path / "events.log"
+    monkeypatch.setenv("PVI_SERVER_LOG", str(log))
+    s = pvi.Server(small_batch=256)
+    mb = pvi.mdp_create(W.config1())
+    msm = pvi.mdp_create(W.config0())
+    tb = s.submit([mb], precision="fp64")[0]
+    ts = s.submit([msm], precision="fp64")[0]
+    assert s.wait(tb)[0] == pvi.PVI_OK and s.wait(ts)[0] == pvi.PVI_OK
+    ib, i_s = s.ticket_info(tb), s.ticket_info(ts)
+    s.close()
+    assert ib["state"] == "done" and not ib["small"] and ib["worker"] in (2, 3)
+    assert ib["sweeps"] >= 30 and ib["bytes"] > 0
+    assert ib["t_submit_ms"] <= ib["t_start_ms"] <= ib["t_done_ms"]
+    assert i_s["state"] == "done" and i_s["small"] and i_s["worker"] in (0, 1)
+    lines = log.read_text().splitlines()
+    for t in (tb, ts):
+        ev = [ln.split()[1] for ln in lines if f"ticket={t} " in ln]
+        assert ev == ["submit", "start", "done"], ev
