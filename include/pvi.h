@@ -251,6 +251,28 @@ pvi_status mdp_life_probs(const pvi_mdp* mdp, double* out);
  * after max_sweeps (results still readable).  res may be NULL. */
 pvi_status vi_solve(pvi_mdp* mdp, const pvi_solve_opts* opts, pvi_result* res);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the FP64 solve of
+ * vi_solve for a scenario-A handle (FIFO or LIFO), with no device or pinned host
+ * allocation.  The caller brings the outputs in device memory: d_v[N_S] (FP64,
+ * also the first value table of the sweeps; V_0 is written into it: zeros, or
+ * opts->v0 copied from the host), d_policy[N_S] (int32) and d_gap[N_S] (FP64).
+ * Everything else (control block, tables, work list, span partials and the
+ * second value table) lives in a fixed device array of the library, about
+ * 33 MiB per device, held until the process ends.  Limits: N_S <= 4,194,304
+ * states; the handle's tables and work list within 512 KiB, its span partials
+ * within 512 KiB.  Options: precision PVI_FP64, stop_rule SPAN or SUPNORM, no
+ * checkpoint files; opts->stream (NULL: the null stream) carries every launch and
+ * copy, and the call returns after synchronising it.  The kernels and their
+ * order are vi_solve's, so V, policy, gap and sweep counts equal vi_solve's
+ * FP64 results bit for bit.  Calls on one device share the array: the library
+ * serialises them within a process (each call takes a per-device lock); every
+ * value a call reads is written by that call first.  Errors: PVI_E_INVALID (NULL
+ * outputs, another family, precision or rule, sizes beyond the limits),
+ * PVI_E_DEVICE, PVI_E_NOT_CONVERGED (results still written). */
+pvi_status vi_solve_noalloc(const pvi_mdp* mdp, const pvi_solve_opts* opts, double* d_v,
+                            int32_t* d_policy, double* d_gap, pvi_result* res);
+
 /* One backup of a caller-given FP64 V (host [N_S]) in the given precision:
  * v_out[N_S] = T(V), policy[N_S] = argmax, q_gap[N_S] = best - second (FP64
  * precision only; NULL allowed).  For parity checks of single sweeps. */

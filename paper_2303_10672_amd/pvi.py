@@ -134,6 +134,7 @@ def load():
         "mdp_life_probs": (i32, [vp, dp]),
         "vi_solve": (i32, [vp, _P(Opts), _P(Result)]),
         "vi_backup": (i32, [vp, i32, dp, dp, _P(i32), dp]),
+        "vi_solve_noalloc": (i32, [vp, _P(Opts), vp, vp, vp, _P(Result)]),
         "policy_get": (i32, [vp, _P(i32), dp]),
         "value_get": (i32, [vp, dp]),
         "checkpoint_read": (i32, [vp, ctypes.c_char_p, dp, _P(i32), _P(i32)]),
@@ -314,6 +315,23 @@ def vi_solve(m, precision="fp32", eps=None, max_sweeps=100000, fixed_sweeps=0, v
     st = _lib.vi_solve(m.handle, ctypes.byref(o), ctypes.byref(r))
     if not (allow_not_converged and st == PVI_E_NOT_CONVERGED):
         _check(st, "vi_solve")
+    return r.to_dict()
+
+
+def vi_solve_noalloc(m, d_v, d_policy, d_gap, eps=None, max_sweeps=100000, fixed_sweeps=0,
+                     v0=None, stream=None, stop_rule="span", allow_not_converged=False):
+    """FP64 scenario-A solve with no device allocation (vi_solve_noalloc).  d_v,
+    d_policy, d_gap: device addresses (e.g. tensor.data_ptr()) of float64[N_S],
+    int32[N_S] and float64[N_S] outputs.  Returns the pvi_result fields as a dict."""
+    v0a = None if v0 is None else np.ascontiguousarray(v0, dtype=np.float64)
+    o = make_opts("fp64", eps, max_sweeps, fixed_sweeps, v0a, stream, 0, False, m.sc,
+                  stop_rule)
+    r = Result()
+    st = _lib.vi_solve_noalloc(m.handle, ctypes.byref(o), ctypes.c_void_p(d_v),
+                               ctypes.c_void_p(d_policy), ctypes.c_void_p(d_gap),
+                               ctypes.byref(r))
+    if not (allow_not_converged and st == PVI_E_NOT_CONVERGED):
+        _check(st, "vi_solve_noalloc")
     return r.to_dict()
 
 
