@@ -279,12 +279,18 @@ pvi_status vi_solve_noalloc(const pvi_mdp* mdp, const pvi_solve_opts* opts, doub
 pvi_status vi_backup(pvi_mdp* mdp, int32_t precision, const double* v_in, double* v_out,
                      int32_t* policy, double* q_gap);
 
-/* Checkpoint file (little-endian): the 8 bytes "PVICKPT1", uint32 version (1),
+/* Checkpoint file (little-endian): the 8 bytes "PVICKPT1", uint32 version (2),
  * uint32 family, uint64 fingerprint of the descriptor, int64 N_S, int32 N_A, int32
  * stop rule, int32 FP64 sweeps done, int32 stopped (1 when the stopping rule had
- * fired at that sweep), int32 H, int32 reserved (0), then H tables of N_S FP64
+ * fired at that sweep), int32 H, int32 reserved (0), then four FP64: the threshold
+ * the writing solve's rule tested (span rule: eps (1-gamma)/gamma; else eps), and
+ * max, min and span of its last V_new - V; then H tables of N_S FP64
  * values: V after the last sweep, then the H - 1 before it (H = 1, or under the
- * periodic rule min(sweeps, P) + 1, the tables its test reads).
+ * periodic rule min(sweeps, P) + 1, the tables its test reads).  Files of version
+ * 1 (no four FP64) are still read.  A resume from a file whose rule had fired
+ * runs no sweep only when the rule is the same and the file's threshold is no
+ * larger than the resuming solve's (its result then reports the file's
+ * increments); with a tighter threshold, or a version-1 file, it goes on sweeping.
  * checkpoint_read checks the file against the handle and returns the sweep count,
  * stopped flag and the last table (v: host [N_S], NULL to skip).  Errors:
  * PVI_E_IO (missing, unreadable or short file), PVI_E_INVALID (wrong magic or

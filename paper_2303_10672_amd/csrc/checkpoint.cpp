@@ -4,6 +4,7 @@
 // cloud sessions from its checkpoints) resumes where it stopped.
 #include "checkpoint.h"
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -15,7 +16,7 @@ namespace pvi {
 namespace {
 
 constexpr char kMagic[8] = {'P', 'V', 'I', 'C', 'K', 'P', 'T', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;  // version 1 (no threshold or increments) is still read
 constexpr int kMaxTables = PVI_MAX_PERIODS + 1;
 
 struct Header {
@@ -26,6 +27,11 @@ struct Header {
     int32_t na, rule, sweeps, stopped, hist, reserved;
 };
 static_assert(sizeof(Header) == 56, "checkpoint header layout");
+// follows the header in version 2
+struct HeaderStats {
+    double threshold, dmax, dmin, span;
+};
+static_assert(sizeof(HeaderStats) == 32, "checkpoint header layout");
 
 struct Fnv {
     uint64_t h = 1469598103934665603ull;
@@ -81,16 +87,24 @@ pvi_status checkpoint_load(const pvi_mdp* p, const char* path, bool want_tables,
     if (std::fread(&hd, sizeof hd, 1, in.f) != 1) return fail(PVI_E_IO, w + ": short header");
     if (std::memcmp(hd.magic, kMagic, sizeof kMagic) != 0)
         return fail(PVI_E_INVALID, w + ": not a checkpoint file");
-    if (hd.version != kVersion) return fail(PVI_E_INVALID, w + ": unknown version");
+    if (hd.version != 1 && hd.version != kVersion)
+        return fail(PVI_E_INVALID, w + ": unknown version");
     if (hd.fingerprint != mdp_fingerprint(p) || hd.ns != p->ns || hd.na != p->na ||
         (int)hd.family != p->family)
         return fail(PVI_E_INVALID, w + ": written for another MDP descriptor");
     if (hd.hist < 1 || hd.hist > kMaxTables || hd.sweeps < 0 || (hd.stopped & ~1) != 0 ||
         hd.rule < PVI_STOP_SPAN || hd.rule > PVI_STOP_PERIODIC)
         return fail(PVI_E_INVALID, w + ": corrupt header");
+    HeaderStats hs{std::nan(""), 0.0, 0.0, 0.0};
+    if (hd.version >= 2 && std::fread(&hs, sizeof hs, 1, in.f) != 1)
+        return fail(PVI_E_IO, w + ": short header");
     out.rule = hd.rule;
     out.sweeps = hd.sweeps;
     out.stopped = hd.stopped;
+    out.threshold = hs.threshold;
+    out.dmax = hs.dmax;
+    out.dmin = hs.dmin;
+    out.span = hs.span;
     out.tables.clear();
     const int n = want_tables ? hd.hist : 1;
     for (int k = 0; k < n; ++k) {
@@ -108,8 +122,8 @@ pvi_status checkpoint_load(const pvi_mdp* p, const char* path, bool want_tables,
 }
 
 pvi_status checkpoint_store(const pvi_mdp* p, const char* path, int32_t rule, int32_t sweeps,
-                            int32_t stopped, const double* const* tables, int n_tables,
-                            hipStream_t s) {
+                            int32_t stopped, const CheckpointStats& stats,
+                            const double* const* tables, int n_tables, hipStream_t s) {
     if (!path || n_tables < 1 || n_tables > kMaxTables)
         return fail(PVI_E_INVALID, "checkpoint: bad arguments");
     std::vector<double> host((size_t)n_tables * p->ns);
@@ -128,12 +142,13 @@ pvi_status checkpoint_store(const pvi_mdp* p, const char* path, int32_t rule, in
     hd.sweeps = sweeps;
     hd.stopped = stopped ? 1 : 0;
     hd.hist = n_tables;
+    const HeaderStats hs{stats.threshold, stats.dmax, stats.dmin, stats.span};
     const std::string tmp = std::string(path) + ".tmp";
     {
         File o;
         o.f = std::fopen(tmp.c_str(), "wb");
         if (!o.f) return fail(PVI_E_IO, "checkpoint " + tmp + ": cannot create");
-        if (std::fwrite(&hd, sizeof hd, 1, o.f) != 1 ||
+        if (std::fwrite(&hd, sizeof hd, 1, o.f) != 1 || std::fwrite(&hs, sizeof hs, 1, o.f) != 1 ||
             std::fwrite(host.data(), sizeof(double), host.size(), o.f) != host.size() ||
             std::fflush(o.f) != 0)
             return fail(PVI_E_IO, "checkpoint " + tmp + ": write failed");

@@ -140,6 +140,7 @@ struct Phase {
     // checkpoints of FP64 sweeps: file, interval, sweeps done before the phase, rule
     const char* ckpt = nullptr;
     int ckpt_every = 0, sweeps0 = 0, rule = 0;
+    double ckpt_thr = 0.0;  // stopping threshold recorded in the files
     // progress report: sweeps of the solve completed so far (earlier phases' plus
     // this one's), stored at every host check
     std::atomic<int>* progress = nullptr;
@@ -168,7 +169,15 @@ pvi_status write_checkpoint(pvi_mdp* p, const Phase& ph, int done, bool stopped,
     const int n = ph.period > 0 ? std::min(ph.hist0 + done, ph.period) + 1 : 1;
     const double* t[PVI_MAX_PERIODS + 1];
     for (int j = 0; j < n; ++j) t[j] = v64_slot(p, ring_slot(done, j, ph.ring));
-    return checkpoint_store(p, ph.ckpt, ph.rule, ph.sweeps0 + done, stopped ? 1 : 0, t, n, s);
+    // the control block the host read at its last check holds this sweep's increments
+    const Ctl& h = *p->dev.h_ctl;
+    CheckpointStats cs;
+    cs.threshold = ph.ckpt_thr;
+    cs.dmax = h.dmax;
+    cs.dmin = h.dmin;
+    cs.span = h.span;
+    return checkpoint_store(p, ph.ckpt, ph.rule, ph.sweeps0 + done, stopped ? 1 : 0, cs, t, n,
+                            s);
 }
 
 pvi_status ensure_ring(pvi_mdp* p, int ring) {
@@ -510,17 +519,22 @@ pvi_status pvi::solve_impl(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result
         ph.ckpt_every = o->checkpoint_every;
         ph.sweeps0 = k0;
         ph.rule = o->stop_rule;
-        // a resumed solve whose checkpoint already met the same stopping rule, or
-        // reached its fixed sweep count or the sweep cap, runs no more sweeps
+        ph.ckpt_thr = thr;
+        // a resumed solve whose checkpoint already met the same stopping rule at a
+        // threshold no larger than this one, or reached its fixed sweep count or the
+        // sweep cap, runs no more sweeps (a file of version 1 holds no threshold: its
+        // solve goes on sweeping, and stops at once if the rule holds)
         const bool done_before = resumed && o->fixed_sweeps <= 0 && ck.stopped &&
-                                 ck.rule == o->stop_rule;
+                                 ck.rule == o->stop_rule && ck.threshold <= thr;
         const bool nothing_left = o->fixed_sweeps > 0 ? ph.fixed <= 0 : ph.max_sweeps <= 0;
         if (done_before || nothing_left)
             o64.stopped = done_before;
         else if ((st = run_phase(p, ph, s, o64)) != PVI_OK)
             return st;
         p->ret_buf = ring_slot(o64.sweeps, 0, ph.ring);
-        if (ph.ckpt && (st = write_checkpoint(p, ph, o64.sweeps, o64.stopped, s)) != PVI_OK)
+        // (a resume that ran no sweep leaves its file as it was)
+        if (ph.ckpt && !(resumed && o64.sweeps == 0) &&
+            (st = write_checkpoint(p, ph, o64.sweeps, o64.stopped, s)) != PVI_OK)
             return st;
     } else {
         p->ret_buf = 0;
@@ -538,10 +552,12 @@ pvi_status pvi::solve_impl(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result
         res->sweeps_fp64 = fp64_phase ? k0 + o64.sweeps : 0;
         res->backup_launches[0] = o64.timed;
         res->backup_launches[1] = o32.timed;
-        res->final_span = h.span;
+        // a resume that ran no sweep reports the increments the file recorded
+        const bool from_file = resumed && o64.sweeps == 0 && fp64_phase;
+        res->final_span = from_file ? ck.span : h.span;
         res->threshold = thr;
-        res->dmax = h.dmax;
-        res->dmin = h.dmin;
+        res->dmax = from_file ? ck.dmax : h.dmax;
+        res->dmin = from_file ? ck.dmin : h.dmin;
         res->backup_ms[0] = o64.backup_ms;
         res->backup_ms[1] = o32.backup_ms;
         const int64_t sweeps = o32.sweeps + o64.sweeps + 1;  // run by this call

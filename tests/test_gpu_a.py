@@ -194,51 +194,3 @@ def test_max_sweeps_not_converged_keeps_results():
     assert e.value.status == pvi.PVI_E_NOT_CONVERGED
     V = pvi.value_get(m)
     assert np.all(np.isfinite(V))
-
-
-# ------------------------------------------------------------- full-size config 1
-
-@pytest.fixture(scope="module")
-def cfg1():
-    sc = W.config1()
-    return sc, Oracle(sc), pvi.mdp_create(sc)
-
-
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("fp32_wide", 1e-6)])
-def test_config1_one_backup_sampled(cfg1, prec, tol):
-    sc, o, m = cfg1
-    V = W.random_values(o.n_states, seed=7, scale=50.0, offset=-800.0)
-    Vg, pig, gapg = pvi.vi_backup(m, V, prec)
-    idx = W.sample_indices(o.n_states, 1500, seed=1)
-    q = o.q_states(V, idx)
-    Vo = q.max(axis=1)
-    assert float(np.abs(Vg[idx] - Vo).max() / np.abs(Vo).max()) < tol
-    qs = np.sort(q, axis=1)
-    clear = (qs[:, -1] - qs[:, -2]) > 1e-9
-    assert np.array_equal(pig[idx][clear], q.argmax(axis=1)[clear])
-
-
-def test_config1_solve_certified(cfg1):
-    """Converged FP32-schedule solve at full size, certified by oracle backups.
-
-    One oracle backup of the GPU's returned V at sampled states gives T V.  By
-    monotonicity and contraction, T V - V must lie in [g dmin, g dmax], where dmin
-    and dmax bound the GPU's last V_new - V; this certifies the GPU's sweep and
-    its span bookkeeping at full size.  The policy must equal the oracle's argmax
-    of Q(V) wherever its gap exceeds 1e-6.
-    """
-    sc, o, m = cfg1
-    g = sc["gamma"]
-    res = pvi.vi_solve(m, precision="fp32")
-    assert res["final_span"] < res["threshold"]
-    V = pvi.value_get(m)
-    pol, gap = pvi.policy_get(m)
-    idx = W.sample_indices(o.n_states, 800, seed=2)
-    q = o.q_states(V, idx)
-    TV = q.max(axis=1)
-    dv = TV - V[idx]
-    assert dv.max() <= g * res["dmax"] + 1e-9 and dv.min() >= g * res["dmin"] - 1e-9
-    qs = np.sort(q, axis=1)
-    clear = (qs[:, -1] - qs[:, -2]) > 1e-6
-    assert np.array_equal(pol[idx][clear], q.argmax(axis=1)[clear])
-    assert np.allclose(gap[idx][clear], (qs[:, -1] - qs[:, -2])[clear], rtol=1e-6, atol=1e-8)

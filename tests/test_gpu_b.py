@@ -66,39 +66,3 @@ def test_converged(sc):
         assert relerr(vhat(pvi.value_get(m), res, g), vhat(ref["V"], ref, g)) < 1e-5
         pol, _ = pvi.policy_get(m)
         assert np.array_equal(pol[clear], tight["pi"][clear])
-
-
-@pytest.fixture(scope="module")
-def cfg2():
-    sc = W.config2()
-    return sc, Oracle(sc), pvi.mdp_create(sc)
-
-
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
-def test_config2_one_backup_sampled(cfg2, prec, tol):
-    sc, o, m = cfg2
-    V = W.random_values(o.n_states, seed=12, scale=3.0, offset=120.0)
-    Vg, pig, _ = pvi.vi_backup(m, V, prec)
-    idx = W.sample_indices(o.n_states, 150, seed=3)
-    q = o.q_states(V, idx)
-    Vo = q.max(axis=1)
-    assert float(np.abs(Vg[idx] - Vo).max() / np.abs(Vo).max()) < tol
-    qs = np.sort(q, axis=1)
-    clear = (qs[:, -1] - qs[:, -2]) > 1e-9
-    assert np.array_equal(pig[idx][clear], q.argmax(axis=1)[clear])
-
-
-def test_config2_solve_certified(cfg2):
-    sc, o, m = cfg2
-    g = sc["gamma"]
-    res = pvi.vi_solve(m, precision="fp32")
-    assert res["final_span"] < res["threshold"]
-    V = pvi.value_get(m)
-    pol, gap = pvi.policy_get(m)
-    idx = W.sample_indices(o.n_states, 120, seed=4)
-    q = o.q_states(V, idx)
-    dv = q.max(axis=1) - V[idx]
-    assert dv.max() <= g * res["dmax"] + 1e-9 and dv.min() >= g * res["dmin"] - 1e-9
-    qs = np.sort(q, axis=1)
-    clear = (qs[:, -1] - qs[:, -2]) > 1e-6
-    assert np.array_equal(pol[idx][clear], q.argmax(axis=1)[clear])

@@ -116,23 +116,3 @@ def test_endogenous_converged(sc):
     res = pvi.vi_solve(m, precision="fp32")
     assert res["final_span"] < res["threshold"]
     assert relerr(vhat(pvi.value_get(m), res, g), vhat(ref["V"], ref, g)) < 1e-5
-
-
-@pytest.fixture(scope="module")
-def cfg3():
-    sc = W.config3()
-    return sc, Oracle(sc), pvi.mdp_create(sc)
-
-
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
-def test_config3_one_backup_sampled(cfg3, prec, tol):
-    sc, o, m = cfg3
-    V = W.random_values(o.n_states, seed=13, scale=30.0, offset=-900.0)
-    Vg, pig, _ = pvi.vi_backup(m, V, prec)
-    idx = W.sample_indices(o.n_states, 12, seed=5)
-    q = o.q_states(V, idx)
-    Vo = q.max(axis=1)
-    assert float(np.abs(Vg[idx] - Vo).max() / np.abs(Vo).max()) < tol
-    qs = np.sort(q, axis=1)
-    clear = (qs[:, -1] - qs[:, -2]) > 1e-9
-    assert np.array_equal(pig[idx][clear], q.argmax(axis=1)[clear])

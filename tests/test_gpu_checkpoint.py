@@ -25,17 +25,18 @@ CASES = {
     "C-periodic": (W.scenario_c(m=3, a_max=6, d_max=10, c0=[0.0, 1.0, 0.5]), "periodic"),
 }
 
-HEADER = struct.Struct("<8sIIQqiiiiii")
+HEADER = struct.Struct("<8sIIQqiiiiiidddd")
 
 
 def _parse(path, n_states):
     raw = open(path, "rb").read()
     (magic, version, family, _fp, ns, na, rule, sweeps, stopped, hist,
-     reserved) = HEADER.unpack_from(raw)
-    assert magic == b"PVICKPT1" and version == 1 and reserved == 0 and ns == n_states
+     reserved, thr, dmax, dmin, span) = HEADER.unpack_from(raw)
+    assert magic == b"PVICKPT1" and version == 2 and reserved == 0 and ns == n_states
     tables = np.frombuffer(raw, dtype="<f8", offset=HEADER.size)
     assert tables.size == hist * ns
     return dict(family=family, na=na, rule=rule, sweeps=sweeps, stopped=stopped,
+                threshold=thr, dmax=dmax, dmin=dmin, span=span,
                 tables=tables.reshape(hist, ns))
 
 
@@ -156,3 +157,35 @@ def test_other_descriptor_and_truncated_file(tmp_path):
         assert "checkpoint" in pvi._lib.pvi_last_error().decode()
     finally:
         server.close()
+
+
+@pytest.mark.parametrize("rule", ["span", "supnorm"])
+def test_resume_with_a_tighter_threshold_goes_on(rule, tmp_path):
+    """A file written when the rule fired at a loose eps does not end a resume that
+    asks for a tighter one: it sweeps on and ends where an uninterrupted solve at the
+    tight eps ends.  A resume at the same eps runs no sweep and reports the file's
+    increments."""
+    sc = W.config0()
+    path = str(tmp_path / "loose.ckpt")
+    m = pvi.mdp_create(sc)
+    loose = pvi.vi_solve(m, precision="fp64", stop_rule=rule, eps=1e-1, checkpoint=path,
+                         checkpoint_every=1)
+    f = _parse(path, m.n_states)
+    assert f["stopped"] == 1 and f["sweeps"] == loose["sweeps_fp64"]
+    assert f["threshold"] == loose["threshold"]
+    assert (f["dmax"], f["dmin"], f["span"]) == (loose["dmax"], loose["dmin"],
+                                                 loose["final_span"])
+    same = pvi.vi_solve(pvi.mdp_create(sc), precision="fp64", stop_rule=rule, eps=1e-1,
+                        checkpoint=path, resume=True)
+    assert same["sweeps_fp64"] == loose["sweeps_fp64"]
+    assert same["final_span"] == loose["final_span"] and same["dmax"] == loose["dmax"]
+    ref_m = pvi.mdp_create(sc)
+    ref = pvi.vi_solve(ref_m, precision="fp64", stop_rule=rule, eps=1e-6)
+    assert ref["sweeps_fp64"] > loose["sweeps_fp64"]
+    fresh = pvi.mdp_create(sc)
+    res = pvi.vi_solve(fresh, precision="fp64", stop_rule=rule, eps=1e-6, checkpoint=path,
+                       resume=True)
+    assert res["sweeps_fp64"] == ref["sweeps_fp64"]
+    assert res["final_span"] == ref["final_span"]
+    assert np.array_equal(pvi.value_get(fresh), pvi.value_get(ref_m))
+    assert np.array_equal(pvi.policy_get(fresh)[0], pvi.policy_get(ref_m)[0])

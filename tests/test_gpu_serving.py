@@ -1,8 +1,8 @@
 """The batched small-instance kernel and the request server, through the C ABI.
 
-* Every batched result equals the same instance solved alone by vi_solve: FP64
-  values to 1e-12 relative with the same sweep count, FP32-schedule values (bound
-  midpoint) to 1e-5, policies equal where the oracle gap exceeds 1e-6.
+* Every batched result equals the same instance solved alone by vi_solve and by
+  the oracle: FP64 values to 1e-12 relative with the same sweep count, FP32-schedule
+  values (bound midpoint) to 1e-5, policies equal where the oracle gap exceeds 1e-6.
 * A result is bit-identical whether its instance ran alone or inside a mixed
   batch (one workgroup per instance, fixed reduction order).
 * Large instances go through the ordinary sweep loop on the server's own streams
@@ -57,7 +57,15 @@ def test_batched_matches_alone_and_oracle(server, prec):
             assert relerr(V, Va) < 1e-12
         else:
             assert relerr(vhat(V, res, g), vhat(Va, ra, g)) < 1e-5
-        tight = Oracle(sc).solve(thr=1e-11)
+        # and directly against the oracle's solve of the same instance
+        o = Oracle(sc)
+        ref = o.solve()
+        if prec == "fp64":
+            assert res["sweeps_fp64"] == ref["sweeps"]
+            assert relerr(V, ref["V"]) < 1e-12
+        else:
+            assert relerr(vhat(V, res, g), vhat(ref["V"], ref, g)) < 1e-5
+        tight = o.solve(thr=1e-11)
         clear = tight["gap"] > 1e-6
         assert np.array_equal(pol[clear], tight["pi"][clear])
 
