@@ -3,12 +3,17 @@
 Workload: the m=4, L=2 scenario-A instance (4,084,101 states, 21 actions, gamma
 demand with mean 4 and CV 1.5 folded at 60, seeded +-20% cost jitter, gamma 0.99,
 span threshold 1e-4 (1-gamma)/gamma).  One step = one complete solve through the
-C ABI from V0 = 0: FP32 sweeps, FP64 check and polish sweeps, and the FP64 policy
-extraction, with the MDP's tables already resident in HBM.
+C ABI from V0 = 0 in the chosen precision (FP64 by default; the FP32 schedules run
+FP32 sweeps, then FP64 check and polish sweeps), and the FP64 policy extraction,
+with the MDP's tables already resident in HBM.
 
 value = logical backups (states x actions x demand outcomes, summed over every
-sweep of every step) / wall time of the timed steps.  The FP64 one-solve-per-call
-path is timed the same way and reported beside it.
+sweep of every step) / wall time of the timed steps.
+
+Beside it: the other schedules (FP64, compensated FP32, FP32 storage with FP64 sums),
+timed the same way on the same
+instance, the cold first calls, the roofline of the dominant kernel on the bytes a
+sweep must move, and the FP32 schedules' error against FP64 for configs 0-3.
 
 Run: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp32_wide|fp64]
 """
@@ -39,6 +44,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the FP32-vs-FP64 error of configs 0-3 (about 20 s)")
     ap.add_argument("--workload", default="config1", choices=["config1", "batch", "serving", "oracle",
                                                                "config2", "config3",
                                                                "paper-a", "paper-b", "paper-c", "rollouts"],
@@ -104,6 +111,44 @@ def time_solves(pvi, m, precision, steps, warmup, stream):
         "backup_ms": kern_ms, "launches": launches,
         "sweeps_fp32": results[-1]["sweeps_fp32"], "sweeps_fp64": results[-1]["sweeps_fp64"],
     }
+
+
+def fp32_errors(pvi, W, cfgs=(0, 1, 2, 3)):
+    """Error of the FP32 schedules against the FP64 solve of the same instance, per
+    config: max |V_32 - V_64| over max |V_64| (normwise) and max |V_32 - V_64| / |V_64|
+    (elementwise), for the returned V and for the bound midpoints V + gamma/(1-gamma)
+    (dmax + dmin)/2 (the two solves stop at different sweeps, so their V differ by up to
+    the stopping tolerance while both midpoints bracket V*); and the number of states
+    whose policy differs where the FP64 solve's best-minus-second Q exceeds 1e-6."""
+    import numpy as np
+    out = {}
+    for c in cfgs:
+        sc = W.config_by_index(c)
+        g = sc["gamma"]
+        m = pvi.mdp_create(sc)
+        r64 = pvi.vi_solve(m, precision="fp64")
+        V64 = pvi.value_get(m)
+        p64, gap64 = pvi.policy_get(m)
+        h64 = V64 + g / (1 - g) * 0.5 * (r64["dmax"] + r64["dmin"])
+        row = {"states": int(m.n_states), "sweeps_fp64": r64["sweeps_fp64"]}
+        for mode in ("fp32", "fp32_wide"):
+            r = pvi.vi_solve(m, precision=mode)
+            V = pvi.value_get(m)
+            p, _ = pvi.policy_get(m)
+            h = V + g / (1 - g) * 0.5 * (r["dmax"] + r["dmin"])
+            clear = gap64 > 1e-6
+            row[mode] = {
+                "sweeps": {"fp32": r["sweeps_fp32"], "fp64": r["sweeps_fp64"]},
+                "v_normwise": float(np.abs(V - V64).max() / np.abs(V64).max()),
+                "v_elementwise": float((np.abs(V - V64) / np.abs(V64)).max()),
+                "vhat_normwise": float(np.abs(h - h64).max() / np.abs(h64).max()),
+                "vhat_elementwise": float((np.abs(h - h64) / np.abs(h64)).max()),
+                "policy_differs_where_gap_gt_1e-6": int((p[clear] != p64[clear]).sum()),
+                "policy_differs_anywhere": int((p != p64).sum()),
+            }
+        out[f"config{c}"] = row
+        del m
+    return out
 
 
 def cpu_baseline(sc, target_s):
@@ -590,16 +635,30 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     sc = W.config1()
-    m = pvi.mdp_create(sc)
     stream = torch.cuda.Stream()
     handle = stream.cuda_stream
+    # cold calls, reported apart from the timed steps: the first solve of the process
+    # (code objects loaded, device buffers allocated, tables uploaded, graphs captured)
+    # and the first solve of a second handle in the warm process
+    cold = {}
+    for key in ("process_first_call_ms", "new_handle_first_call_ms"):
+        mc = pvi.mdp_create(sc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pvi.vi_solve(mc, precision=args.precision, stream=handle)
+        torch.cuda.synchronize()
+        cold[key] = (time.perf_counter() - t0) * 1e3
+        del mc
+    m = pvi.mdp_create(sc)
 
     main_run = time_solves(pvi, m, args.precision, args.steps, args.warmup, handle)
     fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
-    other = "fp32_wide" if args.precision == "fp64" else "fp64"
-    other_run = time_solves(pvi, m, other, fp64_steps, 1, handle)
-    fp64_run = main_run if args.precision == "fp64" else other_run
-    fp32_run = other_run if args.precision == "fp64" else main_run
+    others = [p for p in ("fp64", "fp32", "fp32_wide") if p != args.precision]
+    runs = {args.precision: main_run}
+    for p in others:
+        runs[p] = time_solves(pvi, m, p, fp64_steps, 1, handle)
+    fp64_run = runs["fp64"]
+    cold["warm_p50_ms"] = percentile(main_run["lat_ms"], 0.5)
 
     value = main_run["logical"] / main_run["wall_s"]
     ms_per_step = main_run["wall_s"] * 1e3 / args.steps
@@ -607,9 +666,12 @@ def main():
     dom = 0 if args.precision == "fp64" else 1
     launches = max(main_run["launches"][dom], 1)
     avg_kernel_s = main_run["backup_ms"][dom] / launches * 1e-3
+    # algorithmic bytes of one sweep: read V once and write V' once (FP64: 16 B per
+    # state, FP32 storage: 8 B); the gathers of V[s'] re-read that same table
+    state_bytes = 16 if dom == 0 else 8
+    achieved_gbs = m.n_states * state_bytes / avg_kernel_s / 1e9
     per_launch_logical = m.n_states * m.n_actions * (sc["d_max"][0] + 1)
-    bytes_per_backup = 8 if dom == 0 else 4
-    achieved_gbs = per_launch_logical * bytes_per_backup / avg_kernel_s / 1e9
+    logical_gbs = per_launch_logical * (8 if dom == 0 else 4) / avg_kernel_s / 1e9
     sweeps = main_run["sweeps_fp32"] + main_run["sweeps_fp64"] + 1
     executed_per_launch = main_run["executed"] / (args.steps * sweeps)
     fma_tflops = 2.0 * executed_per_launch / avg_kernel_s / 1e12
@@ -625,9 +687,23 @@ def main():
         traffic_detail = {"unit": "bytes per launch", "fetch": meas[0], "write": meas[1],
                           "source": os.path.relpath(TRAFFIC_PROFILE,
                                                     os.path.dirname(os.path.abspath(__file__))),
-                          "compulsory": 16.0 * m.n_states,
+                          "algorithmic": float(state_bytes * m.n_states),
+                          "measured_over_algorithmic": traffic / (state_bytes * m.n_states),
                           "measured_gbs": measured_gbs,
                           "measured_frac": measured_gbs / HBM_PEAK_GBS}
+
+    def schedule(p):
+        r = runs[p]
+        return {
+            "value": r["logical"] / r["wall_s"],
+            "ms_per_solve": percentile(r["lat_ms"], 0.5),
+            "latency_ms": {"p50": percentile(r["lat_ms"], 0.5),
+                           "p99": percentile(r["lat_ms"], 0.99)},
+            "sweeps": {"fp32": r["sweeps_fp32"], "fp64": r["sweeps_fp64"], "extract": 1},
+            "avg_backup_kernel_ms": {
+                "fp32_storage": r["backup_ms"][1] / max(r["launches"][1], 1),
+                "fp64": r["backup_ms"][0] / max(r["launches"][0], 1)},
+        }
     out = {
         "metric": METRIC,
         "value": value,
@@ -652,24 +728,10 @@ def main():
         },
         "latency_ms": {"p50": percentile(main_run["lat_ms"], 0.5),
                        "p99": percentile(main_run["lat_ms"], 0.99)},
-        "fp64_plain": {
-            "value": fp64_run["logical"] / fp64_run["wall_s"],
-            "ms_per_solve": percentile(fp64_run["lat_ms"], 0.5),
-            "sweeps": fp64_run["sweeps_fp64"] + 1,
-            "avg_backup_kernel_ms": fp64_run["backup_ms"][0] / max(fp64_run["launches"][0], 1),
-            "latency_ms": {"p50": percentile(fp64_run["lat_ms"], 0.5),
-                           "p99": percentile(fp64_run["lat_ms"], 0.99)},
-        },
-        "fp32_schedule": {
-            "mode": args.precision if args.precision != "fp64" else "fp32_wide",
-            "value": fp32_run["logical"] / fp32_run["wall_s"],
-            "ms_per_solve": percentile(fp32_run["lat_ms"], 0.5),
-            "sweeps": {"fp32": fp32_run["sweeps_fp32"], "fp64": fp32_run["sweeps_fp64"],
-                       "extract": 1},
-            "avg_backup_kernel_ms": {
-                "fp32_storage": fp32_run["backup_ms"][1] / max(fp32_run["launches"][1], 1),
-                "fp64_polish": fp32_run["backup_ms"][0] / max(fp32_run["launches"][0], 1)},
-        },
+        "fp64_plain": schedule("fp64"),
+        "fp32_compensated": schedule("fp32"),
+        "fp32_fp64_sums": schedule("fp32_wide"),
+        "cold_calls": cold,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved_gbs,
@@ -681,8 +743,14 @@ def main():
             "kernel": "backup_a_kernel<" + ("double" if dom == 0 else "float") + ">",
             "launches_timed": launches,
             "avg_kernel_ms": avg_kernel_s * 1e3,
-            "basis": f"{bytes_per_backup} B of V per logical backup x {per_launch_logical} "
-                     f"logical backups per launch",
+            "basis": f"{state_bytes} B per state per sweep (read V, write V') x "
+                     f"{m.n_states} states per launch",
+        },
+        "roofline_logical_gathers": {
+            "achieved": logical_gbs, "unit": "GB/s", "frac_of_hbm_peak": logical_gbs / HBM_PEAK_GBS,
+            "basis": f"{8 if dom == 0 else 4} B of V per logical backup x {per_launch_logical} "
+                     "logical backups per launch (above 1: the gathers are served from "
+                     "LDS, L2 and the Infinity Cache, not HBM)",
         },
         "roofline_executed": {
             "bound": "alu",
@@ -692,6 +760,7 @@ def main():
             "frac": fma_tflops / FP64_VECTOR_PEAK_TFLOPS,
             "basis": f"2 flops per executed multiply-add, {executed_per_launch:.4g} per launch",
         },
+        "fp32_error_vs_fp64": None if args.no_errors else fp32_errors(pvi, W),
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(sc, args.cpu_seconds),
     }
     print(json.dumps(out), flush=True)
