@@ -118,6 +118,15 @@ __device__ __forceinline__ void wave_sync() {
 // the same RMAX-wide rows but keep running sums only for the R real actions, which
 // frees registers and skips the padded multiply-adds; the maxima are over the same
 // actions, so their results are identical.
+// Elements between the staged chunks of two tiles of a wavefront: CH * RMAX, padded
+// so that consecutive tiles' rows start 4 banks apart (a stride of 4 dwords modulo
+// 64); the tiles' 16-byte row reads then never share a bank.
+template <typename VT>
+__host__ __device__ constexpr int tile_stride(int ch, int rmax) {
+    const int e = ch * rmax;
+    return sizeof(VT) == 8 ? e + ((2 - e) % 32 + 32) % 32 : e + ((4 - e) % 64 + 64) % 64;
+}
+
 template <typename VT>
 __device__ constexpr VT kPadValue = VT(-1e30);
 template <>
@@ -195,19 +204,35 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
         s_base = (int64_t)(st / p.nz) * p.stride_h;
     }
 
-    VT* buf = reinterpret_cast<VT*>(smem);  // [2][G][CH][RMAX]
-    // RMAX is a multiple of 8, so every staged row starts on a 32-byte boundary
-    double* sP = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)2 * npair * RMAX);
-    double* sF = sP + p.tab;
+    // [2][G][TS] with TS >= CH * RMAX: chunk c & 1, tile slot, point-major rows of RMAX
+    const int TS = tile_stride<VT>(CH, RMAX);
+    VT* buf = reinterpret_cast<VT*>(smem);
+    // RMAX and TS are multiples of 2 doubles or 4 floats, so every staged row starts on
+    // a 16-byte boundary
+    // weight tables (premultiplied by gamma): F and G indexed by d; and, walked upwards
+    // as N grows, the reversed tables Pr[j] = P(k) and Dr[j] = P(k + R) - P(k) at
+    // k = tab - 1 - j, with P(k) read as 0 for k <= 0 and k >= tab (d = 0 never enters
+    // a running sum, and the PMF is zero beyond d_max): a lane's weights at point N are
+    // Pr and Dr at (tab - 1 - u1) + N, with no bound checks
+    const int TW = p.tab + R;
+    double* sF = reinterpret_cast<double*>(smem + sizeof(VT) * (size_t)2 * G * TS);
     double* sG = sF + p.tab;
-    int* soff = reinterpret_cast<int*>(sG + p.tab);  // [G][lpm] block offset of each point
+    double* sPr = sG + p.tab;
+    double* sDr = sPr + TW;
+    int* soff = reinterpret_cast<int*>(sDr + TW);  // [G][lpm] block offset of each point
     const VT* vin = reinterpret_cast<const VT*>(p.v_in);
 
     const double gm = p.gamma;
     for (int i = lane; i < p.tab; i += 64) {
-        sP[i] = gm * p.pmf[i];
         sF[i] = gm * p.cdf[i];
         sG[i] = gm * p.tail[i];
+    }
+    for (int j = lane; j < TW; j += 64) {
+        const int k = p.tab - 1 - j, k2 = k + R;
+        const double pk = k >= 1 ? gm * p.pmf[k] : 0.0;
+        const double pk2 = (k2 >= 1 && k2 < p.tab) ? gm * p.pmf[k2] : 0.0;
+        sPr[j] = pk;
+        sDr[j] = pk2 - pk;
     }
     for (int i = lane; i < G * lp; i += 64) {
         const int gg = i / lp, j = i - gg * lp;
@@ -233,7 +258,7 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
     };
     auto store_chunk = [&](int c) {
         if (stager && c * CH + sj < lp) {
-            VV* dst = reinterpret_cast<VV*>(buf + ((size_t)((c & 1) * G + sg) * CH + sj) * RMAX +
+            VV* dst = reinterpret_cast<VV*>(buf + (size_t)((c & 1) * G + sg) * TS + sj * RMAX +
                                             sh * SPL);
             VT v[SPL];
 #pragma unroll
@@ -257,9 +282,8 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
 
     // r0n and vold are the state's reward-table entry and its current value,
     // loaded ahead of time by the caller
-    auto finish = [&](int X2, int X1, double best, double second, int arg, double r0n,
+    auto finish = [&](uint32_t s_idx, double best, double second, int arg, double r0n,
                       double vold) {
-        const int64_t s_idx = tbase + X2 * R + X1;
         if (EXTRACT) {
             p.pi[s_idx] = arg;
             p.gap[s_idx] = R > 1 ? best - second : INFINITY;
@@ -269,8 +293,10 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
             const double out = (double)o, dv = out - vold;
             dmx = fmax(dmx, dv);
             dmn = fmin(dmn, dv);
-            vmx = fmax(vmx, out);
-            vmn = fmin(vmn, out);
+            if constexpr (sizeof(VT) == 4) {  // the FP32 centring needs the value range
+                vmx = fmax(vmx, out);
+                vmn = fmin(vmn, out);
+            }
         }
     };
     auto take = [&](double qv, int a, double& best, double& second, int& arg) {
@@ -283,7 +309,7 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
         }
     };
 
-    const VV* row0 = reinterpret_cast<const VV*>(buf + (size_t)g * CH * RMAX);
+    const VV* row0 = reinterpret_cast<const VV*>(buf + (size_t)g * TS);
     // N = 0 (only when b = 0): nothing left to deplete, every demand lands on S[0]
     if (b == 0) {
         double r0n = 0.0, vold = 0.0;
@@ -307,7 +333,7 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
                     best = fmax(best, qv);
             }
         }
-        finish(0, l, best, second, arg, r0n, vold);
+        finish((uint32_t)tbase + l, best, second, arg, r0n, vold);
     }
 
     const int n0 = b > 1 ? b : 1, nmax = lp - 1;
@@ -335,21 +361,6 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
         }
     }
 
-    // the state emitted at step N: X_1 = u1 - N while u1 >= N, else u2 - N.  Its
-    // reward-table entry and old value (a read of V that may go to HBM) are fetched
-    // three steps ahead into one of three register slots; the loop is unrolled by
-    // three so each slot is used and then refilled in place, without register moves
-    // that would force the loads to complete early.
-    constexpr int PD = 3;
-    auto prefetch = [&](int N, double& r0s, double& vs) {
-        if constexpr (!EXTRACT) {
-            // steps outside [n0, nmax] emit nothing: clamp to an in-range state
-            const int X1 = min(max((u1 >= N ? u1 : u2) - N, 0), R - 1);
-            const int X2 = min(max(N - b, 0), p.r2 - 1);
-            r0s = p.r0[X1 * p.xt + X1 + X2 + b];
-            vs = (double)vin[tbase + X2 * R + X1];
-        }
-    };
     int c = 0, cj = 0;  // chunk of the current point and position inside it
     // moves to the next point; on entering chunk c + 1 publishes it and starts
     // loading chunk c + 2
@@ -365,17 +376,14 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
         }
     };
     auto point = [&]() {
-        return reinterpret_cast<const VV*>(buf + ((size_t)((c & 1) * G + g) * CH + cj) * RMAX);
+        return reinterpret_cast<const VV*>(buf + (size_t)((c & 1) * G + g) * TS + cj * RMAX);
     };
-    // weights of point N for the two running sums: P(u - N) for u - N >= 1 (the
-    // table is zero past d_max); a finished diagonal (u - N <= 0) adds nothing
+    // weights of point N for the two running sums, P(u1 - N) and P(u2 - N) - P(u1 - N)
+    // (a diagonal with u - N <= 0 is finished and adds nothing)
+    const int wbase = p.tab - 1 - u1;
     auto weights = [&](int N, AW& w1, AW& wd) {
-        const int d1 = u1 - N, d2 = u2 - N;
-        const double pw1 = sP[min(max(d1, 0), p.tab - 1)];
-        const double pw2 = sP[min(max(d2, 0), p.tab - 1)];
-        const double w1d = d1 >= 1 ? pw1 : 0.0;
-        w1 = (AW)w1d;
-        wd = (AW)((d2 >= 1 ? pw2 : 0.0) - w1d);
+        w1 = (AW)sPr[wbase + N];
+        wd = (AW)sDr[wbase + N];
     };
 
     // points 1 .. n0 - 1 precede every state of the group: running sums only
@@ -397,6 +405,42 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
         }
     }
 
+    // The state a lane emits at point N >= n0 has X_2 = N - b and X_1 = u1 - N while
+    // N <= u1, then u2 - N: X_1 steps down by one and wraps once, from 0 to R - 1.  Its
+    // index tbase + X_2 R + X_1 then grows by R - 1, or 2R - 1 at the wrap, and its
+    // reward-table index X_1 (xt + 1) + N by 1 - (xt + 1) or 1 + (R - 1)(xt + 1).  The
+    // reward entry and old value of the state PD points ahead are loaded into one of
+    // PD register slots (the loop is unrolled by PD, so each slot is used and then
+    // refilled in place, with no register move that would force the load to complete
+    // early); past the last point the loads read the tile's first state instead.
+    constexpr int PD = 3;
+    struct Walk {
+        int x;         // X_1
+        uint32_t s;    // state index
+        uint32_t r;    // reward-table index
+    };
+    const int xt1 = p.xt + 1;
+    // next point: the wrap adds R to X_1 (unsigned minimum of x - 1 and x - 1 + R)
+    auto step_walk = [&](Walk& w) {
+        const uint32_t t = (uint32_t)(w.x - 1), tw = (uint32_t)(w.x - 1 + R);
+        const uint32_t x = min(t, tw);
+        const uint32_t d = x - t;  // R at the wrap, else 0
+        w.x = (int)x;
+        w.s += (uint32_t)(R - 1) + d;
+        w.r = w.r + 1u - (uint32_t)xt1 + d * (uint32_t)xt1;
+    };
+    const uint32_t tb = (uint32_t)tbase;
+    Walk cur{l, tb + (uint32_t)((n0 - b) * R + l), (uint32_t)(l * xt1 + n0)};
+    Walk ahd = cur;
+    auto prefetch = [&](int N, double& r0s, double& vs) {
+        if constexpr (!EXTRACT) {
+            const bool live = N <= nmax;  // the same for every lane
+            r0s = p.r0[live ? ahd.r : 0u];
+            vs = (double)vin[live ? ahd.s : tb];
+            step_walk(ahd);
+        }
+    };
+
     // points n0 .. nmax: every lane emits one state per point.  Each pair (or
     // quad) of actions of the point is read, used for the state and both sums,
     // and dropped, so the row is never held whole.  The sums are also advanced
@@ -406,14 +450,13 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
         const VV* rN = point();
         AW w1, wd;
         weights(N, w1, wd);
-        const bool on2 = u1 < N;
-        const int X1 = (on2 ? u2 : u1) - N;
-        const double fwr = sF[min(max(X1, 0), p.dmax)];
-        // Q_a = gamma (F(X_1) S[N][a] + C(u, N) + G(u) S[0][a]) - c_var a
-        const double msel = on2 ? 1.0 : 0.0;
+        const double fwr = sF[min(cur.x, p.dmax)];
+        // Q_a = gamma (F(X_1) S[N][a] + C(u, N) + G(u) S[0][a]) - c_var a, with
+        // C(u, N) = A1 + D once the lane is on its second diagonal
+        const double msel = u1 < N ? 1.0 : 0.0;
         double best = -DBL_MAX, second = -DBL_MAX;
         int arg = 0;
-        double bq[4] = {-DBL_MAX, -DBL_MAX, -DBL_MAX, -DBL_MAX};
+        double bq[4];
 #pragma unroll
         for (int q = 0; q < (RC + W - 1) / W; ++q) {
             const VV sq = rN[q];
@@ -428,14 +471,18 @@ __device__ __forceinline__ void backup_a_body(ADev p, unsigned char* smem) {
                     take(fma(fwr, sv, run), a, best, second, arg);
                 } else {
                     const double qv = KAHAN ? fma(fwr, sv, run) - cv * a : fma(fwr, sv, run);
-                    bq[a & 3] = fmax(bq[a & 3], qv);
+                    bq[a & 3] = a < 4 ? qv : fmax(bq[a & 3], qv);
                 }
                 A1[a].add(w1, svt);
                 D[a].add(wd, svt);
             }
         }
-        if (!EXTRACT) best = fmax(fmax(bq[0], bq[1]), fmax(bq[2], bq[3]));
-        finish(N - b, X1, best, second, arg, r0s, vs);
+        if (!EXTRACT) {
+            static_assert(RC >= 4, "the partial maxima need four actions");
+            best = fmax(fmax(bq[0], bq[1]), fmax(bq[2], bq[3]));
+        }
+        finish(cur.s, best, second, arg, r0s, vs);
+        step_walk(cur);
         prefetch(N + PD, r0s, vs);  // the slot is consumed: refill it for step N + PD
     };
     double ra = 0.0, va = 0.0, rb = 0.0, vb = 0.0, rc = 0.0, vc = 0.0;
@@ -525,8 +572,9 @@ static hipError_t launch_a_r(const ADev& p, hipStream_t s) {
     if (p.G < 1 || p.G * p.R > 64 || p.CH < 1 || (RMAX / 8) * p.G * p.CH > 64 ||
         p.ngroups < 1)
         return hipErrorInvalidConfiguration;
-    size_t bytes = sizeof(VT) * (size_t)2 * p.G * p.CH * RMAX;
-    bytes += sizeof(double) * 3 * (size_t)p.tab + sizeof(int) * (size_t)p.G * lp_max;
+    size_t bytes = sizeof(VT) * (size_t)2 * p.G * tile_stride<VT>(p.CH, RMAX);
+    bytes += sizeof(double) * (2 * (size_t)p.tab + 2 * ((size_t)p.tab + p.R)) +
+             sizeof(int) * (size_t)p.G * lp_max;
     if (bytes > 65536) return hipErrorInvalidConfiguration;
     // G is read at u2 <= b + 2R and P, F at clamped indices
     if (p.tab < 2 * p.R + lp_max + 1 || p.tab < p.dmax + 2) return hipErrorInvalidValue;
