@@ -308,7 +308,13 @@ pvi_status policy_get_device(const pvi_mdp* mdp, int32_t* d_policy, void* stream
 
 /* Request server: solves of many MDPs of different sizes, admitted by free HBM
  * within hbm_budget_bytes (0 = 80% of free device memory).  Small scenario-A
- * instances are batched, up to small_batch per persistent launch.  Each ticket's
+ * instances (FIFO, span rule, no v0, both value tables within 60 KB of LDS) go to a
+ * persistent slot kernel with small_batch slots (at most as many work groups as stay
+ * resident): one work group per slot solves one instance at a time, and a request
+ * that arrives while the kernel runs takes the next free slot of that launch
+ * (continuous refill).  A launch with no busy slot for 2 ms is stopped (set
+ * PVI_SLOT_IDLE_MS in the environment at pvi_server_create to change it); the next
+ * small request starts another.  Each ticket's
  * results stay in its pvi_mdp handle, which the caller keeps alive until the
  * ticket completes.  A handle that had no device state when its request started
  * gets its results in host memory and its device buffers freed once the solve
@@ -334,7 +340,8 @@ typedef struct pvi_ticket_info {
     int32_t worker;       /* server worker that took it; -1 while queued */
     int32_t sweeps;       /* sweep-loop requests: sweeps completed at the last host check */
     int32_t status;       /* pvi_status once done, else PVI_E_NOT_READY */
-    int32_t reserved;
+    int32_t launch;       /* small requests: number of the slot-kernel launch that serves
+                             it (1 = the server's first); 0 for sweep-loop requests */
     int64_t bytes;        /* device bytes a sweep-loop request holds while it runs */
     double t_submit_ms, t_start_ms, t_done_ms;
 } pvi_ticket_info;

@@ -1,15 +1,15 @@
-// Batched value iteration of many small scenario-A instances in one launch.
+// Value iteration of small scenario-A instances, one work group per instance, served
+// by a persistent slot kernel that the host refills while it runs.
 //
-// One workgroup solves one instance completely: both value tables live in LDS,
-// the workgroup sweeps (deterministic-transition update of Methods, "Value
-// iteration"; T from Appendix A), reduces max/min of V_new - V itself, applies
-// the span stopping rule, and finally extracts the greedy policy with one more
-// FP64 backup.  The FP32 schedule keeps V in LDS as centred FP32 (V = c + v)
-// until the span reaches the FP32 floor, then converts to FP64 and polishes to
-// the threshold.  Every instance has its own sizes, costs and tables, so a batch
-// may mix instances; each workgroup's arithmetic depends only on its own instance,
-// which makes results independent of the batch they ran in.  The sweep loop is
-// bounded by max_sweeps, so every workgroup exits.
+// One work group solves one instance completely (solve_item): both value tables live
+// in LDS, the work group sweeps (deterministic-transition update of Methods, "Value
+// iteration"; T from Appendix A), reduces max/min of V_new - V itself, applies the
+// span stopping rule, and finally extracts the greedy policy with one more FP64
+// backup.  The FP32 schedule keeps V in LDS as centred FP32 (V = c + v) until the
+// span reaches the FP32 floor, then converts to FP64 and polishes to the threshold.
+// Every instance has its own sizes, costs and tables; each work group's arithmetic
+// depends only on its own instance, which makes results independent of what else
+// runs.  The sweep loop is bounded by max_sweeps, so every solve ends.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -17,6 +17,7 @@
 
 #include "device_common.h"
 #include "pvi_internal.h"
+#include "slot_layout.h"
 
 namespace pvi {
 
@@ -108,12 +109,12 @@ __device__ void batch_sweep(const BatchItem& it, const VT* src, VT* dst, const d
     __syncthreads();
 }
 
+// The whole solve of one instance by one work group (256 threads): tables into LDS,
+// the FP32 phase (FP32 schedule), the FP64 phase, the extraction, results to it.v,
+// it.pi, it.gap, it.stats.
 template <int RMAX>
-__global__ __launch_bounds__(256) void batch_solve_kernel(const BatchItem* items) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[64];
-    __shared__ BatchShared sh;
-    const BatchItem it = items[blockIdx.x];
+__device__ void solve_item(const BatchItem& it, unsigned char* smem, double* red,
+                           BatchShared& sh) {
     double* V0 = reinterpret_cast<double*>(smem);
     double* V1 = V0 + it.ns;
     double* sP = V1 + it.ns;
@@ -223,19 +224,94 @@ __global__ __launch_bounds__(256) void batch_solve_kernel(const BatchItem* items
     }
 }
 
-hipError_t launch_batch(const BatchItem* d_items, int n, size_t lds_bytes, int rmax,
-                        hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    if (lds_bytes > 65536) return hipErrorInvalidConfiguration;
-    if (rmax <= 8)
-        hipLaunchKernelGGL((batch_solve_kernel<8>), dim3(n), dim3(256), lds_bytes, s, d_items);
-    else if (rmax <= 16)
-        hipLaunchKernelGGL((batch_solve_kernel<16>), dim3(n), dim3(256), lds_bytes, s, d_items);
-    else if (rmax <= 24)
-        hipLaunchKernelGGL((batch_solve_kernel<24>), dim3(n), dim3(256), lds_bytes, s, d_items);
-    else
-        return hipErrorInvalidValue;
+// The slot kernel: work group k serves slot k of the table for as long as the host
+// keeps it alive.  It waits for the slot's request number to move past the last one
+// it served, copies the request's descriptor into LDS with system-coherent loads (the
+// host rewrites the slot for every request, so nothing of it may come from a cache),
+// solves it with solve_item, makes its results visible to the host and then publishes
+// the request number as done.  It returns when the host sets the stop word, or when
+// the heartbeat word has not changed for kSlotIdlePolls polls (a host that stopped
+// serving), so every work group ends.  The poll interval backs off from about 3 us to
+// about 27 us while the slot is idle.
+__device__ __forceinline__ uint32_t load_sys(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <int RMAX>
+__global__ __launch_bounds__(256) void slot_kernel(SlotHeader* hdr, SlotSync* sync,
+                                                   const BatchItem* items) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[64];
+    __shared__ BatchShared sh;
+    __shared__ uint32_t s_item[(sizeof(BatchItem) + 3) / 4];
+    __shared__ uint32_t s_seq;
+    __shared__ int s_exit;
+    const int k = blockIdx.x;
+    uint32_t last = 0;
+    if (threadIdx.x == 0) last = load_sys(&sync[k].done);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            uint32_t hb_seen = load_sys(&hdr->heartbeat), still = 0, s = last;
+            int nap = 1, ex = 0;
+            for (;;) {
+                if (load_sys(&hdr->stop)) {
+                    ex = 1;
+                    break;
+                }
+                s = load_sys(&sync[k].seq);
+                if (s != last) break;
+                const uint32_t hb = load_sys(&hdr->heartbeat);
+                if (hb != hb_seen) {
+                    hb_seen = hb;
+                    still = 0;
+                } else if (++still > kSlotIdlePolls) {
+                    ex = 1;
+                    break;
+                }
+                for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(127);
+                nap = nap < 8 ? 2 * nap : 8;
+            }
+            s_exit = ex;
+            s_seq = s;
+        }
+        __syncthreads();
+        if (s_exit) return;
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(items + k);
+        for (int i = threadIdx.x; i < (int)((sizeof(BatchItem) + 3) / 4); i += blockDim.x)
+            s_item[i] = load_sys(src + i);
+        __syncthreads();
+        BatchItem it;
+        __builtin_memcpy(&it, s_item, sizeof(BatchItem));
+        solve_item<RMAX>(it, smem, red, sh);
+        // every thread's result writes reach host memory before the slot is marked done
+        __threadfence_system();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(&sync[k].done, s_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            last = s_seq;
+        }
+    }
+}
+
+hipError_t launch_slots(SlotHeader* hdr, SlotSync* sync, const BatchItem* items, int nslots,
+                        size_t lds_bytes, hipStream_t s) {
+    if (nslots <= 0) return hipSuccess;
+    if (lds_bytes > 65536 - 1024) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((slot_kernel<kSlotRmax>), dim3(nslots), dim3(256), lds_bytes, s, hdr, sync,
+                       items);
     return hipGetLastError();
+}
+
+int slot_capacity(size_t lds_bytes) {
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(&slot_kernel<kSlotRmax>), 256, lds_bytes) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
 }
 
 }  // namespace pvi

@@ -29,6 +29,8 @@
 #include "families.h"
 #include "mdp.h"
 #include "server_core.h"
+#include "slot_layout.h"
+#include "slots.h"
 
 namespace {
 
@@ -49,18 +51,25 @@ size_t small_lds_bytes(const pvi_mdp* p) {
     return sizeof(double) * (2 * (size_t)p->ns + 3 * (size_t)p->tab + p->a_r0.size());
 }
 
-// The batched kernel runs FIFO scenario A under the span rule; everything else
-// takes the sweep loop.
+// The slot kernel runs FIFO scenario A under the span rule; everything else takes the
+// sweep loop.
+size_t slot_need(const pvi_mdp* p);
+
 bool is_small(const pvi_mdp* p, const pvi_solve_opts& o) {
     return p->family == PVI_FAMILY_LEADTIME && p->d.issuing == PVI_FIFO &&
-           o.stop_rule == PVI_STOP_SPAN && o.v0 == nullptr && p->rad[0] <= 24 &&
-           small_lds_bytes(p) <= kSmallMaxLds;
+           o.stop_rule == PVI_STOP_SPAN && o.v0 == nullptr && p->rad[0] <= pvi::kSlotRmax &&
+           small_lds_bytes(p) <= kSmallMaxLds && slot_need(p) <= (size_t(96) << 10);
 }
 
 }  // namespace
 
+namespace {
+struct HipSlotOps;
+}  // namespace
+
 struct pvi_server {
     std::unique_ptr<pvi::srv::Core> core;
+    std::unique_ptr<HipSlotOps> slots;  // the small-instance slot kernel (null: none)
     int small_batch = 256;
     int device = 0;
     std::vector<std::thread> workers;
@@ -103,168 +112,169 @@ void large_worker(pvi_server* S, int w) {
     if (have_stream) (void)hipStreamDestroy(stream);
 }
 
-// Device arena of one batch worker: items, per-instance tables and outputs.
-struct Arena {
-    size_t bytes = 0;
-    char* d = nullptr;
-    char* h = nullptr;  // pinned staging copy
+// Device side of the slot feeder: the slot table, one request arena per slot and the
+// launches of the slot kernel, all in one block of coherent pinned host memory that
+// the kernel reads and writes directly (the host never copies through the device).
+// Per slot the arena holds the request's tables (P, F, G, reward), then its results
+// (V, Q gap, 8 statistics, policy).
+constexpr size_t kSlotArena = size_t(96) << 10;
+
+size_t slot_need(const pvi_mdp* p) {
+    return sizeof(double) * (3 * (size_t)p->tab + p->a_r0.size() + 2 * (size_t)p->ns + 8) +
+           sizeof(int32_t) * (size_t)p->ns;
+}
+
+struct HipSlotOps : pvi::srv::SlotOps {
+    int nslots = 0;
+    size_t lds = 0;
+    char* host = nullptr;   // the block (host address)
+    char* dev = nullptr;    // the same block (device address)
+    pvi::SlotHeader* hdr = nullptr;
+    pvi::SlotSync* sync = nullptr;
+    pvi::BatchItem* items = nullptr;
+    size_t arena0 = 0;      // offset of slot 0's arena
+    hipStream_t stream = nullptr;
+    hipEvent_t done_ev = nullptr;
+    bool launched = false;
+
+    template <class T>
+    T* dptr(T* h) const {
+        return reinterpret_cast<T*>(dev + (reinterpret_cast<char*>(h) - host));
+    }
+    char* arena(int k) const { return host + arena0 + (size_t)k * kSlotArena; }
+
+    bool init(int n) {
+        nslots = n;
+        lds = kSmallMaxLds;
+        const size_t items_off = sizeof(pvi::SlotHeader) + sizeof(pvi::SlotSync) * (size_t)n;
+        arena0 = (items_off + sizeof(pvi::BatchItem) * (size_t)n + 255) & ~size_t(255);
+        const size_t bytes = arena0 + kSlotArena * (size_t)n;
+        if (hipHostMalloc((void**)&host, bytes, hipHostMallocCoherent) != hipSuccess) {
+            host = nullptr;
+            return false;
+        }
+        std::memset(host, 0, bytes);
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, host, 0) != hipSuccess ||
+            hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&done_ev, hipEventDisableTiming) != hipSuccess)
+            return false;
+        dev = static_cast<char*>(d);
+        hdr = reinterpret_cast<pvi::SlotHeader*>(host);
+        sync = reinterpret_cast<pvi::SlotSync*>(host + sizeof(pvi::SlotHeader));
+        items = reinterpret_cast<pvi::BatchItem*>(host + items_off);
+        return true;
+    }
+    ~HipSlotOps() override {
+        if (launched) (void)hipEventSynchronize(done_ev);
+        if (done_ev) (void)hipEventDestroy(done_ev);
+        if (stream) (void)hipStreamDestroy(stream);
+        if (host) (void)hipHostFree(host);
+    }
+
+    void prepare(int k, pvi::srv::Job* j) override {
+        const auto* r = static_cast<Request*>(j);
+        const pvi_mdp* p = r->mdp;
+        char* hb = arena(k);
+        const size_t t = sizeof(double) * p->tab;
+        std::memcpy(hb, p->a_pmf.data(), t);
+        std::memcpy(hb + t, p->a_cdf.data(), t);
+        std::memcpy(hb + 2 * t, p->a_tail.data(), t);
+        std::memcpy(hb + 3 * t, p->a_r0.data(), sizeof(double) * p->a_r0.size());
+        const size_t o_v = 3 * t + sizeof(double) * p->a_r0.size();
+        const size_t o_gap = o_v + sizeof(double) * p->ns;
+        const size_t o_st = o_gap + sizeof(double) * p->ns;
+        const size_t o_pi = o_st + sizeof(double) * 8;
+        pvi::BatchItem it{};
+        it.m = p->m;
+        it.R = p->rad[0];
+        it.dmax = p->dmax[0];
+        it.tab = p->tab;
+        it.xt = p->xt;
+        it.ns = (int)p->ns;
+        int nh = 1;
+        for (int q = 0; q < p->L - 1; ++q) nh *= p->rad[0];
+        it.nh = nh;
+        int sh = 1;
+        for (int q = 0; q < p->m - 1; ++q) sh *= p->rad[0];
+        it.stride_h = sh;
+        it.stride_a = sh * nh;
+        it.max_sweeps = r->opts.max_sweeps > 0 ? r->opts.max_sweeps : r->opts.fixed_sweeps;
+        it.fixed = r->opts.fixed_sweeps;
+        it.fp32 = r->opts.precision != PVI_FP64;
+        it.gamma = p->d.gamma;
+        it.cvar = p->d.c_var[0];
+        it.thr = r->opts.eps * (1.0 - p->d.gamma) / p->d.gamma;
+        auto* dd = reinterpret_cast<double*>(dptr(hb));
+        it.pmf = dd;
+        it.cdf = dd + p->tab;
+        it.tail = dd + 2 * p->tab;
+        it.r0 = dd + 3 * p->tab;
+        it.v = reinterpret_cast<double*>(dptr(hb + o_v));
+        it.gap = reinterpret_cast<double*>(dptr(hb + o_gap));
+        it.stats = reinterpret_cast<double*>(dptr(hb + o_st));
+        it.pi = reinterpret_cast<int32_t*>(dptr(hb + o_pi));
+        items[k] = it;
+    }
+
+    int collect(int k, pvi::srv::Job* j) override {
+        auto* r = static_cast<Request*>(j);
+        pvi_mdp* p = r->mdp;
+        const char* hb = arena(k);
+        const size_t t = sizeof(double) * p->tab;
+        const size_t o_v = 3 * t + sizeof(double) * p->a_r0.size();
+        const size_t o_gap = o_v + sizeof(double) * p->ns;
+        const size_t o_st = o_gap + sizeof(double) * p->ns;
+        const size_t o_pi = o_st + sizeof(double) * 8;
+        const double* stt = reinterpret_cast<const double*>(hb + o_st);
+        {
+            std::lock_guard<std::mutex> lk(p->mu);
+            p->h_v.assign(reinterpret_cast<const double*>(hb + o_v),
+                          reinterpret_cast<const double*>(hb + o_v) + p->ns);
+            p->h_gap.assign(reinterpret_cast<const double*>(hb + o_gap),
+                            reinterpret_cast<const double*>(hb + o_gap) + p->ns);
+            p->h_pi.assign(reinterpret_cast<const int32_t*>(hb + o_pi),
+                           reinterpret_cast<const int32_t*>(hb + o_pi) + p->ns);
+            p->have_result = 2;
+        }
+        pvi_result& res = r->res;
+        std::memset(&res, 0, sizeof(res));
+        res.sweeps_fp32 = (int32_t)stt[0];
+        res.sweeps_fp64 = (int32_t)stt[1];
+        res.final_span = stt[2];
+        res.dmax = stt[3];
+        res.dmin = stt[4];
+        res.threshold = r->opts.eps * (1.0 - p->d.gamma) / p->d.gamma;
+        const int64_t sw = res.sweeps_fp32 + res.sweeps_fp64 + 1;
+        res.logical_backups = p->logical_per_sweep * sw;
+        res.executed_terms = p->executed_per_sweep * sw;
+        res.status = stt[5] == 0.0 ? PVI_OK : PVI_E_NOT_CONVERGED;
+        return res.status;
+    }
+
+    bool launch() override {
+        if (pvi::launch_slots(dptr(hdr), dptr(sync), dptr(items), nslots, lds, stream) !=
+                hipSuccess ||
+            hipEventRecord(done_ev, stream) != hipSuccess)
+            return false;
+        launched = true;
+        return true;
+    }
+    bool finished() override { return !launched || hipEventQuery(done_ev) == hipSuccess; }
+    void wait() override {
+        if (launched) (void)hipEventSynchronize(done_ev);
+    }
 };
 
-void small_worker(pvi_server* S, int w) {
+void slot_feeder(pvi_server* S) {
     (void)hipSetDevice(S->device);
-    hipStream_t stream;
-    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return;
-    Arena ar;
-    // take the arena up front so the first batch does not pay for allocation
-    {
-        const size_t want = size_t(32) << 20;
-        if (hipMalloc((void**)&ar.d, want) == hipSuccess &&
-            hipHostMalloc((void**)&ar.h, want, hipHostMallocDefault) == hipSuccess) {
-            ar.bytes = want;
-        } else {
-            if (ar.d) (void)hipFree(ar.d);
-            if (ar.h) (void)hipHostFree(ar.h);
-            ar = Arena{};
-        }
-    }
-    std::vector<Job*> jobs;
-    for (;;) {
-        if (S->core->next_small(w, S->small_batch, -1, jobs) == 0) {
-            if (S->core->stopping()) break;
-            continue;
-        }
-        std::vector<Request*> batch;
-        for (Job* j : jobs) batch.push_back(static_cast<Request*>(j));
-        // layout: items | per instance: tables, V, gap, policy, stats (8-byte aligned)
-        const int n = (int)batch.size();
-        size_t off = sizeof(pvi::BatchItem) * n;
-        off = (off + 255) & ~size_t(255);
-        std::vector<size_t> base(n);
-        size_t lds = 0;
-        int rmax = 1;
-        for (int i = 0; i < n; ++i) {
-            const pvi_mdp* p = batch[i]->mdp;
-            base[i] = off;
-            off += sizeof(double) * (3 * (size_t)p->tab + p->a_r0.size());
-            off += sizeof(double) * (2 * (size_t)p->ns + 8) + sizeof(int32_t) * p->ns;
-            off = (off + 15) & ~size_t(15);
-            lds = std::max(lds, small_lds_bytes(p));
-            rmax = std::max(rmax, p->rad[0]);
-        }
-        pvi_status st = PVI_OK;
-        if (off > ar.bytes) {
-            if (ar.d) (void)hipFree(ar.d);
-            if (ar.h) (void)hipHostFree(ar.h);
-            ar = Arena{};
-            const size_t want = std::max(off, size_t(8) << 20);
-            if (hipMalloc((void**)&ar.d, want) != hipSuccess ||
-                hipHostMalloc((void**)&ar.h, want, hipHostMallocDefault) != hipSuccess) {
-                st = PVI_E_NOMEM;
-            } else {
-                ar.bytes = want;
-            }
-        }
-        if (st == PVI_OK) {
-            auto* items = reinterpret_cast<pvi::BatchItem*>(ar.h);
-            for (int i = 0; i < n; ++i) {
-                const Request* r = batch[i];
-                const pvi_mdp* p = r->mdp;
-                char* hb = ar.h + base[i];
-                char* db = ar.d + base[i];
-                const size_t t = sizeof(double) * p->tab;
-                std::memcpy(hb, p->a_pmf.data(), t);
-                std::memcpy(hb + t, p->a_cdf.data(), t);
-                std::memcpy(hb + 2 * t, p->a_tail.data(), t);
-                std::memcpy(hb + 3 * t, p->a_r0.data(), sizeof(double) * p->a_r0.size());
-                const size_t o_v = 3 * t + sizeof(double) * p->a_r0.size();
-                const size_t o_gap = o_v + sizeof(double) * p->ns;
-                const size_t o_st = o_gap + sizeof(double) * p->ns;
-                const size_t o_pi = o_st + sizeof(double) * 8;
-                pvi::BatchItem& it = items[i];
-                it = pvi::BatchItem{};
-                it.m = p->m;
-                it.R = p->rad[0];
-                it.dmax = p->dmax[0];
-                it.tab = p->tab;
-                it.xt = p->xt;
-                it.ns = (int)p->ns;
-                int nh = 1;
-                for (int k = 0; k < p->L - 1; ++k) nh *= p->rad[0];
-                it.nh = nh;
-                int sh = 1;
-                for (int k = 0; k < p->m - 1; ++k) sh *= p->rad[0];
-                it.stride_h = sh;
-                it.stride_a = sh * nh;
-                it.max_sweeps = r->opts.max_sweeps > 0 ? r->opts.max_sweeps : r->opts.fixed_sweeps;
-                it.fixed = r->opts.fixed_sweeps;
-                it.fp32 = r->opts.precision != PVI_FP64;
-                it.gamma = p->d.gamma;
-                it.cvar = p->d.c_var[0];
-                it.thr = r->opts.eps * (1.0 - p->d.gamma) / p->d.gamma;
-                auto* dd = reinterpret_cast<double*>(db);
-                it.pmf = dd;
-                it.cdf = dd + p->tab;
-                it.tail = dd + 2 * p->tab;
-                it.r0 = dd + 3 * p->tab;
-                it.v = reinterpret_cast<double*>(db + o_v);
-                it.gap = reinterpret_cast<double*>(db + o_gap);
-                it.stats = reinterpret_cast<double*>(db + o_st);
-                it.pi = reinterpret_cast<int32_t*>(db + o_pi);
-            }
-            const auto t0 = clk::now();
-            if (hipMemcpyAsync(ar.d, ar.h, off, hipMemcpyHostToDevice, stream) != hipSuccess ||
-                pvi::launch_batch(reinterpret_cast<pvi::BatchItem*>(ar.d), n, lds, rmax,
-                                  stream) != hipSuccess ||
-                hipMemcpyAsync(ar.h, ar.d, off, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-                hipStreamSynchronize(stream) != hipSuccess)
-                st = PVI_E_DEVICE;
-            const double dev_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
-            if (st == PVI_OK) {
-                for (int i = 0; i < n; ++i) {
-                    Request* r = batch[i];
-                    pvi_mdp* p = r->mdp;
-                    const char* hb = ar.h + base[i];
-                    const size_t t = sizeof(double) * p->tab;
-                    const size_t o_v = 3 * t + sizeof(double) * p->a_r0.size();
-                    const size_t o_gap = o_v + sizeof(double) * p->ns;
-                    const size_t o_st = o_gap + sizeof(double) * p->ns;
-                    const size_t o_pi = o_st + sizeof(double) * 8;
-                    const double* stt = reinterpret_cast<const double*>(hb + o_st);
-                    {
-                        std::lock_guard<std::mutex> lk(p->mu);
-                        p->h_v.assign(reinterpret_cast<const double*>(hb + o_v),
-                                      reinterpret_cast<const double*>(hb + o_v) + p->ns);
-                        p->h_gap.assign(reinterpret_cast<const double*>(hb + o_gap),
-                                        reinterpret_cast<const double*>(hb + o_gap) + p->ns);
-                        p->h_pi.assign(reinterpret_cast<const int32_t*>(hb + o_pi),
-                                       reinterpret_cast<const int32_t*>(hb + o_pi) + p->ns);
-                        p->have_result = 2;
-                    }
-                    pvi_result& res = r->res;
-                    std::memset(&res, 0, sizeof(res));
-                    res.sweeps_fp32 = (int32_t)stt[0];
-                    res.sweeps_fp64 = (int32_t)stt[1];
-                    res.final_span = stt[2];
-                    res.dmax = stt[3];
-                    res.dmin = stt[4];
-                    res.threshold = r->opts.eps * (1.0 - p->d.gamma) / p->d.gamma;
-                    res.backup_ms[1] = dev_ms;  // the batch launch this request ran in
-                    const int64_t sw = res.sweeps_fp32 + res.sweeps_fp64 + 1;
-                    res.logical_backups = p->logical_per_sweep * sw;
-                    res.executed_terms = p->executed_per_sweep * sw;
-                    res.status = stt[5] == 0.0 ? PVI_OK : PVI_E_NOT_CONVERGED;
-                }
-            }
-        }
-        for (Request* r : batch) {
-            const pvi_status rs = st != PVI_OK ? st : (pvi_status)r->res.status;
-            r->res.status = rs;
-            S->core->complete(r, rs);
-        }
-    }
-    if (ar.d) (void)hipFree(ar.d);
-    if (ar.h) (void)hipHostFree(ar.h);
-    (void)hipStreamDestroy(stream);
+    pvi::srv::SlotConfig cfg;
+    cfg.nslots = S->slots->nslots;
+    cfg.worker = 0;
+    cfg.launch_error_status = PVI_E_DEVICE;
+    if (const char* e = std::getenv("PVI_SLOT_IDLE_MS")) cfg.idle_ms = std::max(1, std::atoi(e));
+    pvi::srv::SlotFeeder feeder(*S->core, *S->slots, S->slots->hdr, S->slots->sync, cfg);
+    feeder.run();
 }
 
 }  // namespace
@@ -292,7 +302,18 @@ pvi_status pvi_server_create(int64_t hbm_budget_bytes, int32_t small_batch, pvi_
     S->device = device;
     S->core = std::make_unique<pvi::srv::Core>(cfg);
     S->small_batch = small_batch > 0 ? small_batch : 256;
-    for (int i = 0; i < 2; ++i) S->workers.emplace_back(small_worker, S, i);
+    if (small_batch > 0) {
+        // as many slots as asked for, but no more than stay resident at once: every slot
+        // needs a running work group
+        int cap = pvi::slot_capacity(kSmallMaxLds);
+        if (cap <= 0) cap = 256;
+        S->slots = std::make_unique<HipSlotOps>();
+        if (!S->slots->init(std::min(S->small_batch, cap))) {
+            delete S;
+            return fail(PVI_E_NOMEM, "pvi_server_create: slot table allocation failed");
+        }
+        S->workers.emplace_back(slot_feeder, S);
+    }
     for (int i = 0; i < 2; ++i) S->workers.emplace_back(large_worker, S, 2 + i);
     *out = S;
     return PVI_OK;
@@ -389,6 +410,7 @@ pvi_status vi_ticket_info(pvi_server* S, uint64_t ticket, pvi_ticket_info* out) 
         out->worker = j.worker;
         out->sweeps = q.sweeps.load();
         out->status = j.state == pvi::srv::kDone ? j.status : PVI_E_NOT_READY;
+        out->launch = j.launch.load();
         out->bytes = j.bytes;
         out->t_submit_ms = S->core->ms_since_start(j.t_submit);
         out->t_start_ms = j.state >= pvi::srv::kRunning ? S->core->ms_since_start(j.t_start) : -1.0;

@@ -14,6 +14,7 @@
 // recheck interval instead of relying on a notification alone.
 #pragma once
 
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
@@ -43,6 +44,7 @@ struct Job {
     int state = kQueued;
     int status = 0;           // pvi_status once done
     int worker = -1;          // worker that ran it
+    std::atomic<int> launch{0};  // small: number of the slot-kernel launch serving it
     clk::time_point t_submit, t_start, t_done;
 };
 

@@ -90,7 +90,7 @@ POLICY_PARAMS = 16
 class TicketInfo(ctypes.Structure):
     _fields_ = [
         ("state", ctypes.c_int32), ("small", ctypes.c_int32), ("worker", ctypes.c_int32),
-        ("sweeps", ctypes.c_int32), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32), ("status", ctypes.c_int32), ("launch", ctypes.c_int32),
         ("bytes", ctypes.c_int64), ("t_submit_ms", ctypes.c_double),
         ("t_start_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
     ]
@@ -431,7 +431,8 @@ class Server:
         _check(_lib.vi_ticket_info(self.handle, ctypes.c_uint64(ticket), ctypes.byref(i)),
                "vi_ticket_info")
         return {"state": ("queued", "running", "done")[i.state], "small": bool(i.small),
-                "worker": i.worker, "sweeps": i.sweeps, "status": i.status, "bytes": i.bytes,
+                "worker": i.worker, "sweeps": i.sweeps, "status": i.status, "launch": i.launch,
+                "bytes": i.bytes,
                 "t_submit_ms": i.t_submit_ms, "t_start_ms": i.t_start_ms,
                 "t_done_ms": i.t_done_ms}
 

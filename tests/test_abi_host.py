@@ -269,7 +269,7 @@ def test_checkpoint_options_are_checked_before_the_device(tmp_path):
     assert solve(checkpoint=str(other), resume=True) == pvi.PVI_E_INVALID
     assert "another MDP" in err()
     newer = tmp_path / "newer.ckpt"
-    newer.write_bytes(struct.pack("<8sIIQqiiiiii", b"PVICKPT1", 2, 0, 0, 121, 11, 0, 3, 0, 1, 0))
+    newer.write_bytes(struct.pack("<8sIIQqiiiiii", b"PVICKPT1", 3, 0, 0, 121, 11, 0, 3, 0, 1, 0))
     assert solve(checkpoint=str(newer), resume=True) == pvi.PVI_E_INVALID
     assert "version" in err()
     with pytest.raises(pvi.PviError):

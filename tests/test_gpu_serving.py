@@ -1,10 +1,12 @@
-"""The batched small-instance kernel and the request server, through the C ABI.
+"""The small-instance slot kernel and the request server, through the C ABI.
 
 * Every batched result equals the same instance solved alone by vi_solve and by
   the oracle: FP64 values to 1e-12 relative with the same sweep count, FP32-schedule
   values (bound midpoint) to 1e-5, policies equal where the oracle gap exceeds 1e-6.
-* A result is bit-identical whether its instance ran alone or inside a mixed
-  batch (one workgroup per instance, fixed reduction order).
+* A result is bit-identical whether its instance ran alone or among others (one
+  work group per slot, fixed reduction order).  Requests arriving while the slot
+  kernel runs are served by that launch (continuous refill); an idle launch stops and
+  the next request starts another.
 * Large instances go through the ordinary sweep loop on the server's own streams
   and match vi_solve; a request larger than the budget completes with BUSY.
 """
@@ -176,3 +178,49 @@ def test_ticket_info_and_event_log(tmp_path, monkeypatch):
     for t in (tb, ts):
         ev = [ln.split()[1] for ln in lines if f"ticket={t} " in ln]
         assert ev == ["submit", "start", "done"], ev
+
+
+def test_slots_refill_within_one_launch(monkeypatch):
+    """Continuous refill: 80 small requests through 16 slots are all served by the
+    first launch of the slot kernel (each freed slot takes the next request while the
+    launch runs), including requests submitted one by one while others run; each
+    result is bit-identical to the same instance served alone."""
+    monkeypatch.setenv("PVI_SLOT_IDLE_MS", "5000")
+    scs = small_mix(80, seed=5)
+    s = pvi.Server(small_batch=16)
+    mdps = [pvi.mdp_create(sc) for sc in scs]
+    tickets = s.submit(mdps[:60], precision="fp32")
+    for m in mdps[60:]:
+        tickets += s.submit([m], precision="fp32")
+    for t in tickets:
+        assert s.wait(t, timeout_us=60_000_000)[0] == pvi.PVI_OK
+    launches = {s.ticket_info(t)["launch"] for t in tickets}
+    s.close()
+    assert launches == {1}
+    for i in (0, 37, 61, 79):
+        alone = pvi.Server(small_batch=1)
+        m = pvi.mdp_create(scs[i])
+        (t,) = alone.submit([m], precision="fp32")
+        assert alone.wait(t)[0] == pvi.PVI_OK
+        alone.close()
+        assert np.array_equal(pvi.value_get(m), pvi.value_get(mdps[i]))
+        assert np.array_equal(pvi.policy_get(m)[0], pvi.policy_get(mdps[i])[0])
+
+
+def test_slots_idle_launch_stops_and_restarts(monkeypatch):
+    """A launch with no busy slot for the idle window is stopped; the next request
+    starts a new launch and gets the same result."""
+    monkeypatch.setenv("PVI_SLOT_IDLE_MS", "20")
+    import time
+    sc = W.config0()
+    s = pvi.Server(small_batch=8)
+    m1, m2 = pvi.mdp_create(sc), pvi.mdp_create(sc)
+    (t1,) = s.submit([m1], precision="fp64")
+    assert s.wait(t1)[0] == pvi.PVI_OK
+    time.sleep(0.3)
+    (t2,) = s.submit([m2], precision="fp64")
+    assert s.wait(t2)[0] == pvi.PVI_OK
+    l1, l2 = s.ticket_info(t1)["launch"], s.ticket_info(t2)["launch"]
+    s.close()
+    assert (l1, l2) == (1, 2)
+    assert np.array_equal(pvi.value_get(m1), pvi.value_get(m2))
