@@ -314,10 +314,114 @@ pvi_status tune_c(pvi_mdp* p) {
 }
 }  // namespace
 
+// Tiles per wavefront (G) and path points per staged chunk (CH) of the scenario-A
+// FIFO backup, chosen by timing at the first solve of a shape (R, m, L) in a process
+// and kept for every later handle of that shape.  Candidates: G = floor(64 / R), 2
+// and 1, each with the longest chunk its staging lanes allow and half of it; each is
+// timed over three FP64 sweeps (after one untimed) on this handle's buffers, with
+// the stopping rule off.  PVI_TUNE=0 keeps the rule of build_a_work_list;
+// PVI_A_GROUP and PVI_A_CHUNK fix the choice.  Results do not depend on it.
+namespace {
+std::mutex g_tune_a_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune_a;
+
+pvi_status tune_a(pvi_mdp* p) {
+    const char* env = std::getenv("PVI_TUNE");
+    if ((env && std::strcmp(env, "0") == 0) || std::getenv("PVI_A_GROUP") ||
+        std::getenv("PVI_A_CHUNK") || (p->d.issuing == PVI_LIFO && p->m >= 2))
+        return PVI_OK;
+    const TuneKey key{p->rad[0], p->m, p->L};
+    std::lock_guard<std::mutex> lock(g_tune_a_mu);
+    auto it = g_tune_a.find(key);
+    if (it == g_tune_a.end()) {
+        auto& d = p->dev;
+        std::vector<std::pair<int, int>> cand;
+        const int gmax = a_group_max(p);
+        for (int G : {gmax, std::min(gmax, 2), 1})
+            for (int CH : {a_chunk_max(p, G), std::max(1, a_chunk_max(p, G) / 2)})
+                if (std::find(cand.begin(), cand.end(), std::make_pair(G, CH)) == cand.end())
+                    cand.emplace_back(G, CH);
+        hipStream_t s = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int32_t* groups = nullptr;
+        double* parts = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = launch_fill(d.v64[0], 0.0, p->ns, s);
+        // one fixed-length sweep after another: the stop flag is never set
+        Ctl zero{};
+        if (e == hipSuccess) e = hipMemcpyAsync(d.ctl, &zero, sizeof(Ctl), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        float best = 1e30f;
+        std::pair<int, int> choice{p->a_G, p->a_CH};
+        for (const auto& c : cand) {
+            if (e != hipSuccess) break;
+            build_a_work_list(p, c.first, c.second);
+            const int ng = (int)(p->a_groups.size() / p->a_G);
+            if (groups) (void)hipFree(groups);
+            if (parts) (void)hipFree(parts);
+            groups = nullptr;
+            parts = nullptr;
+            if ((e = upload_vec(&groups, p->a_groups)) != hipSuccess ||
+                (e = hipMalloc((void**)&parts, sizeof(double) * 4 * (size_t)ng)) != hipSuccess)
+                break;
+            ADev a = make_adev(p);
+            a.groups = groups;
+            a.partials = parts;
+            a.v_in = d.v64[0];
+            a.v_out = d.v64[1];
+            a.fixed = 1;
+            if ((e = launch_backup_a(a, 0, 0, 0, s)) != hipSuccess ||
+                (e = hipEventRecord(e0, s)) != hipSuccess)
+                break;
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_backup_a(a, 0, 0, 0, s);
+            if (e != hipSuccess || (e = hipEventRecord(e1, s)) != hipSuccess ||
+                (e = hipEventSynchronize(e1)) != hipSuccess)
+                break;
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (ms < best) {
+                best = ms;
+                choice = c;
+            }
+        }
+        if (groups) (void)hipFree(groups);
+        if (parts) (void)hipFree(parts);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
+        if (e != hipSuccess)
+            return fail(PVI_E_DEVICE, std::string("scenario A tuning: ") + hipGetErrorString(e));
+        it = g_tune_a.emplace(key, choice).first;
+        const char* verbose = std::getenv("PVI_TUNE_VERBOSE");
+        if (verbose && std::strcmp(verbose, "1") == 0)
+            std::fprintf(stderr, "pvi: scenario A R=%d m=%d L=%d: G=%d CH=%d (%.1f us per sweep)\n",
+                         p->rad[0], p->m, p->L, choice.first, choice.second, 1e3f * best / 3.f);
+    }
+    if (p->a_G != it->second.first || p->a_CH != it->second.second)
+        build_a_work_list(p, it->second.first, it->second.second);
+    return PVI_OK;
+}
+}  // namespace
+
 pvi_status family_init(pvi_mdp* p) {
     auto& d = p->dev;
-    if (p->family == PVI_FAMILY_LEADTIME && upload_vec(&d.agroups, p->a_groups) != hipSuccess)
-        return fail(PVI_E_NOMEM, "scenario A work list allocation failed");
+    if (p->family == PVI_FAMILY_LEADTIME) {
+        pvi_status st = tune_a(p);
+        if (st != PVI_OK) return st;
+        // the chosen work list may have more groups than the partials were sized for
+        const int nt = family_tiles(p);
+        if (nt > d.tiles) {
+            (void)hipFree(d.partials);
+            d.partials = nullptr;
+            if (hipMalloc((void**)&d.partials, 4 * sizeof(double) * (size_t)nt) != hipSuccess)
+                return fail(PVI_E_NOMEM, "scenario A partials allocation failed");
+        }
+        d.tiles = nt;
+        if (upload_vec(&d.agroups, p->a_groups) != hipSuccess)
+            return fail(PVI_E_NOMEM, "scenario A work list allocation failed");
+    }
     if (p->family == PVI_FAMILY_SUBST2) {
         const size_t zn = (size_t)p->b_rows * ipow(p->rad[1], p->m);
         if (hipMalloc((void**)&d.z, sizeof(double) * zn) != hipSuccess ||

@@ -34,6 +34,92 @@ static int64_t ipow_i(int64_t b, int e) {
 // (X_1, total stock) for FIFO or (X_1, X_2 + ... + X_m) for LIFO:
 // sum_d P(d) (-C_h [X - d - W]^+ - C_s [d - X]^+ - C_w W) with W from the FIFO or
 // LIFO issuing equation (Appendix A, reward equation).
+// Work list of the scenario-A backup kernel for G tiles per wavefront (0: the rule
+// below) and CH path points per staged chunk (0: as many as the staging lanes allow).
+// One wavefront takes G tiles of equal digit sum b (so their loops run in lockstep),
+// R lanes each.  Tiles are grouped per block of G in-transit vectors and, inside one
+// digit sum, by (X_m..X_3) then in-transit vector, so a full group is one (X_m..X_3)
+// over G in-transit vectors.  The rule: G = floor(64 / R), or 2 when full groups
+// would give fewer wavefronts than the chip has SIMDs (1,024): more wavefronts, and
+// each stages longer chunks of its path.  The autotuner (families.cpp) times other
+// choices at the first solve of a shape.  Results do not depend on G or CH (each
+// lane's arithmetic is its own tile's).  PVI_A_GROUP=<G> (1 .. floor(64 / R)) and
+// PVI_A_CHUNK=<CH> fix them, for tests.
+void build_a_work_list(pvi_mdp* p, int G_req, int CH_req) {
+    const int R = p->rad[0];
+    int64_t nh = 1;
+    for (int i = 0; i < p->L - 1; ++i) nh *= R;
+    const int64_t nzt = p->m >= 2 ? (int64_t)ipow_i(R, p->m - 2) : 1;
+    const int gmax = a_group_max(p);
+    p->a_G = G_req > 0 ? std::min(G_req, gmax)
+                       : (nh * nzt / gmax < 1024 ? std::min(gmax, 2) : gmax);
+    if (const char* force = std::getenv("PVI_A_GROUP")) {
+        const int g = std::atoi(force);
+        if (g >= 1 && g <= gmax) p->a_G = g;
+    }
+    const int G = p->a_G;
+    const int chmax = a_chunk_max(p, G);
+    p->a_CH = CH_req > 0 ? std::min(CH_req, chmax) : chmax;
+    if (const char* force = std::getenv("PVI_A_CHUNK")) {
+        const int c = std::atoi(force);
+        if (c >= 1 && c <= chmax) p->a_CH = c;
+    }
+    std::vector<int> zsum(nzt, 0);
+    for (int64_t z = 0; z < nzt; ++z) {
+        int64_t t = z;
+        for (int i = 2; i <= p->m - 1; ++i) {
+            zsum[z] += (int)(t % R);
+            t /= R;
+        }
+    }
+    const int bmax = std::max(0, p->m - 2) * (R - 1);
+    p->a_groups.clear();
+    for (int64_t hb = 0; hb < nh; hb += G) {
+        const int64_t he = std::min<int64_t>(hb + G, nh);
+        for (int b = bmax; b >= 0; --b) {
+            int fill = 0;
+            for (int64_t z = 0; z < nzt; ++z) {
+                if (zsum[z] != b) continue;
+                for (int64_t h = hb; h < he; ++h) {
+                    p->a_groups.push_back((int32_t)(h * nzt + z));
+                    if (++fill == G) fill = 0;
+                }
+            }
+            for (; fill != 0 && fill < G; ++fill) p->a_groups.push_back(-1);
+        }
+    }
+    // Workgroups are dispatched round-robin over the 8 XCDs and the kernel gives
+    // XCD x a contiguous range of groups (its L2 then holds the V blocks of those
+    // in-transit vectors).  Sorting each range by digit sum, longest path first,
+    // makes the in-order dispatch onto freed slots a longest-first list schedule,
+    // which shortens the tail of the launch.
+    const int ng = (int)(p->a_groups.size() / G), q = ng >> 3, r = ng & 7;
+    std::vector<int32_t> sorted;
+    sorted.reserve(p->a_groups.size());
+    for (int x = 0; x < 8; ++x) {
+        const int lo = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+        const int cnt = q + (x < r ? 1 : 0);
+        std::vector<int> idx(cnt);
+        for (int k = 0; k < cnt; ++k) idx[k] = lo + k;
+        auto bsum = [&](int grp) { return zsum[p->a_groups[(size_t)grp * G] % nzt]; };
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return bsum(a) > bsum(b); });
+        for (int k : idx)
+            sorted.insert(sorted.end(), p->a_groups.begin() + (size_t)k * G,
+                          p->a_groups.begin() + (size_t)(k + 1) * G);
+    }
+    p->a_groups.swap(sorted);
+}
+
+int a_group_max(const pvi_mdp* p) { return std::min(16, std::max(1, 64 / p->rad[0])); }
+
+// The kernel pads the actions to RMAX = 8, 16, 24 or 32 and stages each path point
+// with RMAX / 8 lanes of 8 actions: CH points per chunk of G tiles fill <= 64 lanes.
+int a_chunk_max(const pvi_mdp* p, int G) {
+    const int R = p->rad[0];
+    const int rmax = R <= 8 ? 8 : R <= 16 ? 16 : R <= 24 ? 24 : 32;
+    return std::max(1, 64 / ((rmax / 8) * G));
+}
+
 static void build_a_tables(pvi_mdp* p) {
     const int R = p->rad[0], dm = p->dmax[0];
     const auto& P = p->pmf[0];
@@ -106,74 +192,7 @@ static void build_a_tables(pvi_mdp* p) {
         p->executed_per_sweep = nh * ex2 * R;
     }
 
-    // Work list of the backup kernel.  One wavefront takes G = floor(64 / R) tiles
-    // of equal digit sum b (so their loops run in lockstep), R lanes each.  Tiles are
-    // grouped per block of G in-transit vectors and, inside one digit sum, by
-    // (X_m..X_3) then in-transit vector, so a full group is one (X_m..X_3) over G
-    // in-transit vectors.
-    // When full groups would give fewer wavefronts than the chip has SIMDs (1,024),
-    // two tiles per wavefront are faster: more wavefronts, and each stages longer
-    // chunks of its path.  Results do not depend on G (each lane's arithmetic is its
-    // own tile's).  PVI_A_GROUP=<G> (1 .. floor(64 / R)) fixes G, for tests.
-    const int64_t nzt = p->m >= 2 ? (int64_t)ipow_i(R, p->m - 2) : 1;
-    const int gmax = std::min(16, std::max(1, 64 / R));
-    p->a_G = nh * nzt / gmax < 1024 ? std::min(gmax, 2) : gmax;
-    if (const char* force = std::getenv("PVI_A_GROUP")) {
-        const int g = std::atoi(force);
-        if (g >= 1 && g <= gmax) p->a_G = g;
-    }
-    // the kernel pads the actions to RMAX = 8, 16, 24 or 32 and stages each path
-    // point with RMAX / 8 lanes of 8 actions: CH points per chunk fill <= 64 lanes
-    const int rmax = R <= 8 ? 8 : R <= 16 ? 16 : R <= 24 ? 24 : 32;
-    p->a_CH = std::max(1, 64 / ((rmax / 8) * p->a_G));
-    const int G = p->a_G;
-    std::vector<int> zsum(nzt, 0);
-    for (int64_t z = 0; z < nzt; ++z) {
-        int64_t t = z;
-        for (int i = 2; i <= p->m - 1; ++i) {
-            zsum[z] += (int)(t % R);
-            t /= R;
-        }
-    }
-    const int bmax = std::max(0, p->m - 2) * (R - 1);
-    p->a_groups.clear();
-    for (int64_t hb = 0; hb < nh; hb += G) {
-        const int64_t he = std::min<int64_t>(hb + G, nh);
-        for (int b = bmax; b >= 0; --b) {
-            int fill = 0;
-            for (int64_t z = 0; z < nzt; ++z) {
-                if (zsum[z] != b) continue;
-                for (int64_t h = hb; h < he; ++h) {
-                    p->a_groups.push_back((int32_t)(h * nzt + z));
-                    if (++fill == G) fill = 0;
-                }
-            }
-            for (; fill != 0 && fill < G; ++fill) p->a_groups.push_back(-1);
-        }
-    }
-    // Workgroups are dispatched round-robin over the 8 XCDs and the kernel gives
-    // XCD x a contiguous range of groups (its L2 then holds the V blocks of those
-    // in-transit vectors).  Sorting each range by digit sum, longest path first,
-    // makes the in-order dispatch onto freed slots a longest-first list schedule,
-    // which shortens the tail of the launch.
-    {
-        const int ng = (int)(p->a_groups.size() / G), q = ng >> 3, r = ng & 7;
-        std::vector<int32_t> sorted;
-        sorted.reserve(p->a_groups.size());
-        for (int x = 0; x < 8; ++x) {
-            const int lo = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
-            const int cnt = q + (x < r ? 1 : 0);
-            std::vector<int> idx(cnt);
-            for (int k = 0; k < cnt; ++k) idx[k] = lo + k;
-            auto bsum = [&](int grp) { return zsum[p->a_groups[(size_t)grp * G] % nzt]; };
-            std::stable_sort(idx.begin(), idx.end(),
-                             [&](int a, int b) { return bsum(a) > bsum(b); });
-            for (int k : idx)
-                sorted.insert(sorted.end(), p->a_groups.begin() + (size_t)k * G,
-                              p->a_groups.begin() + (size_t)(k + 1) * G);
-        }
-        p->a_groups.swap(sorted);
-    }
+    build_a_work_list(p, 0, 0);
     p->logical_per_sweep = p->ns * p->na * (int64_t)(dm + 1);
 }
 

@@ -108,5 +108,10 @@ pvi_status park_results(pvi_mdp* p);
 pvi_status solve_impl(pvi_mdp* p, const pvi_solve_opts* opts, pvi_result* res, bool graphs,
                       std::atomic<int>* progress);
 size_t device_bytes(const pvi_mdp* p);
+// Scenario-A work list for G tiles per wavefront and CH path points per staged chunk
+// (0: the default rule); the largest G and CH the kernel takes.
+void build_a_work_list(pvi_mdp* p, int G, int CH);
+int a_group_max(const pvi_mdp* p);
+int a_chunk_max(const pvi_mdp* p, int G);
 pvi::ADev make_adev(const pvi_mdp* p);
 }  // namespace pvi
