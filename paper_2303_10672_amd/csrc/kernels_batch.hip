@@ -229,10 +229,13 @@ __device__ void solve_item(const BatchItem& it, unsigned char* smem, double* red
 // it served, copies the request's descriptor into LDS with system-coherent loads (the
 // host rewrites the slot for every request, so nothing of it may come from a cache),
 // solves it with solve_item, makes its results visible to the host and then publishes
-// the request number as done.  It returns when the host sets the stop word, or when
-// the heartbeat word has not changed for kSlotIdlePolls polls (a host that stopped
-// serving), so every work group ends.  The poll interval backs off from about 3 us to
-// about 27 us while the slot is idle.
+// the request number as done.  With no request pending it returns when the host has
+// set the stop word, or when the heartbeat word has not changed for kSlotIdlePolls
+// polls (a host that stopped serving), so every work group ends.  The poll interval
+// backs off from about 3 us to about 27 us while the slot is idle.  The work group
+// size (64, 128 or 256 threads) is a launch parameter: solve_item strides over the
+// states by the block size and reduces over whole wavefronts, so the results do not
+// depend on it.
 __device__ __forceinline__ uint32_t load_sys(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -254,12 +257,13 @@ __global__ __launch_bounds__(256) void slot_kernel(SlotHeader* hdr, SlotSync* sy
             uint32_t hb_seen = load_sys(&hdr->heartbeat), still = 0, s = last;
             int nap = 1, ex = 0;
             for (;;) {
+                // a request already in the slot is served even when the stop word is set
+                s = load_sys(&sync[k].seq);
+                if (s != last) break;
                 if (load_sys(&hdr->stop)) {
                     ex = 1;
                     break;
                 }
-                s = load_sys(&sync[k].seq);
-                if (s != last) break;
                 const uint32_t hb = load_sys(&hdr->heartbeat);
                 if (hb != hb_seen) {
                     hb_seen = hb;
@@ -295,20 +299,21 @@ __global__ __launch_bounds__(256) void slot_kernel(SlotHeader* hdr, SlotSync* sy
 }
 
 hipError_t launch_slots(SlotHeader* hdr, SlotSync* sync, const BatchItem* items, int nslots,
-                        size_t lds_bytes, hipStream_t s) {
+                        int threads, size_t lds_bytes, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
-    if (lds_bytes > 65536 - 1024) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((slot_kernel<kSlotRmax>), dim3(nslots), dim3(256), lds_bytes, s, hdr, sync,
-                       items);
+    if (lds_bytes > 65536 - 1024 || (threads != 64 && threads != 128 && threads != 256))
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((slot_kernel<kSlotRmax>), dim3(nslots), dim3(threads), lds_bytes, s, hdr,
+                       sync, items);
     return hipGetLastError();
 }
 
-int slot_capacity(size_t lds_bytes) {
+int slot_capacity(int threads, size_t lds_bytes) {
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&slot_kernel<kSlotRmax>), 256, lds_bytes) !=
-            hipSuccess ||
+            &per_cu, reinterpret_cast<const void*>(&slot_kernel<kSlotRmax>), threads,
+            lds_bytes) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     return per_cu * cus;

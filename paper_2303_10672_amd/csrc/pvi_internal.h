@@ -190,15 +190,17 @@ struct BatchItem {
     double* stats;  // [8]: sweeps fp32, sweeps fp64, span, dmax, dmin, status
 };
 // The slot kernel (kernels_batch.hip): work group k serves slot k of a table in
-// coherent pinned host memory (slot_layout.h) until the host stops it.  Instances up
+// coherent pinned host memory (slot_layout.h) until the host stops it; a request
+// already placed in a slot is served before the stop word is honoured.  Instances up
 // to kSlotRmax actions; lds_bytes of dynamic LDS per work group.
 struct SlotHeader;
 struct SlotSync;
 constexpr int kSlotRmax = 24;
 hipError_t launch_slots(SlotHeader* hdr, SlotSync* sync, const BatchItem* items, int nslots,
-                        size_t lds_bytes, hipStream_t s);
-// Work groups of the slot kernel the device keeps resident at once (0 if unknown).
-int slot_capacity(size_t lds_bytes);
+                        int threads, size_t lds_bytes, hipStream_t s);
+// Work groups of `threads` (64, 128 or 256) of the slot kernel the device keeps
+// resident at once (0 if unknown).
+int slot_capacity(int threads, size_t lds_bytes);
 
 // launchers (kernels_a.hip)
 // LIFO issuing (p.lifo = 1, m >= 2): tiles (O, X_{m-1}..X_2), FP64 accumulation.

@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cstddef>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <thread>
@@ -126,6 +127,7 @@ size_t slot_need(const pvi_mdp* p) {
 
 struct HipSlotOps : pvi::srv::SlotOps {
     int nslots = 0;
+    int threads = 256;      // threads per slot work group
     size_t lds = 0;
     char* host = nullptr;   // the block (host address)
     char* dev = nullptr;    // the same block (device address)
@@ -253,7 +255,7 @@ struct HipSlotOps : pvi::srv::SlotOps {
     }
 
     bool launch() override {
-        if (pvi::launch_slots(dptr(hdr), dptr(sync), dptr(items), nslots, lds, stream) !=
+        if (pvi::launch_slots(dptr(hdr), dptr(sync), dptr(items), nslots, threads, lds, stream) !=
                 hipSuccess ||
             hipEventRecord(done_ev, stream) != hipSuccess)
             return false;
@@ -265,6 +267,81 @@ struct HipSlotOps : pvi::srv::SlotOps {
         if (launched) (void)hipEventSynchronize(done_ev);
     }
 };
+
+// Threads per slot work group, timed at the first server of a process: every slot is
+// filled with a copy of a small instance of the serving family (m = 3, L = 1, order
+// cap 10, Poisson(4) demand: 1,331 states, FP32 schedule), the stop word is set so
+// that each work group serves its slot once and returns, and the launch is timed at
+// 64, 128 and 256 threads; the fastest is kept for the process.  The size does not
+// change any result.  PVI_SLOT_THREADS=64|128|256 fixes it; PVI_TUNE=0 keeps 256.
+int slot_threads(HipSlotOps& ops) {
+    if (const char* f = std::getenv("PVI_SLOT_THREADS")) {
+        const int t = std::atoi(f);
+        if (t == 64 || t == 128 || t == 256) return t;
+    }
+    const char* env = std::getenv("PVI_TUNE");
+    if (env && std::strcmp(env, "0") == 0) return 256;
+    static std::mutex mu;
+    static int chosen = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (chosen) return chosen;
+    pvi_mdp_desc d{};
+    d.struct_size = sizeof(d);
+    d.family = PVI_FAMILY_LEADTIME;
+    d.m = 3;
+    d.lead_time = 1;
+    d.n_periods = 1;
+    d.a_max[0] = 10;
+    d.d_max[0] = 20;
+    d.demand_kind[0] = PVI_DEMAND_POISSON;
+    d.demand_mean[0][0] = 4.0;
+    d.c_var[0] = 3.0;
+    d.c_hold = 1.0;
+    d.c_short = 5.0;
+    d.c_waste = 7.0;
+    d.gamma = 0.99;
+    d.issuing = PVI_FIFO;
+    pvi_mdp* m = nullptr;
+    if (mdp_create(&d, &m) != PVI_OK) return 256;
+    Request r;
+    r.mdp = m;
+    r.opts.struct_size = sizeof(pvi_solve_opts);
+    r.opts.precision = PVI_FP32;
+    r.opts.eps = 1e-4;
+    r.opts.max_sweeps = 100000;
+    for (int k = 0; k < ops.nslots; ++k) ops.prepare(k, &r);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best = 1e30f;
+    int pick = 256;
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+        for (int t : {256, 128, 64}) {
+            ops.threads = t;
+            for (int k = 0; k < ops.nslots; ++k)
+                __atomic_store_n(&ops.sync[k].seq, ops.sync[k].seq + 1, __ATOMIC_RELEASE);
+            __atomic_store_n(&ops.hdr->stop, 1u, __ATOMIC_RELEASE);
+            float ms = 0.f;
+            if (hipEventRecord(e0, ops.stream) != hipSuccess || !ops.launch() ||
+                hipEventRecord(e1, ops.stream) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                break;
+            if (ms < best) {
+                best = ms;
+                pick = t;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    __atomic_store_n(&ops.hdr->stop, 0u, __ATOMIC_RELEASE);
+    mdp_destroy(m);
+    const char* verbose = std::getenv("PVI_TUNE_VERBOSE");
+    if (verbose && std::strcmp(verbose, "1") == 0)
+        std::fprintf(stderr, "pvi: slot kernel %d threads per slot (%.2f ms for %d solves)\n",
+                     pick, best, ops.nslots);
+    chosen = pick;
+    return pick;
+}
 
 void slot_feeder(pvi_server* S) {
     (void)hipSetDevice(S->device);
@@ -305,13 +382,14 @@ pvi_status pvi_server_create(int64_t hbm_budget_bytes, int32_t small_batch, pvi_
     if (small_batch > 0) {
         // as many slots as asked for, but no more than stay resident at once: every slot
         // needs a running work group
-        int cap = pvi::slot_capacity(kSmallMaxLds);
+        int cap = pvi::slot_capacity(256, kSmallMaxLds);
         if (cap <= 0) cap = 256;
         S->slots = std::make_unique<HipSlotOps>();
         if (!S->slots->init(std::min(S->small_batch, cap))) {
             delete S;
             return fail(PVI_E_NOMEM, "pvi_server_create: slot table allocation failed");
         }
+        S->slots->threads = slot_threads(*S->slots);
         S->workers.emplace_back(slot_feeder, S);
     }
     for (int i = 0; i < 2; ++i) S->workers.emplace_back(large_worker, S, 2 + i);

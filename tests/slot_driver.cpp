@@ -96,12 +96,13 @@ struct FakeDevice : SlotOps {
             int still = 0;
             bool ex = false;
             for (;;) {
+                // a request already in the slot is served even when the stop word is set
+                s = ld(&sync[k].seq);
+                if (s != last) break;
                 if (ld(&hdr.stop)) {
                     ex = true;
                     break;
                 }
-                s = ld(&sync[k].seq);
-                if (s != last) break;
                 const uint32_t hb = ld(&hdr.heartbeat);
                 if (hb != hb_seen) {
                     hb_seen = hb;

@@ -224,3 +224,26 @@ def test_slots_idle_launch_stops_and_restarts(monkeypatch):
     s.close()
     assert (l1, l2) == (1, 2)
     assert np.array_equal(pvi.value_get(m1), pvi.value_get(m2))
+
+
+@pytest.mark.parametrize("threads", ["64", "128", "256"])
+def test_slot_threads_do_not_change_results(threads, monkeypatch):
+    """The threads per slot work group (timed at server creation, fixed here with
+    PVI_SLOT_THREADS) only change how a work group strides over the states: the
+    results are bit-identical to the 256-thread ones."""
+    scs = small_mix(12, seed=9)
+    monkeypatch.setenv("PVI_SLOT_THREADS", "256")
+    ref = pvi.Server(small_batch=16)
+    mr = [pvi.mdp_create(sc) for sc in scs]
+    for t in ref.submit(mr, precision="fp32"):
+        assert ref.wait(t)[0] == pvi.PVI_OK
+    ref.close()
+    monkeypatch.setenv("PVI_SLOT_THREADS", threads)
+    s = pvi.Server(small_batch=16)
+    ms = [pvi.mdp_create(sc) for sc in scs]
+    for t in s.submit(ms, precision="fp32"):
+        assert s.wait(t)[0] == pvi.PVI_OK
+    s.close()
+    for a, b in zip(mr, ms):
+        assert np.array_equal(pvi.value_get(a), pvi.value_get(b))
+        assert np.array_equal(pvi.policy_get(a)[0], pvi.policy_get(b)[0])
