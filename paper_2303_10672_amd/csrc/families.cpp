@@ -214,8 +214,11 @@ int family_tiles(const pvi_mdp* p) {
         return p->a_G > 0 ? (int)(p->a_groups.size() / p->a_G) : 1;  // one per tile group
     }
     if (p->family == PVI_FAMILY_SUBST2) return (int)ipow(p->rad[1], p->m - 1);
-    if (p->family == PVI_FAMILY_RUL_WEEKDAY)
+    if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
+        if (p->m >= 4 && p->c_exogenous)  // top merge fused with the final sum
+            return (int)c_partial_slots(p->P, ipow(p->rad[0], p->m - 2));
         return (int)(p->P * ((ipow(p->rad[0], p->m - 1) + 255) / 256));
+    }
     if (p->family == PVI_FAMILY_SUBST2_L1)
         return (int)(ipow(p->rad[1], p->m) * ((ipow(p->rad[0], p->m) + 255) / 256));
     return 1;
@@ -275,8 +278,12 @@ pvi_status tune_c(pvi_mdp* p) {
             return fail(PVI_E_INVALID, "PVI_C_BLOCK must be 4, 8, 12, 16 or 32");
         const int R = p->rad[0], rc = R <= 8 ? 8 : R <= 16 ? 16 : R <= 24 ? 24 : 32;
         for (int a = 0; a < 2; ++a) {
-            const bool fits = (size_t)(a ? 4 : 8) * R * rc * w <= 65536 && R * w <= 1024;
-            for (int j = 3; j < 10; ++j) p->c_lb[a][j] = fits ? w : 0;
+            for (int j = 3; j < 10; ++j) {
+                const bool fused = j == p->m - 1 && p->c_exogenous;
+                const bool fits = (size_t)(a ? 4 : 8) * R * rc * w <= 65536 &&
+                                  R * w <= (fused ? kCTopThreads : 1024);
+                p->c_lb[a][j] = fits ? w : 0;
+            }
         }
         return PVI_OK;
     }

@@ -338,6 +338,129 @@ __global__ __launch_bounds__(256) void c_final_kernel(CDev p, const void* tin) {
     }
 }
 
+// Rows r .. nr-1 of the top merge for one y_m, each folded into the final sums at once:
+// T(r) = sum_{y<=r} Bin(y; r, q_{m-1}) slab(r - y, c(x_{m-1} + y)) (the merge kernel's
+// terms and order, rounded to the table type as a stored table would be), then
+// B[r] += Bin(y_m; y_m + r, p_m) T(r), B[r] being the running final sum of order y_m + r.
+template <typename VT, int LB, int RC, int r>
+__device__ __forceinline__ void c_top_rows(const VT* slab, const int (&zoff)[RC], ConstF64 w,
+                                           ConstF64 bm, int R, int ym, int nr,
+                                           double (&B)[RC]) {
+    if constexpr (r < RC) {
+        if (r < nr) {
+            constexpr int RS = RC * LB;
+            const ConstF64 wr = w + r * R;
+            double acc = 0.0;
+#pragma unroll
+            for (int y = 0; y <= r; ++y)
+                acc = fma(wr[y], (double)slab[(r - y) * RS + zoff[y]], acc);
+            B[r] = fma(bm[(ym + r) * R + ym], (double)(VT)acc, B[r]);
+        }
+        // each row completes before the next one's reads are issued, so the rows' inputs
+        // are never all live at once
+        asm volatile("" ::: "memory");
+        c_top_rows<VT, LB, RC, r + 1>(slab, zoff, w, bm, R, ym, nr, B);
+    }
+}
+
+// Top merge (life class m-1, m >= 4, order-independent life) fused with the final sum
+// and the max over orders, so the top table is never written or read back:
+//   Q(tau, x, a) = -C_f [a > 0] + sum_{y_m<=a} Bin(y_m; a, p_m) T_{m-1}(tau, y_m, x; a - y_m).
+// One workgroup per (tau, block of LB consecutive values of the digits below m-1); lanes
+// (x_{m-1}, lo) as in the merge kernel, one state each.  The loop runs over y_m; for each
+// it stages the slab T_{m-2}(tau, y_m, z, lo; r') (r' < R - y_m) in LDS and adds every
+// row's merge into B (other workgroups on the CU load while this one computes).  Order
+// a = y_m is then complete (its terms arrive in the order y_m = 0, 1, .., a, as in the
+// final kernel), so the running best, second and argmax follow the order of a, and B
+// shifts down by one.  Partial slot of a workgroup: its block id; slots past the grid
+// (the count is sized for the narrowest block) get neutral values.
+template <typename VT, int LB, int RC>
+__global__ __launch_bounds__(kCTopThreads) void c_top_final_kernel(CDev p, const void* in_,
+                                                                  int nslots) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[64];
+    if (!p.extract && p.ctl->stop) return;
+    constexpr int RS = RC * LB;
+    const int R = p.R, tid = threadIdx.x, j = p.m - 1;
+    VT* slab = reinterpret_cast<VT*>(smem);  // [r'][z < RC][LB]
+    const int nlo = (int)p.pow_r[j - 1];     // R^(m-2): the digits below m-1
+    const int nlob = (nlo + LB - 1) / LB;
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int tau = lid / nlob;
+    const int lo0 = (lid - tau * nlob) * LB;
+    const int l = tid % LB, xz = tid / LB;  // lane: lo offset, digit m-1
+    const bool lane_ok = xz < R && lo0 + l < nlo;
+    const int64_t D = (int64_t)xz * nlo + lo0 + l;  // the lane's state within weekday tau
+    const int64_t trow = (int64_t)tau * p.npair;
+    const VT* in = reinterpret_cast<const VT*>(in_);
+    const ConstI32 pb = (ConstI32)p.pair_base;
+    int zoff[RC];  // slab offset of column c(x_{m-1} + y) in row 0
+#pragma unroll
+    for (int y = 0; y < RC; ++y) zoff[y] = min(xz + y, R - 1) * LB + l;
+    const ConstF64 w = (ConstF64)(p.binq + (size_t)j * R * R);
+    const ConstF64 bm = (ConstF64)p.binm;
+    double B[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) B[r] = 0.0;
+    double best = -DBL_MAX, second = -DBL_MAX;
+    int arg = 0;
+    for (int ym = 0; ym < R; ++ym) {
+        const int nr = R - ym;
+        if (ym > 0) __syncthreads();  // the previous y_m's rows are read
+        if (lane_ok) {
+            // every row's load is issued before the first LDS write waits for one
+            const VT* src = in + (trow + pb[ym]) * p.nblk + D;
+            VT v[RC];
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr) v[rr] = rr < nr ? src[(int64_t)rr * p.nblk] : VT(0);
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr)
+                if (rr < nr) slab[rr * RS + xz * LB + l] = v[rr];
+        }
+        __syncthreads();
+        if (lane_ok) {
+            // the merge weights do not change with y_m; an opaque copy of their address
+            // keeps the compiler from hoisting all of them out of the loop into registers
+            ConstF64 wl = w;
+            asm volatile("" : "+s"(wl));
+            c_top_rows<VT, LB, RC, 0>(slab, zoff, wl, bm, R, ym, nr, B);
+            const double q = (ym > 0 ? -p.cfixed : 0.0) + B[0];
+            if (q > best) {
+                second = best;
+                best = q;
+                arg = ym;
+            } else if (q > second) {
+                second = q;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r + 1 < RC; ++r) B[r] = B[r + 1];
+        B[RC - 1] = 0.0;
+    }
+    double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
+    if (lane_ok) {
+        const int64_t s = (int64_t)tau * p.nblk + D;
+        const double mu = sizeof(VT) == 4 ? p.ctl->mu : 0.0;
+        const VT o = (VT)(best - mu);
+        reinterpret_cast<VT*>(p.v_out)[s] = o;
+        const double out = (double)o;
+        const double dv = out - (double)reinterpret_cast<const VT*>(p.v_in)[s];
+        dmx = dmn = dv;
+        vmx = vmn = out;
+    }
+    block_reduce4(dmx, dmn, vmx, vmn, red);
+    if (threadIdx.x == 0) {
+        for (int k = lid; k < nslots; k += gridDim.x) {
+            double* pp = p.partials + 4 * (size_t)k;
+            const bool mine = k == lid;
+            pp[0] = mine ? dmx : -DBL_MAX;
+            pp[1] = mine ? dmn : DBL_MAX;
+            pp[2] = mine ? vmx : -DBL_MAX;
+            pp[3] = mine ? vmn : DBL_MAX;
+        }
+    }
+}
+
 // compile-time bound of the merge sums for R (the merge kernels' RC)
 static int c_rc_for(int R) { return R <= 8 ? 8 : R <= 16 ? 16 : R <= 24 ? 24 : 32; }
 
@@ -355,10 +478,53 @@ static int c_default_lb(const CDev& p) {
 }
 
 template <typename VT>
-static hipError_t launch_c_chain(const CDev& p, void* top, hipStream_t s);
+static hipError_t launch_c_chain(const CDev& p, void* top, int jlast, hipStream_t s);
 template <typename VT>
 static hipError_t launch_merge_lb(const CDev& p, int j, const void* in, void* out, int lb,
                                   dim3 grid, int threads, size_t lds, hipStream_t s);
+
+// block width of merge level j (tuned, else the LDS rule)
+template <typename VT>
+static int c_level_lb(const CDev& p, int j) {
+    const int tuned = p.lb[sizeof(VT) == 4 ? 1 : 0][j];
+    return tuned > 0 ? tuned : c_default_lb<VT>(p);
+}
+
+template <typename VT, int LB>
+static hipError_t launch_top_final_rc(const CDev& p, const void* in, int nslots, dim3 grid,
+                                      int threads, size_t lds, hipStream_t s) {
+    if (p.R <= 8)
+        hipLaunchKernelGGL((c_top_final_kernel<VT, LB, 8>), grid, dim3(threads), lds, s, p, in, nslots);
+    else if (p.R <= 16)
+        hipLaunchKernelGGL((c_top_final_kernel<VT, LB, 16>), grid, dim3(threads), lds, s, p, in, nslots);
+    else if (p.R <= 24)
+        hipLaunchKernelGGL((c_top_final_kernel<VT, LB, 24>), grid, dim3(threads), lds, s, p, in, nslots);
+    else
+        hipLaunchKernelGGL((c_top_final_kernel<VT, LB, 32>), grid, dim3(threads), lds, s, p, in, nslots);
+    return hipGetLastError();
+}
+
+// The fused top merge and final sum at block width lb, reading level m-2 from `in`.
+template <typename VT>
+static hipError_t launch_top_final(const CDev& p, const void* in, int lb, hipStream_t s) {
+    const int64_t nlo = p.pow_r[p.m - 2];
+    const int64_t nlob = (nlo + lb - 1) / lb;
+    const int64_t nwg = nlob * p.P;
+    const int64_t nslots = c_partial_slots(p.P, nlo);
+    const int threads = ((p.R * lb + 63) / 64) * 64;
+    const size_t lds = c_lds_for<VT>(p, lb);
+    if (p.m < 4 || !p.exogenous || p.R > 32 || lds > 65536 || p.R * lb > kCTopThreads ||
+        nslots > 0x7fffffff || nwg > nslots || nlo * p.R != p.nblk)
+        return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)nwg);
+    const int ns = (int)nslots;
+    if (lb == 32) return launch_top_final_rc<VT, 32>(p, in, ns, grid, threads, lds, s);
+    if (lb == 16) return launch_top_final_rc<VT, 16>(p, in, ns, grid, threads, lds, s);
+    if (lb == 12) return launch_top_final_rc<VT, 12>(p, in, ns, grid, threads, lds, s);
+    if (lb == 8) return launch_top_final_rc<VT, 8>(p, in, ns, grid, threads, lds, s);
+    if (lb == 4) return launch_top_final_rc<VT, 4>(p, in, ns, grid, threads, lds, s);
+    return hipErrorInvalidValue;
+}
 
 template <typename VT, bool EXTRACT>
 static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
@@ -373,15 +539,22 @@ static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
     if (e != hipSuccess) return e;
     const unsigned gx = (unsigned)((p.nblk + 255) / 256);
     const void* tin = p.u;
+    if (!EXTRACT && p.m >= 4 && p.exogenous) {
+        // levels 2 .. m-2, then the top level fused with the final sum
+        if ((e = launch_c_chain<VT>(p, nullptr, p.m - 2, s)) != hipSuccess) return e;
+        tin = ((p.m - 2) & 1) ? p.t1 : p.t0;
+        return launch_top_final<VT>(p, tin, c_level_lb<VT>(p, p.m - 1), s);
+    }
     if (p.m >= 3 && p.exogenous) {
-        if ((e = launch_c_chain<VT>(p, p.t1 /* level m-1 output */, s)) != hipSuccess) return e;
+        if ((e = launch_c_chain<VT>(p, p.t1 /* level m-1 output */, p.m - 1, s)) != hipSuccess)
+            return e;
         tin = ((p.m - 1) & 1) ? p.t1 : p.t0;
     } else if (p.m >= 3) {
         for (int a = 0; a < p.R; ++a) {
             CDev q = p;
             q.binq = p.binq + (size_t)a * p.m * p.R * p.R;
             q.alim = a;
-            if ((e = launch_c_chain<VT>(q, p.tf, s)) != hipSuccess) return e;
+            if ((e = launch_c_chain<VT>(q, p.tf, p.m - 1, s)) != hipSuccess) return e;
         }
         tin = p.tf;
     }
@@ -397,15 +570,15 @@ static hipError_t launch_c_t(const CDev& p, hipStream_t s) {
     return hipGetLastError();
 }
 
-// The merges of life classes 2 .. m-1 from U.  Levels alternate between the two
-// ping-pong tables; in the order-dependent case (alim < a_max possible) the top
-// level writes only its row r = alim - y_m, into `top`.
+// The merges of life classes 2 .. jlast from U.  Levels alternate between the two
+// ping-pong tables (level j writes t_{j mod 2}); in the order-dependent case (alim <
+// a_max possible) the top level m-1 writes only its row r = alim - y_m, into `top`.
 template <typename VT>
-static hipError_t launch_c_chain(const CDev& p, void* top, hipStream_t s) {
+static hipError_t launch_c_chain(const CDev& p, void* top, int jlast, hipStream_t s) {
     hipError_t e = hipSuccess;
     const void* in = p.u;
     void* bufs[2] = {p.t0, p.t1};
-    for (int j = 2; j <= p.m - 1; ++j) {
+    for (int j = 2; j <= jlast; ++j) {
         CDev q = p;
         void* out = bufs[j & 1];
         if (!p.exogenous && j == p.m - 1) {
@@ -427,8 +600,7 @@ static hipError_t launch_c_chain(const CDev& p, void* top, hipStream_t s) {
             // the tuned block width of this level, else the widest block of low digits
             // (up to 64 bytes per slab row) whose slab stays within 32 KB of LDS, so
             // several workgroups share a CU
-            const int tuned = p.lb[sizeof(VT) == 4 ? 1 : 0][j];
-            const int lb = tuned > 0 ? tuned : c_default_lb<VT>(p);
+            const int lb = c_level_lb<VT>(p, j);
             if (c_lds_for<VT>(p, lb) > 65536 || p.R * lb > 1024)
                 return hipErrorInvalidConfiguration;
             auto lds_for = [&](int w) { return c_lds_for<VT>(p, w); };
@@ -491,6 +663,20 @@ static hipError_t launch_merge_once(const CDev& p, int j, int lb, hipStream_t s)
                                c_lds_for<VT>(p, lb), s);
 }
 
+// One launch of level j at block width lb as a sweep runs it: the fused top merge and
+// final sum for the top level of the order-independent case (values into t1, read and
+// written in place by each lane), else the merge kernel from t0 into t1.
+template <typename VT>
+static hipError_t launch_level_once(const CDev& p, int j, int lb, hipStream_t s) {
+    if (j == p.m - 1 && p.exogenous) {
+        CDev q = p;
+        q.v_in = p.t1;
+        q.v_out = p.t1;
+        return launch_top_final<VT>(q, p.t0, lb, s);
+    }
+    return launch_merge_once<VT>(p, j, lb, s);
+}
+
 template <typename VT>
 static hipError_t tune_levels(const CDev& p, hipStream_t s, int32_t* lb_out) {
     hipEvent_t e0, e1;
@@ -502,11 +688,12 @@ static hipError_t tune_levels(const CDev& p, hipStream_t s, int32_t* lb_out) {
     }
     for (int j = 3; j <= p.m - 1 && j < 10 && e == hipSuccess; ++j) {
         float best = 1e30f;
+        const bool fused = j == p.m - 1 && p.exogenous;
         for (int lb : {4, 8, 12, 16, 32}) {
-            if (c_lds_for<VT>(p, lb) > 65536 || p.R * lb > 1024) continue;
-            if ((e = launch_merge_once<VT>(p, j, lb, s)) != hipSuccess) break;  // warm-up
+            if (c_lds_for<VT>(p, lb) > 65536 || p.R * lb > (fused ? kCTopThreads : 1024)) continue;
+            if ((e = launch_level_once<VT>(p, j, lb, s)) != hipSuccess) break;  // warm-up
             if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
-            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_merge_once<VT>(p, j, lb, s);
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_level_once<VT>(p, j, lb, s);
             if (e != hipSuccess || (e = hipEventRecord(e1, s)) != hipSuccess ||
                 (e = hipEventSynchronize(e1)) != hipSuccess)
                 break;

@@ -227,8 +227,16 @@ hipError_t launch_fill(double* v, double value, int64_t n, hipStream_t s);
 // kernels_c.hip
 hipError_t launch_backup_c(const CDev& p, int storage_fp32, int extract, hipStream_t s);
 // Time the merge kernels of levels 3..m-1 at each block width that fits (4, 8, 12, 16, 32 low
-// digits per workgroup) on the handle's own tables, and write the fastest into lb.
+// digits per workgroup) on the handle's own tables, and write the fastest into lb.  With
+// order-independent life the top level m-1 is timed as it runs, fused with the final sum.
 hipError_t tune_c_merge(const CDev& p, hipStream_t s, int32_t lb[2][10]);
+// Span partial slots of a scenario-C sweep whose top merge is fused with the final sum
+// (m >= 4, order-independent life): one per workgroup at the narrowest block width, 4
+// of the nlo = R^(m-2) low-digit values, for each of the P weekdays.
+inline int64_t c_partial_slots(int64_t P, int64_t nlo) { return P * ((nlo + 3) / 4); }
+// Most lanes (R x block width) of a fused top-merge workgroup: two wavefronts per SIMD,
+// so that its per-lane sums, prefetched rows and offsets fit in registers.
+constexpr int kCTopThreads = 512;
 // kernels_b.hip
 hipError_t launch_backup_b(const BDev& p, int storage_fp32, int extract, hipStream_t s);
 
