@@ -73,6 +73,10 @@ def parse():
                     help="paper workloads: also time an FP64 solve that writes a checkpoint "
                          "file as often as the paper did (A every 100 sweeps, B and C "
                          "every sweep)")
+    ap.add_argument("--fixed-sweeps", type=int, default=0,
+                    help="config2/config3: instead of full solves, one FP64 and one "
+                         "FP32-storage run of exactly this many sweeps (for profiles and "
+                         "counters)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a known-traffic "
                          "kernel for scaling HBM counters)")
@@ -368,15 +372,17 @@ def bench_single(args, pvi, W, cfg):
     m = pvi.mdp_create(sc)
     out = {}
     runs = [("fp64", "span"), ("fp32", "span")]
-    if cfg == 3:
+    if cfg == 3 and args.fixed_sweeps <= 0:
         runs += [("fp64", "periodic"), ("fp32", "periodic")]
+    k = max(args.fixed_sweeps, 0)
     for prec, rule in runs:
         key = prec if rule == "span" else f"{prec}_{rule}"
-        pvi.vi_solve(m, precision=prec, max_sweeps=20000, allow_not_converged=True,
-                     stop_rule=rule)
+        if k == 0:
+            pvi.vi_solve(m, precision=prec, max_sweeps=20000, allow_not_converged=True,
+                         stop_rule=rule)
         t0 = time.perf_counter()
         r = pvi.vi_solve(m, precision=prec, max_sweeps=20000, time_kernels=True,
-                         allow_not_converged=True, stop_rule=rule)
+                         allow_not_converged=True, stop_rule=rule, fixed_sweeps=k)
         dt = time.perf_counter() - t0
         print(f"{key}: {dt:.2f} s, {r['sweeps_fp32']} + {r['sweeps_fp64']} sweeps",
               file=sys.stderr, flush=True)
@@ -613,6 +619,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "batch":
         return bench_batch(args, pvi, W)
     if args.workload == "serving":
@@ -627,13 +640,6 @@ def main():
         return bench_paper_b(args, pvi, W)
     if args.workload == "rollouts":
         return bench_rollouts(args, pvi, W)
-    if args.copy_calibration_mb > 0:
-        n = args.copy_calibration_mb * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     sc = W.config1()
     stream = torch.cuda.Stream()
     handle = stream.cuda_stream

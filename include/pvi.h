@@ -208,6 +208,14 @@ typedef struct pvi_result {
     int64_t logical_backups;   /* sum over the sweeps this call ran (and the policy
                                   extraction) of N_S * sum_a |Omega(s,a)| */
     int64_t executed_terms;    /* multiply-adds the kernels actually ran */
+    double vhat_shift;         /* gamma/(1-gamma) (dmax + dmin)/2: V + vhat_shift is the
+                                  midpoint of the MacQueen bounds on V* (0 when gamma = 1).
+                                  The returned V already holds any FP32-storage offset,
+                                  so no separate offset is reported */
+    double device_ms;          /* stream time from the first to the last kernel of the
+                                  solve (HIP events); 0 where not measured: requests
+                                  served by the small-instance kernel and
+                                  vi_solve_noalloc */
 } pvi_result;
 
 typedef struct pvi_mdp pvi_mdp;

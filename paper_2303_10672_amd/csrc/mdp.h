@@ -79,6 +79,7 @@ struct pvi_mdp {
         int tiles = 0;
         size_t bytes = 0;
         std::vector<hipEvent_t> ev;
+        hipEvent_t span_ev[2] = {nullptr, nullptr};  // a whole solve's stream time
         // instantiated graphs of kGraphSweeps sweeps (backup + span launches), keyed by
         // storage precision, compensated sums and fixed-length runs; their kernel
         // arguments hold this handle's buffers, so they live and die with them
@@ -114,4 +115,11 @@ void build_a_work_list(pvi_mdp* p, int G, int CH);
 int a_group_max(const pvi_mdp* p);
 int a_chunk_max(const pvi_mdp* p, int G);
 pvi::ADev make_adev(const pvi_mdp* p);
+// Shift from V to the midpoint of MacQueen's bounds on V* (the standard bounds of
+// discounted value iteration, V + gamma/(1-gamma) [dmin, dmax] with dmax, dmin the last
+// sweep's largest and smallest increment): gamma/(1-gamma) times the increments' mean;
+// 0 for gamma = 1, where the bounds do not apply.
+inline double vhat_shift(double gamma, double dmax, double dmin) {
+    return gamma < 1.0 ? gamma / (1.0 - gamma) * 0.5 * (dmax + dmin) : 0.0;
+}
 }  // namespace pvi

@@ -194,6 +194,7 @@ extern "C" pvi_status vi_solve_noalloc(const pvi_mdp* cp, const pvi_solve_opts* 
         res->dmin = hc.dmin;
         res->logical_backups = p->logical_per_sweep * (int64_t)(sweeps + 1);
         res->executed_terms = p->executed_per_sweep * (int64_t)(sweeps + 1);
+        res->vhat_shift = pvi::vhat_shift(g, hc.dmax, hc.dmin);
         res->wall_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
                 .count();

@@ -250,6 +250,7 @@ struct HipSlotOps : pvi::srv::SlotOps {
         const int64_t sw = res.sweeps_fp32 + res.sweeps_fp64 + 1;
         res.logical_backups = p->logical_per_sweep * sw;
         res.executed_terms = p->executed_per_sweep * sw;
+        res.vhat_shift = pvi::vhat_shift(p->d.gamma, res.dmax, res.dmin);
         res.status = stt[5] == 0.0 ? PVI_OK : PVI_E_NOT_CONVERGED;
         return res.status;
     }

@@ -47,6 +47,8 @@ void free_device(pvi_mdp* p) {
     family_free(p);
     if (d.h_ctl) (void)hipHostFree(d.h_ctl);
     for (auto e : d.ev) (void)hipEventDestroy(e);
+    for (auto e : d.span_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto& g : d.graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (d.own) (void)hipStreamDestroy(d.own);
@@ -443,6 +445,9 @@ pvi_status pvi::solve_impl(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result
     if (st != PVI_OK) return st;
     auto& d = p->dev;
     hipStream_t s = o->stream ? (hipStream_t)o->stream : d.own;
+    for (auto& e : d.span_ev)
+        if (!e) PVI_HIP(hipEventCreate(&e));
+    PVI_HIP(hipEventRecord(d.span_ev[0], s));
     const double g = p->d.gamma;
     // span rule: eps (1 - gamma)/gamma; undiscounted (gamma = 1), span < eps as in
     // Appendix B's test
@@ -541,6 +546,7 @@ pvi_status pvi::solve_impl(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result
     }
     // policy and Q gap from one more FP64 backup of the returned V
     PVI_HIP(family_backup(p, 0, 0, 1, 0, v64_slot(p, p->ret_buf), nullptr, s));
+    PVI_HIP(hipEventRecord(d.span_ev[1], s));
     PVI_HIP(hipStreamSynchronize(s));
     p->have_result = 1;
     const bool converged = o->fixed_sweeps > 0 || o64.stopped;
@@ -565,6 +571,10 @@ pvi_status pvi::solve_impl(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result
         res->executed_terms = p->executed_per_sweep * sweeps;
         res->wall_ms = std::chrono::duration<double, std::milli>(
                            std::chrono::steady_clock::now() - t0).count();
+        res->vhat_shift = vhat_shift(g, res->dmax, res->dmin);
+        float ms = 0.f;
+        PVI_HIP(hipEventElapsedTime(&ms, d.span_ev[0], d.span_ev[1]));
+        res->device_ms = ms;
     }
     if (!converged) return fail(PVI_E_NOT_CONVERGED, "vi_solve: max_sweeps reached");
     return PVI_OK;

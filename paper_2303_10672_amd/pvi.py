@@ -72,7 +72,8 @@ class Result(ctypes.Structure):
         ("final_span", ctypes.c_double), ("threshold", ctypes.c_double),
         ("dmax", ctypes.c_double), ("dmin", ctypes.c_double), ("wall_ms", ctypes.c_double),
         ("backup_ms", ctypes.c_double * 2), ("logical_backups", ctypes.c_int64),
-        ("executed_terms", ctypes.c_int64),
+        ("executed_terms", ctypes.c_int64), ("vhat_shift", ctypes.c_double),
+        ("device_ms", ctypes.c_double),
     ]
 
     def to_dict(self):

@@ -34,9 +34,40 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(pvi.Desc) % 8 == 0
     assert ctypes.sizeof(pvi.Opts) == 72
     assert pvi.Opts.checkpoint_path.offset == 56
-    assert ctypes.sizeof(pvi.Result) == 96
+    assert ctypes.sizeof(pvi.Result) == 112
+    assert pvi.Result.vhat_shift.offset == 96 and pvi.Result.device_ms.offset == 104
     assert ctypes.sizeof(pvi.RolloutOpts) == 80
     assert pvi.RolloutOpts.product_kpis.offset == 64
+
+
+def test_binding_layouts_match_the_header_as_compiled(tmp_path):
+    """Sizes and field offsets of the result and option structs as a C compiler lays
+    them out from include/pvi.h, against the Python binding's ctypes structures."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fields = {"pvi_result": (pvi.Result, [k for k, _ in pvi.Result._fields_]),
+              "pvi_solve_opts": (pvi.Opts, [k for k, _ in pvi.Opts._fields_])}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "pvi.h"', "int main(void) {"]
+    for st, (_, names) in fields.items():
+        lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for n in names:
+            lines.append(f'printf("{st} {n} %zu\\n", offsetof({st}, {n}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(root, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                               text=True).stdout.splitlines():
+        st, key, val = line.split()
+        got[(st, key)] = int(val)
+    for st, (cls, names) in fields.items():
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for n in names:
+            assert got[(st, n)] == getattr(cls, n).offset, (st, n)
 
 
 def test_rollout_options_are_validated_before_the_device():

@@ -114,6 +114,26 @@ def vhat(V, res, gamma):
     return V + gamma / (1.0 - gamma) * 0.5 * (res["dmax"] + res["dmin"])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_result_vhat_shift_and_device_time(prec):
+    """vhat_shift is gamma/(1-gamma) times the mean of the last increments, and V plus
+    it lies within MacQueen's half-width gamma/(1-gamma) (dmax - dmin)/2 of V* (the
+    oracle's own bound midpoint at a span of 1e-11, which the span rule alone does not
+    bring near V*); device_ms is the solve's stream time, within its wall time."""
+    sc = SMALL[0]
+    g = sc["gamma"]
+    tight = Oracle(sc).solve(thr=1e-11)
+    star = vhat(tight["V"], tight, g)
+    m = pvi.mdp_create(sc)
+    res = pvi.vi_solve(m, precision=prec)
+    k = g / (1.0 - g)
+    assert res["vhat_shift"] == pytest.approx(k * 0.5 * (res["dmax"] + res["dmin"]), rel=1e-15)
+    half = k * 0.5 * (res["dmax"] - res["dmin"])
+    err = np.abs(pvi.value_get(m) + res["vhat_shift"] - star).max()
+    assert err <= half + 1e-9 * np.abs(star).max()
+    assert 0.0 < res["device_ms"] <= res["wall_ms"]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp32_wide"])
 @pytest.mark.parametrize("sc", SMALL, ids=IDS)
 def test_converged_fp32_schedule(sc, prec):
