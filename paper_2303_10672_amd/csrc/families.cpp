@@ -281,7 +281,7 @@ pvi_status tune_c(pvi_mdp* p) {
             for (int j = 3; j < 10; ++j) {
                 const bool fused = j == p->m - 1 && p->c_exogenous;
                 const bool fits = (size_t)(a ? 4 : 8) * R * rc * w <= 65536 &&
-                                  R * w <= (fused ? kCTopThreads : 1024);
+                                  R * w <= (fused ? kCFusedThreads : 1024);
                 p->c_lb[a][j] = fits ? w : 0;
             }
         }

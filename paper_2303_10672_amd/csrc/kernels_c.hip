@@ -28,6 +28,7 @@
 // lanes touch consecutive addresses.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cfloat>
 #include <cmath>
 
@@ -188,6 +189,49 @@ __device__ __forceinline__ void c_merge_rows(const VT* slab, const int (&zoff)[R
     }
 }
 
+// One row of a merge of level j >= 3 from its slab: terms y = 0, 1, .., r in order.
+template <typename VT, int LB, int RC, int r>
+__device__ __forceinline__ double c_merge_row(const VT* slab, const int (&zoff)[RC], ConstF64 w,
+                                              int R) {
+    constexpr int RS = RC * LB;
+    const ConstF64 wr = w + r * R;
+    double acc = 0.0;
+#pragma unroll
+    for (int y = 0; y <= r; ++y) acc = fma(wr[y], (double)slab[(r - y) * RS + zoff[y]], acc);
+    return acc;
+}
+
+// Rows r .. nr-1 of a lane's merge output (every row), four rows per block as above.
+template <typename VT, int LB, int RC, int r>
+__device__ __forceinline__ void c_merge_rows4(const VT* slab, const int (&zoff)[RC], ConstF64 w,
+                                              int R, int nr, VT* out, int64_t nblk) {
+    if constexpr (r + 3 < RC) {
+        if (r + 3 < nr) {
+            const double a0 = c_merge_row<VT, LB, RC, r>(slab, zoff, w, R);
+            const double a1 = c_merge_row<VT, LB, RC, r + 1>(slab, zoff, w, R);
+            const double a2 = c_merge_row<VT, LB, RC, r + 2>(slab, zoff, w, R);
+            const double a3 = c_merge_row<VT, LB, RC, r + 3>(slab, zoff, w, R);
+            out[(int64_t)r * nblk] = (VT)a0;
+            out[(int64_t)(r + 1) * nblk] = (VT)a1;
+            out[(int64_t)(r + 2) * nblk] = (VT)a2;
+            out[(int64_t)(r + 3) * nblk] = (VT)a3;
+            c_merge_rows4<VT, LB, RC, r + 4>(slab, zoff, w, R, nr, out, nblk);
+            return;
+        }
+    }
+    if constexpr (r < RC) {
+        if (r < nr) out[(int64_t)r * nblk] = (VT)c_merge_row<VT, LB, RC, r>(slab, zoff, w, R);
+    }
+    if constexpr (r + 1 < RC) {
+        if (r + 1 < nr)
+            out[(int64_t)(r + 1) * nblk] = (VT)c_merge_row<VT, LB, RC, r + 1>(slab, zoff, w, R);
+    }
+    if constexpr (r + 2 < RC) {
+        if (r + 2 < nr)
+            out[(int64_t)(r + 2) * nblk] = (VT)c_merge_row<VT, LB, RC, r + 2>(slab, zoff, w, R);
+    }
+}
+
 // Merge of life class j >= 3.  One workgroup per (tau, y_m, digits above j, block of
 // LB consecutive values of the digits below j); the slab in[r'][z_j][lo] for every
 // remaining count r' is staged in LDS once, and each lane (x_j, lo) produces
@@ -245,7 +289,10 @@ __global__ __launch_bounds__(1024) void c_merge_kernel(CDev p, int j, const void
     // weights Bin(y; r, q_j) at r R + y
     const ConstF64 w = (ConstF64)(p.binq + (size_t)j * R * R);
     VT* out = reinterpret_cast<VT*>(out_) + row0 * p.nblk + base + (int64_t)xz * nlo + l;
-    c_merge_rows<VT, LB, RC, 0>(slab, zoff, w, R, nr, p.top_only ? nr - 1 : 0, out, p.nblk);
+    if (p.top_only)
+        c_merge_rows<VT, LB, RC, 0>(slab, zoff, w, R, nr, nr - 1, out, p.nblk);
+    else
+        c_merge_rows4<VT, LB, RC, 0>(slab, zoff, w, R, nr, out, p.nblk);
 }
 
 // Orders a .. R-1 of one state's final sum (m >= 3), one order per template instance so
@@ -338,26 +385,127 @@ __global__ __launch_bounds__(256) void c_final_kernel(CDev p, const void* tin) {
     }
 }
 
+// Merges of life classes 2 and 3 in one kernel (m >= 5): T_3 straight from U, so T_2 is
+// never stored.  One workgroup per (y_m, tau, digits above 3), longest rows (small y_m)
+// first; it stages the whole cube U(tau, y_m, .., z_3, z_2, z_1) (R^3 values) in LDS once
+// and walks the blocks of LB consecutive values lo = (x_2, x_1).  Per block, lane
+// (z_3, lo) first forms its slab column
+//   T_2(z_3, lo; r') = sum_{y<=r'} Bin(y; r', q_2) U(z_3, c(x_2 + y), c(x_1 + r' - y))
+// for every r' (the first merge kernel's terms and order, rounded to the table type),
+// then, as lane (x_3, lo), the level-3 merge of the merge kernel from that slab, written
+// to T_3.  The cube is read from HBM once per sweep; the work per workgroup is
+// LDS-bound (one LDS read per term).
+// One row of the first merge from a U plane: terms y = 0, 1, .., r in order.
+template <typename VT, int RC, int r>
+__device__ __forceinline__ double c23_first_row(const VT* plane, const int (&o2)[RC],
+                                                const int (&o1)[RC], ConstF64 w, int R) {
+    const ConstF64 wr = w + r * R;
+    double acc = 0.0;
+#pragma unroll
+    for (int y = 0; y <= r; ++y) acc = fma(wr[y], (double)plane[o2[y] + o1[r - y]], acc);
+    return acc;
+}
+
+// Rows r .. nr-1 of the lane's first merge into its slab column (rows rs apart), four
+// rows per block where all four exist, so that their independent chains of
+// multiply-adds interleave; each row's own terms stay in order.
+template <typename VT, int RC, int r>
+__device__ __forceinline__ void c23_first_rows(const VT* plane, const int (&o2)[RC],
+                                               const int (&o1)[RC], ConstF64 w, int R, int nr,
+                                               VT* col, int rs) {
+    if constexpr (r + 3 < RC) {
+        if (r + 3 < nr) {
+            const double a0 = c23_first_row<VT, RC, r>(plane, o2, o1, w, R);
+            const double a1 = c23_first_row<VT, RC, r + 1>(plane, o2, o1, w, R);
+            const double a2 = c23_first_row<VT, RC, r + 2>(plane, o2, o1, w, R);
+            const double a3 = c23_first_row<VT, RC, r + 3>(plane, o2, o1, w, R);
+            col[r * rs] = (VT)a0;
+            col[(r + 1) * rs] = (VT)a1;
+            col[(r + 2) * rs] = (VT)a2;
+            col[(r + 3) * rs] = (VT)a3;
+            c23_first_rows<VT, RC, r + 4>(plane, o2, o1, w, R, nr, col, rs);
+            return;
+        }
+    }
+    if constexpr (r < RC) {
+        if (r < nr) col[r * rs] = (VT)c23_first_row<VT, RC, r>(plane, o2, o1, w, R);
+    }
+    if constexpr (r + 1 < RC) {
+        if (r + 1 < nr) col[(r + 1) * rs] = (VT)c23_first_row<VT, RC, r + 1>(plane, o2, o1, w, R);
+    }
+    if constexpr (r + 2 < RC) {
+        if (r + 2 < nr) col[(r + 2) * rs] = (VT)c23_first_row<VT, RC, r + 2>(plane, o2, o1, w, R);
+    }
+}
+
+template <typename VT, int LB, int RC>
+__global__ __launch_bounds__(kCFusedThreads) void c_merge23_kernel(CDev p, const void* u_,
+                                                                   void* out_) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (!p.extract && p.ctl->stop) return;
+    constexpr int RS = RC * LB;  // slab row stride
+    const int R = p.R, tid = threadIdx.x;
+    const int RR = R * R, R3 = RR * R;
+    VT* cube = reinterpret_cast<VT*>(smem);  // U[z_3][z_2][z_1]
+    VT* slab = cube + R3;                    // T_2[r'][z_3 < RC][LB]
+    const int nhi = (int)(p.nblk / R3);      // values of the digits above 3
+    int b = blockIdx.x;
+    const int ym = b / (p.P * nhi);
+    b -= ym * p.P * nhi;
+    const int tau = b / nhi, hi = b - tau * nhi;
+    const int nr = min(R - ym, p.alim - ym + 1);
+    if (nr <= 0) return;
+    {
+        const VT* U = reinterpret_cast<const VT*>(u_) + ((int64_t)tau * R + ym) * p.nblk +
+                      (int64_t)hi * R3;
+        for (int i = tid; i < R3; i += blockDim.x) cube[i] = U[i];
+    }
+    const int l = tid % LB, xz = tid / LB;  // lane: lo offset, digit 3 (z_3, then x_3)
+    int zoff[RC];                           // slab offset of column c(x_3 + y) in row 0
+#pragma unroll
+    for (int y = 0; y < RC; ++y) zoff[y] = min(xz + y, R - 1) * LB + l;
+    const ConstF64 w2 = (ConstF64)(p.binq + (size_t)2 * R * R);
+    const ConstF64 w3 = (ConstF64)(p.binq + (size_t)3 * R * R);
+    VT* T = reinterpret_cast<VT*>(out_) +
+            ((int64_t)tau * p.npair + p.pair_base[ym]) * p.nblk + (int64_t)hi * R3 +
+            (int64_t)xz * RR + l;
+    const int nlob = (RR + LB - 1) / LB;
+    __syncthreads();
+    for (int blk = 0; blk < nlob; ++blk) {
+        const int lo = blk * LB + l;
+        const bool ok = xz < R && lo < RR;
+        if (ok) {
+            const int x2 = lo / R, x1 = lo - x2 * R;
+            int o2[RC], o1[RC];  // plane offsets of c(x_2 + y) rows and c(x_1 + k) columns
+#pragma unroll
+            for (int y = 0; y < RC; ++y) {
+                o2[y] = min(x2 + y, R - 1) * R;
+                o1[y] = min(x1 + y, R - 1);
+            }
+            c23_first_rows<VT, RC, 0>(cube + xz * RR, o2, o1, w2, R, nr, slab + xz * LB + l,
+                                      RS);
+        }
+        __syncthreads();
+        if (ok) c_merge_rows4<VT, LB, RC, 0>(slab, zoff, w3, R, nr, T + blk * LB, p.nblk);
+        __syncthreads();
+    }
+}
+
 // Rows r .. nr-1 of the top merge for one y_m, each folded into the final sums at once:
 // T(r) = sum_{y<=r} Bin(y; r, q_{m-1}) slab(r - y, c(x_{m-1} + y)) (the merge kernel's
 // terms and order, rounded to the table type as a stored table would be), then
 // B[r] += Bin(y_m; y_m + r, p_m) T(r), B[r] being the running final sum of order y_m + r.
+// A compiler barrier after each row keeps the reads of later rows from being hoisted
+// above it (the rows' inputs would otherwise all be live at once and spill).
 template <typename VT, int LB, int RC, int r>
 __device__ __forceinline__ void c_top_rows(const VT* slab, const int (&zoff)[RC], ConstF64 w,
                                            ConstF64 bm, int R, int ym, int nr,
                                            double (&B)[RC]) {
     if constexpr (r < RC) {
         if (r < nr) {
-            constexpr int RS = RC * LB;
-            const ConstF64 wr = w + r * R;
-            double acc = 0.0;
-#pragma unroll
-            for (int y = 0; y <= r; ++y)
-                acc = fma(wr[y], (double)slab[(r - y) * RS + zoff[y]], acc);
-            B[r] = fma(bm[(ym + r) * R + ym], (double)(VT)acc, B[r]);
+            const double t = c_merge_row<VT, LB, RC, r>(slab, zoff, w, R);
+            B[r] = fma(bm[(ym + r) * R + ym], (double)(VT)t, B[r]);
         }
-        // each row completes before the next one's reads are issued, so the rows' inputs
-        // are never all live at once
         asm volatile("" ::: "memory");
         c_top_rows<VT, LB, RC, r + 1>(slab, zoff, w, bm, R, ym, nr, B);
     }
@@ -375,7 +523,7 @@ __device__ __forceinline__ void c_top_rows(const VT* slab, const int (&zoff)[RC]
 // shifts down by one.  Partial slot of a workgroup: its block id; slots past the grid
 // (the count is sized for the narrowest block) get neutral values.
 template <typename VT, int LB, int RC>
-__global__ __launch_bounds__(kCTopThreads) void c_top_final_kernel(CDev p, const void* in_,
+__global__ __launch_bounds__(kCFusedThreads) void c_top_final_kernel(CDev p, const void* in_,
                                                                   int nslots) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[64];
@@ -490,6 +638,68 @@ static int c_level_lb(const CDev& p, int j) {
     return tuned > 0 ? tuned : c_default_lb<VT>(p);
 }
 
+// LDS a workgroup may take on the current device (more than 64 KB on gfx950), cached
+// per device.
+static size_t c_device_lds() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess || v <= 0)
+            v = 65536;
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return (size_t)v;
+}
+
+// LDS of one workgroup of the fused first two merges: the U cube and the level-3 slab
+template <typename VT>
+static size_t c23_lds_for(const CDev& p, int lb) {
+    return sizeof(VT) * ((size_t)p.R * p.R * p.R + (size_t)p.R * c_rc_for(p.R) * lb);
+}
+
+// Whether the first two merges run fused at level-3 block width lb (m >= 5, where level 3
+// is not the top level): the cube and slab must fit the device's LDS.
+template <typename VT>
+static bool c_use23(const CDev& p, int lb) {
+    const int64_t r3 = (int64_t)p.R * p.R * p.R;
+    return p.m >= 5 && p.R <= 32 && p.R * lb <= kCFusedThreads &&
+           c23_lds_for<VT>(p, lb) <= c_device_lds() && p.nblk % r3 == 0 &&
+           (int64_t)p.R * p.P * (p.nblk / r3) <= 0x7fffffff;
+}
+
+template <typename VT, int LB>
+static hipError_t launch_merge23_rc(const CDev& p, const void* u, void* out, dim3 grid,
+                                    int threads, size_t lds, hipStream_t s) {
+    if (p.R <= 8)
+        hipLaunchKernelGGL((c_merge23_kernel<VT, LB, 8>), grid, dim3(threads), lds, s, p, u, out);
+    else if (p.R <= 16)
+        hipLaunchKernelGGL((c_merge23_kernel<VT, LB, 16>), grid, dim3(threads), lds, s, p, u, out);
+    else if (p.R <= 24)
+        hipLaunchKernelGGL((c_merge23_kernel<VT, LB, 24>), grid, dim3(threads), lds, s, p, u, out);
+    else
+        hipLaunchKernelGGL((c_merge23_kernel<VT, LB, 32>), grid, dim3(threads), lds, s, p, u, out);
+    return hipGetLastError();
+}
+
+// The fused first two merges at level-3 block width lb, U in `u`, T_3 into `out`.
+template <typename VT>
+static hipError_t launch_merge23(const CDev& p, const void* u, void* out, int lb, hipStream_t s) {
+    if (!c_use23<VT>(p, lb)) return hipErrorInvalidConfiguration;
+    const int64_t nhi = p.nblk / ((int64_t)p.R * p.R * p.R);
+    const dim3 grid((unsigned)(p.R * p.P * nhi));
+    const int threads = ((p.R * lb + 63) / 64) * 64;
+    const size_t lds = c23_lds_for<VT>(p, lb);
+    if (lb == 32) return launch_merge23_rc<VT, 32>(p, u, out, grid, threads, lds, s);
+    if (lb == 16) return launch_merge23_rc<VT, 16>(p, u, out, grid, threads, lds, s);
+    if (lb == 12) return launch_merge23_rc<VT, 12>(p, u, out, grid, threads, lds, s);
+    if (lb == 8) return launch_merge23_rc<VT, 8>(p, u, out, grid, threads, lds, s);
+    if (lb == 4) return launch_merge23_rc<VT, 4>(p, u, out, grid, threads, lds, s);
+    return hipErrorInvalidValue;
+}
+
 template <typename VT, int LB>
 static hipError_t launch_top_final_rc(const CDev& p, const void* in, int nslots, dim3 grid,
                                       int threads, size_t lds, hipStream_t s) {
@@ -513,7 +723,7 @@ static hipError_t launch_top_final(const CDev& p, const void* in, int lb, hipStr
     const int64_t nslots = c_partial_slots(p.P, nlo);
     const int threads = ((p.R * lb + 63) / 64) * 64;
     const size_t lds = c_lds_for<VT>(p, lb);
-    if (p.m < 4 || !p.exogenous || p.R > 32 || lds > 65536 || p.R * lb > kCTopThreads ||
+    if (p.m < 4 || !p.exogenous || p.R > 32 || lds > 65536 || p.R * lb > kCFusedThreads ||
         nslots > 0x7fffffff || nwg > nslots || nlo * p.R != p.nblk)
         return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)nwg);
@@ -584,6 +794,15 @@ static hipError_t launch_c_chain(const CDev& p, void* top, int jlast, hipStream_
         if (!p.exogenous && j == p.m - 1) {
             q.top_only = 1;
             out = top;
+        }
+        if (j == 2 && jlast >= 3 && c_use23<VT>(p, c_level_lb<VT>(p, 3))) {
+            // levels 2 and 3 in one kernel, T_3 into level 3's table
+            out = bufs[1];
+            if ((e = launch_merge23<VT>(p, in, out, c_level_lb<VT>(p, 3), s)) != hipSuccess)
+                return e;
+            in = out;
+            ++j;
+            continue;
         }
         if (j == 2) {
             const int threads = ((p.R * p.R + 63) / 64) * 64;
@@ -674,6 +893,13 @@ static hipError_t launch_level_once(const CDev& p, int j, int lb, hipStream_t s)
         q.v_out = p.t1;
         return launch_top_final<VT>(q, p.t0, lb, s);
     }
+    if (j == 3 && p.m >= 5) {
+        // level 3 runs fused with level 2 where it fits; otherwise the first merge is
+        // timed with it, so that every width is timed on the same work
+        if (c_use23<VT>(p, lb)) return launch_merge23<VT>(p, p.u, p.t1, lb, s);
+        hipError_t e = launch_c_chain<VT>(p, nullptr, 2, s);  // U into t0
+        if (e != hipSuccess) return e;
+    }
     return launch_merge_once<VT>(p, j, lb, s);
 }
 
@@ -690,7 +916,9 @@ static hipError_t tune_levels(const CDev& p, hipStream_t s, int32_t* lb_out) {
         float best = 1e30f;
         const bool fused = j == p.m - 1 && p.exogenous;
         for (int lb : {4, 8, 12, 16, 32}) {
-            if (c_lds_for<VT>(p, lb) > 65536 || p.R * lb > (fused ? kCTopThreads : 1024)) continue;
+            const bool fits = c_lds_for<VT>(p, lb) <= 65536 &&
+                              p.R * lb <= (fused ? kCFusedThreads : 1024);
+            if (!fits && !(j == 3 && c_use23<VT>(p, lb))) continue;
             if ((e = launch_level_once<VT>(p, j, lb, s)) != hipSuccess) break;  // warm-up
             if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
             for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_level_once<VT>(p, j, lb, s);

@@ -234,9 +234,10 @@ hipError_t tune_c_merge(const CDev& p, hipStream_t s, int32_t lb[2][10]);
 // (m >= 4, order-independent life): one per workgroup at the narrowest block width, 4
 // of the nlo = R^(m-2) low-digit values, for each of the P weekdays.
 inline int64_t c_partial_slots(int64_t P, int64_t nlo) { return P * ((nlo + 3) / 4); }
-// Most lanes (R x block width) of a fused top-merge workgroup: two wavefronts per SIMD,
-// so that its per-lane sums, prefetched rows and offsets fit in registers.
-constexpr int kCTopThreads = 512;
+// Most lanes (R x block width) of a workgroup of the fused scenario-C kernels (top merge
+// with the final sum; first two merges): two wavefronts per SIMD, so that their per-lane
+// sums and offsets fit in registers.
+constexpr int kCFusedThreads = 512;
 // kernels_b.hip
 hipError_t launch_backup_b(const BDev& p, int storage_fp32, int extract, hipStream_t s);
 
