@@ -105,6 +105,10 @@ static B1Dev make_b1dev(const pvi_mdp* p) {
     b.cb = std::min(16, b.Rb);
     while (b.cb > 1 && (int64_t)b.na1 * stride(b.cb) + 3 * (b.HA + 1) > 8192) --b.cb;
     b.cbp = stride(b.cb);
+    // PVI_B1_LANES=0 keeps the final kernel over lanes of x_a for every sweep (for tests:
+    // both give the same values)
+    const char* lanes = std::getenv("PVI_B1_LANES");
+    b.lanes_ab = lanes && std::strcmp(lanes, "0") == 0 ? 0 : 1;
     b.gamma = p->d.gamma;
     b.cva = p->d.c_var[0];
     b.cvb = p->d.c_var[1];
@@ -119,8 +123,10 @@ static B1Dev make_b1dev(const pvi_mdp* p) {
     b.j = d.b1j;
     b.jc = d.b1jc;
     b.rev = d.b1rev;
+    b.xb_order = d.b1xb;
     b.ctl = d.ctl;
     b.partials = d.partials;
+    b.nslots = family_tiles(p);
     b.pi = d.pi;
     b.gap = d.gap;
     return b;
@@ -219,8 +225,10 @@ int family_tiles(const pvi_mdp* p) {
             return (int)c_partial_slots(p->P, ipow(p->rad[0], p->m - 2));
         return (int)(p->P * ((ipow(p->rad[0], p->m - 1) + 255) / 256));
     }
-    if (p->family == PVI_FAMILY_SUBST2_L1)
-        return (int)(ipow(p->rad[1], p->m) * ((ipow(p->rad[0], p->m) + 255) / 256));
+    if (p->family == PVI_FAMILY_SUBST2_L1)  // either final kernel's grid fits
+        return (int)(ipow(p->rad[1], p->m) *
+                     std::max((ipow(p->rad[0], p->m) + 255) / 256,
+                              (ipow(p->rad[0], p->m - 1) + kB1Groups - 1) / kB1Groups));
     return 1;
 }
 
@@ -251,6 +259,33 @@ size_t family_extra_bytes(const pvi_mdp* p) {
                                  p->b1_pb.size() + p->b1_fb.size() +
                                  p->b1_j.size() + p->b1_jc.size() + p->b1_rev.size());
     return 0;
+}
+
+// The stock vectors x_b of product b ordered by their digit sum I_b (stable): the final
+// kernels take x_b in this order, so the workgroups that read one I_b slice of the Y
+// table (Ra Rb NA values) run together and find it in the caches.
+static std::vector<int32_t> b1_xb_order(const pvi_mdp* p) {
+    const int R = p->rad[1], m = p->m;
+    const int64_t nb = ipow(R, m);
+    std::vector<int32_t> order((size_t)nb);
+    std::vector<int> sum((size_t)nb);
+    for (int64_t x = 0; x < nb; ++x) {
+        int t = 0;
+        for (int64_t v = x, k = 0; k < m; ++k, v /= R) t += (int)(v % R);
+        sum[(size_t)x] = t;
+        order[(size_t)x] = (int32_t)x;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return sum[(size_t)a] < sum[(size_t)b]; });
+    return order;
+}
+
+// A demand table of product a followed by kB1Pad zeros: the final kernel over lanes of b's
+// orders reads it at x_1 + k for every x_1 < 16, also past a's largest issue.
+static std::vector<double> padded(const std::vector<double>& v) {
+    std::vector<double> out(v);
+    out.resize(v.size() + kB1Pad, 0.0);
+    return out;
 }
 
 template <class T>
@@ -463,14 +498,15 @@ pvi_status family_init(pvi_mdp* p) {
     if (p->family == PVI_FAMILY_SUBST2_L1) {
         if (hipMalloc((void**)&d.b1w, sizeof(double) * b1_w_entries(p)) != hipSuccess ||
             hipMalloc((void**)&d.b1y, sizeof(double) * b1_y_entries(p)) != hipSuccess ||
-            upload_vec(&d.b1pa, p->b1_pa1) != hipSuccess ||
-            upload_vec(&d.b1fa, p->b1_fa) != hipSuccess ||
-            upload_vec(&d.b1ga, p->b1_ga) != hipSuccess ||
+            upload_vec(&d.b1pa, padded(p->b1_pa1)) != hipSuccess ||
+            upload_vec(&d.b1fa, padded(p->b1_fa)) != hipSuccess ||
+            upload_vec(&d.b1ga, padded(p->b1_ga)) != hipSuccess ||
             upload_vec(&d.b1pb, p->b1_pb) != hipSuccess ||
             upload_vec(&d.b1fb, p->b1_fb) != hipSuccess ||
             upload_vec(&d.b1j, p->b1_j) != hipSuccess ||
             upload_vec(&d.b1jc, p->b1_jc) != hipSuccess ||
-            upload_vec(&d.b1rev, p->b1_rev) != hipSuccess)
+            upload_vec(&d.b1rev, p->b1_rev) != hipSuccess ||
+            upload_vec(&d.b1xb, b1_xb_order(p)) != hipSuccess)
             return fail(PVI_E_NOMEM, "lead-time-1 two-product table allocation failed");
     }
     return PVI_OK;
@@ -481,11 +517,12 @@ void family_free(pvi_mdp* p) {
     void* bufs[] = {d.z,    d.rexp0, d.epmf,  d.ecdf,  d.etail, d.rexp1, d.cu,  d.ct0,
                     d.ct1,  d.cpmf,  d.ccdf,  d.ctail, d.cr0,   d.cbinq,  d.cbinm, d.cpy,
                     d.cpr,  d.cpb, d.agroups, d.ctf, d.b1w, d.b1y, d.b1pa, d.b1fa, d.b1ga,
-                    d.b1pb, d.b1fb, d.b1j, d.b1jc, d.b1rev};
+                    d.b1pb, d.b1fb, d.b1j, d.b1jc, d.b1rev, d.b1xb};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     d.b1w = d.b1y = d.b1pa = d.b1fa = d.b1ga = d.b1pb = d.b1fb = d.b1j = d.b1jc = d.b1rev =
         nullptr;
+    d.b1xb = nullptr;
     d.z = d.rexp0 = d.epmf = d.ecdf = d.etail = d.rexp1 = nullptr;
     d.cu = d.ct0 = d.ct1 = d.ctf = nullptr;
     d.cpmf = d.ccdf = d.ctail = d.cr0 = d.cbinq = d.cbinm = nullptr;

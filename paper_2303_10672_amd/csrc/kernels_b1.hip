@@ -19,12 +19,17 @@
 // the max over the joint order (ties to the lowest index) and the span partials.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 
 #include "device_common.h"
 #include "pvi_internal.h"
 
 namespace pvi {
+
+// Pointer into the constant address space: loads through it whose address is the
+// same for every lane go through the scalar cache.
+typedef const __attribute__((address_space(4))) double* ConstF64B;
 
 namespace {
 
@@ -160,12 +165,14 @@ __global__ __launch_bounds__(256) void b1_final_kernel(B1Dev p) {
         wf[i] = p.fa[i];
         wg[i] = p.ga[i];
     }
-    // one-dimensional grid, remapped so each XCD takes contiguous runs of x_b: the
-    // workgroups of one x_b read the same W slice and, for equal I_b, the same Y rows,
-    // which then meet in that XCD's L2
+    // one-dimensional grid, remapped so each XCD takes contiguous runs of x_b, which come
+    // in order of their digit sum I_b: the workgroups of one x_b read the same W slice
+    // (in that XCD's L2), and all x_b of one I_b the same slice of Y, which stays in the
+    // caches while they run
     const int gx = (p.NA + (int)blockDim.x - 1) / (int)blockDim.x;
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
-    const int xb = lid / gx, bx = lid - xb * gx;
+    const int xbi = lid / gx, bx = lid - xbi * gx;
+    const int xb = p.xb_order[xbi];  // x_b by digit sum: equal I_b run together
     const int xa = bx * blockDim.x + threadIdx.x;
     const bool ok = xa < p.NA;
     const Digits da = digits_of(ok ? xa : 0, p.Ra, p.m);
@@ -239,11 +246,150 @@ __global__ __launch_bounds__(256) void b1_final_kernel(B1Dev p) {
     if (EXTRACT) return;
     block_reduce4(dmx, dmn, vmx, vmn, red);
     if (threadIdx.x == 0) {
-        double* pp = p.partials + 4 * ((size_t)xb * gx + bx);
-        pp[0] = dmx;
-        pp[1] = dmn;
-        pp[2] = vmx;
-        pp[3] = vmn;
+        // this workgroup's slot (xb gx + bx = lid), and neutral values past the grid
+        for (int k = lid; k < p.nslots; k += gridDim.x) {
+            double* pp = p.partials + 4 * (size_t)k;
+            const bool mine = k == lid;
+            pp[0] = mine ? dmx : -DBL_MAX;
+            pp[1] = mine ? dmn : DBL_MAX;
+            pp[2] = mine ? vmx : -DBL_MAX;
+            pp[3] = mine ? vmn : DBL_MAX;
+        }
+    }
+}
+
+// The same Q and max with the lanes over b's orders (a_max of both products below 16):
+// lane (path group, ab), where a path group is x_a without X_1 (all x_a = g Ra + X_1 share
+// its FIFO path), keeps 16 accumulators, one per X_1.  The lane walks its path once and
+// keeps the K + 1 point offsets in registers; per order of a it then reads one W value
+// (its order ab) per point from LDS, instead of the 16 orders' row that each of 16 lanes
+// read in b1_final_kernel, with the 16 weights P(D_a = X_1 + k), the same for the
+// whole wavefront, from the scalar cache.  The points run as straight-line code up to the
+// wavefront's longest path in steps of 8; points past a lane's own path add exact zeros.
+// The group's 16 x 16 sums then pass through LDS (in the W slice's space) so that lane l
+// holds those of X_1 = l for every ab: its Y values are then consecutive across the lanes
+// and it keeps the running maximum of its own state.  Terms, their order and the
+// comparisons are those of b1_final_kernel, so V is identical.  GB path groups per
+// workgroup; the W slice of one order of a, [g][ab] with rows of 17 doubles, sits in LDS.
+// KMAX > the longest path (m - 1)(Ra - 1).  FP64 and FP32 storage sweeps; the policy
+// extraction keeps b1_final_kernel.
+template <typename VT, int GB, int KMAX>
+__global__ __launch_bounds__(GB * 16) void b1_final_ab_kernel(B1Dev p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[64];
+    if (p.ctl->stop) return;
+    constexpr int X1 = 16, WSP = 17, TSP = 17;
+    double* ws = reinterpret_cast<double*>(smem);  // [na1][WSP], then [GB][16][TSP]
+    const int ngb = (p.na1 + GB - 1) / GB;         // workgroups per x_b
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int xbi = lid / ngb, bx = lid - xbi * ngb;
+    const int xb = p.xb_order[xbi];  // x_b by digit sum: equal I_b run together
+    const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;  // l: ab, then X_1
+    const int g0 = bx * GB + grp;
+    const bool gok = g0 < p.na1;
+    const Digits da = digits_of(gok ? g0 * p.Ra : 0, p.Ra, p.m);  // X_1 = 0: the path group
+    const int K = da.sum, Ib = digits_of(xb, p.Rb, p.m).sum;
+    // the path's points (LDS offsets of their W rows); past the path, the first point
+    int off[KMAX];
+    int offl = g0 * WSP;  // the last point, k = K
+    {
+        int o = g0;
+        PathWalk w{1, da.d[1], 1};
+        off[0] = g0 * WSP;
+#pragma unroll
+        for (int k = 1; k < KMAX; ++k) {
+            if (k <= K) o -= step(w, da, p.Ra);
+            off[k] = (k < K ? o : g0) * WSP;
+            if (k == K) offl = o * WSP;
+        }
+    }
+    // the wavefront's longest path: the straight-line points stop there
+    int kw = gok ? K : 0;
+    for (int o = 32; o > 0; o >>= 1) kw = max(kw, __shfl_xor(kw, o, 64));
+    kw = __builtin_amdgcn_readfirstlane(kw);
+    const ConstF64B fa = (ConstF64B)p.fa;
+    const ConstF64B pa = (ConstF64B)p.pa1;
+    const bool sok = gok && l < p.Ra;  // lane l's state x_a = g0 Ra + l exists
+    const double rev = sok ? p.rev[(size_t)(l + K) * p.HB + Ib] : 0.0;
+    double best = -DBL_MAX;
+    for (int aa = 0; aa < p.Ra; ++aa) {
+        __syncthreads();
+        for (int jb = 0; jb < p.Rb; ++jb) {
+            const double* src = p.w + ((int64_t)(aa * p.Rb + jb) * p.NB + xb) * p.na1;
+            for (int g = threadIdx.x; g < p.na1; g += blockDim.x) ws[g * WSP + jb] = src[g];
+        }
+        __syncthreads();
+        double acc[X1];
+        if (gok && l < p.Rb) {
+            const double* wl = ws + l;
+            {
+                // first point: P(D_a <= X_1), or all of the mass with no older stock
+                const double r0 = wl[off[0]];
+#pragma unroll
+                for (int i = 0; i < X1; ++i) acc[i] = (K > 0 ? fa[i] : 1.0) * r0;
+            }
+            // inner points k = 1 .. K-1: P(D_a = X_1 + k)
+#pragma unroll
+            for (int c = 1; c < KMAX; c += 8) {
+                if (c >= kw) break;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = c + u;
+                    if (k < KMAX) {
+                        const double r = k < K ? wl[off[k]] : 0.0;
+#pragma unroll
+                        for (int i = 0; i < X1; ++i) acc[i] = fma(pa[i + k], r, acc[i]);
+                    }
+                }
+            }
+            if (K > 0) {  // last point: P(D_a >= I_a)
+                const double r = wl[offl];
+                const double* wg = p.ga + K;
+#pragma unroll
+                for (int i = 0; i < X1; ++i) acc[i] = fma(wg[i], r, acc[i]);
+            }
+        }
+        __syncthreads();  // the W slice is read: its space takes the transposes
+        double* tile = ws + grp * 16 * TSP;  // [ab][X_1]
+        if (gok && l < p.Rb) {
+#pragma unroll
+            for (int i = 0; i < X1; ++i) tile[l * TSP + i] = acc[i];
+        }
+        __syncthreads();
+        if (sok) {
+            const double* yrow = p.y + ((int64_t)(aa * p.Rb) * p.HB + Ib) * p.NA +
+                                 (int64_t)g0 * p.Ra + l;
+            const int64_t ystride = (int64_t)p.HB * p.NA;  // next order of b
+            for (int ab = 0; ab < p.Rb; ++ab) {
+                const double yv = yrow[ab * ystride];
+                const double q =
+                    (-p.cva * aa - p.cvb * ab + rev) + p.gamma * (tile[ab * TSP + l] + yv);
+                if (q > best) best = q;
+            }
+        }
+    }
+    double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
+    if (sok) {
+        const int64_t s = ((int64_t)g0 * p.Ra + l) * p.NB + xb;
+        const double mu = sizeof(VT) == 4 ? p.ctl->mu : 0.0;
+        const VT o = (VT)(best - mu);
+        reinterpret_cast<VT*>(p.v_out)[s] = o;
+        const double out = (double)o;
+        const double dv = out - (double)reinterpret_cast<const VT*>(p.v_in)[s];
+        dmx = dmn = dv;
+        vmx = vmn = out;
+    }
+    block_reduce4(dmx, dmn, vmx, vmn, red);
+    if (threadIdx.x == 0) {
+        // this workgroup's slot, and neutral values in the slots past the grid
+        for (int k = lid; k < p.nslots; k += gridDim.x) {
+            double* pp = p.partials + 4 * (size_t)k;
+            const bool mine = k == lid;
+            pp[0] = mine ? dmx : -DBL_MAX;
+            pp[1] = mine ? dmn : DBL_MAX;
+            pp[2] = mine ? vmx : -DBL_MAX;
+            pp[3] = mine ? vmn : DBL_MAX;
+        }
     }
 }
 
@@ -271,7 +417,25 @@ static hipError_t launch_b1_t(const B1Dev& p, hipStream_t s) {
     const unsigned gx = (unsigned)((p.NA + 255) / 256);
     hipLaunchKernelGGL((b1_stage_y_kernel<VT>), dim3(gx, nact), dim3(256), ly, s, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((int64_t)gx * p.NB > 0x7fffffff) return hipErrorInvalidConfiguration;
+    if ((int64_t)gx * p.NB > 0x7fffffff || (int64_t)gx * p.NB > p.nslots)
+        return hipErrorInvalidConfiguration;
+    constexpr int GB = 16;  // path groups per workgroup of the lanes-over-orders kernel
+    // LDS: the W slice of one order of a, which then holds the GB 16 x 17 transposes
+    const size_t lab = sizeof(double) * (size_t)std::max(p.na1, GB * 16) * 17;
+    const int64_t nab = (int64_t)((p.na1 + GB - 1) / GB) * p.NB;
+    // the lanes-over-orders kernel where it was measured faster: 16 orders of each
+    // product (fewer leave lanes idle in both 16-wide dimensions)
+    const int kpath = (p.m - 1) * (p.Ra - 1);  // longest path: K points after the first
+    if (!EXTRACT && p.lanes_ab && p.Ra == 16 && p.Rb == 16 && kpath < 32 && lab <= 65536 &&
+        nab <= p.nslots) {
+        if (kpath < 16)
+            hipLaunchKernelGGL((b1_final_ab_kernel<VT, GB, 16>), dim3((unsigned)nab),
+                               dim3(GB * 16), lab, s, p);
+        else
+            hipLaunchKernelGGL((b1_final_ab_kernel<VT, GB, 32>), dim3((unsigned)nab),
+                               dim3(GB * 16), lab, s, p);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((b1_final_kernel<VT, EXTRACT>), dim3(gx * (unsigned)p.NB), dim3(256), lf,
                        s, p);
     return hipGetLastError();

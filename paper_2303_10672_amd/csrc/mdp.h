@@ -76,6 +76,7 @@ struct pvi_mdp {
         double *b1w = nullptr, *b1y = nullptr, *b1pa = nullptr, *b1fa = nullptr, *b1ga = nullptr,
                *b1pb = nullptr, *b1fb = nullptr, *b1j = nullptr, *b1jc = nullptr,
                *b1rev = nullptr;
+        int32_t* b1xb = nullptr;  // x_b in the final kernels' order (by digit sum I_b)
         int tiles = 0;
         size_t bytes = 0;
         std::vector<hipEvent_t> ev;

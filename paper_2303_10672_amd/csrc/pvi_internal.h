@@ -132,25 +132,33 @@ struct B1Dev {
     void* v_out;
     int32_t* pi;
     double* gap;
-    double* partials;     // [NB * ceil(NA / 256)][4]
+    double* partials;     // [nslots][4]
+    int32_t nslots;       // NB * max(ceil(NA / 256), ceil(na1 / kB1Groups))
     double* w;            // [Ra][Rb][NB][na1]: sum over h_b < I_b of V, per next A part
     double* y;            // [Ra][Rb][HB][NA]: the b-runs-out term per I_b
-    const double* pa1;    // [HA + 1] P(D_a = h)
-    const double* fa;     // [HA + 1] P(D_a <= h)
-    const double* ga;     // [HA + 1] P(D_a >= h)
+    const double* pa1;    // [HA + 1 + kB1Pad] P(D_a = h), zeros past HA
+    const double* fa;     // [HA + 1 + kB1Pad] P(D_a <= h), zeros past HA
+    const double* ga;     // [HA + 1 + kB1Pad] P(D_a >= h), zeros past HA
     const double* pb;     // [HB + 1] demand of b
     const double* fb;     // [HB + 1] its CDF
     const double* j;      // [HB][HA][HA] P(h_a, h_b = I_b | I_a, I_b)
     const double* jc;     // [HB][HA][HA] cumulative over h_a
     const double* rev;    // [HA][HB] expected one-day revenue
+    const int32_t* xb_order;  // [NB] x_b by digit sum: the final kernels' order
     Ctl* ctl;
     int32_t m, Ra, Rb, HA, HB, na1, nb1, NA, NB, extract;
     int32_t gw;           // stage W: values of the next A part per workgroup
     int32_t cb;           // final stage: orders of b per LDS chunk
     int32_t cbp;          // its LDS row stride in doubles (even, 2 mod 4)
+    int32_t lanes_ab;     // 1: the final sweeps use the kernel over lanes of b's orders
+                          // where it applies (0: b1_final_kernel everywhere)
     double gamma, cva, cvb;
 };
 hipError_t launch_backup_b1(const B1Dev& p, int storage_fp32, int extract, hipStream_t s);
+// The final kernel over lanes of b's orders: path groups (x_a without X_1) per workgroup,
+// and the zeros after a's demand tables (pa1, fa, ga) that its reads at x_1 + k need.
+constexpr int kB1Groups = 16;
+constexpr int kB1Pad = 48;
 hipError_t launch_b1_initial(const B1Dev& p, double* v, hipStream_t s);
 
 // ------------------------------------------------------------------ rollouts

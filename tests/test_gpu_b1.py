@@ -128,6 +128,24 @@ def test_paper_m3_sampled(exp, n):
     assert np.array_equal(pol[idx][clear], Q.argmax(axis=1)[clear])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_final_kernels_agree(prec):
+    """The final stage over lanes of b's orders (16 orders of each product) and the one
+    over lanes of x_a (PVI_B1_LANES=0) give bit-identical sweeps."""
+    import os
+    sc = W.scenario_b_paper(3, "1")
+    m = pvi.mdp_create(sc)
+    pvi.vi_solve(m, precision=prec, fixed_sweeps=3)
+    a = pvi.value_get(m)
+    os.environ["PVI_B1_LANES"] = "0"
+    try:
+        pvi.vi_solve(m, precision=prec, fixed_sweeps=3)
+        b = pvi.value_get(m)
+    finally:
+        del os.environ["PVI_B1_LANES"]
+    assert np.array_equal(a, b)
+
+
 def test_rollouts_match_oracle():
     sc = W.scenario_b1(m=2, a_max=(5, 4), means=(3.0, 2.0), rho=0.6, d_max=12)
     o = Oracle(sc)
