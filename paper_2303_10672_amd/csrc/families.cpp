@@ -535,15 +535,39 @@ void family_free(pvi_mdp* p) {
 // the separate single-workgroup span launch it would save.
 bool family_fused_span(const pvi_mdp*) { return false; }
 
+static hipError_t family_backup_launch(pvi_mdp* p, int fp32, int kahan, int extract, int fixed,
+                                       const void* vin, void* vout, hipStream_t s);
+
 hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, int fixed,
-                         const void* vin, void* vout, hipStream_t s) {
+                         const void* vin, void* vout, hipStream_t s, hipEvent_t ev0,
+                         hipEvent_t ev1) {
+    if (p->family == PVI_FAMILY_LEADTIME) {
+        ADev a = make_adev(p);
+        if (!a.lifo) {
+            // the FIFO kernel takes the events with its launch (no separate stream packets)
+            a.v_in = vin;
+            a.v_out = vout;
+            a.fixed = fixed;
+            return launch_backup_a(a, fp32, kahan, extract, s, ev0, ev1);
+        }
+    }
+    hipError_t e;
+    if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
+    if ((e = family_backup_launch(p, fp32, kahan, extract, fixed, vin, vout, s)) != hipSuccess)
+        return e;
+    return ev1 ? hipEventRecord(ev1, s) : hipSuccess;
+}
+
+// The backup of every family other than scenario-A FIFO (that one too, without events).
+static hipError_t family_backup_launch(pvi_mdp* p, int fp32, int kahan, int extract, int fixed,
+                                       const void* vin, void* vout, hipStream_t s) {
     if (p->family == PVI_FAMILY_LEADTIME) {
         ADev a = make_adev(p);
         a.v_in = vin;
         a.v_out = vout;
         a.fixed = fixed;
         if (a.lifo) return launch_backup_a_lifo(a, fp32, extract, s);
-        return launch_backup_a(a, fp32, kahan, extract, s);
+        return launch_backup_a(a, fp32, kahan, extract, s, nullptr, nullptr);
     }
     if (p->family == PVI_FAMILY_SUBST2) {
         BDev b = make_bdev(p);

@@ -17,7 +17,9 @@ void family_free(pvi_mdp* p);
 // extract = 1, the FP64 policy/gap extraction of vin.
 // fixed = 1: the sweep belongs to a fixed-length run (no stopping rule).
 hipError_t family_backup(pvi_mdp* p, int fp32, int kahan, int extract, int fixed,
-                         const void* vin, void* vout, hipStream_t s);
+                         const void* vin, void* vout, hipStream_t s, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);  // ev0/ev1: recorded at the backup's start
+                                                     // and end (kernel time), when given
 // True when the family's backup kernel reduces the span itself (its last
 // workgroup applies the stopping rule), so no separate span launch follows it.
 bool family_fused_span(const pvi_mdp* p);

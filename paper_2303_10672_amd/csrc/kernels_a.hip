@@ -23,6 +23,7 @@
 // Wavefront = G tiles (O, X_m..X_3) of one digit sum, R lanes per tile; the tile's
 // path list streams through LDS.  Ties in the max go to the lowest action.  No
 // atomics: every reduction is a fixed tree, so reruns are bit-identical.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -566,7 +567,7 @@ __global__ void to_f32_kernel(const double* v64, float* v32, double c, int64_t n
 // ------------------------------------------------------------------ launchers
 
 template <typename VT, bool KAHAN, bool EXTRACT, int RMAX, int RC = RMAX>
-static hipError_t launch_a_r(const ADev& p, hipStream_t s) {
+static hipError_t launch_a_r(const ADev& p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int lp_max = (p.m >= 2 ? (p.m - 2) * (p.R - 1) : 0) + p.r2;
     // lanes: G tiles of R lanes; staging: RMAX / 8 action slices of G x CH points
     if (p.G < 1 || p.G * p.R > 64 || p.CH < 1 || (RMAX / 8) * p.G * p.CH > 64 ||
@@ -579,36 +580,46 @@ static hipError_t launch_a_r(const ADev& p, hipStream_t s) {
     // G is read at u2 <= b + 2R and P, F at clamped indices
     if (p.tab < 2 * p.R + lp_max + 1 || p.tab < p.dmax + 2) return hipErrorInvalidValue;
     constexpr bool wide = RMAX == 32 || (KAHAN && RMAX >= 16);
-    if constexpr (wide)
-        hipLaunchKernelGGL((backup_a_wide_kernel<VT, KAHAN, RMAX, EXTRACT, RC>), dim3(p.ngroups),
-                           dim3(64), bytes, s, p);
-    else
-        hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT, RC>), dim3(p.ngroups),
-                           dim3(64), bytes, s, p);
+    // with events, they are recorded by the launch itself at the kernel's start and end
+    if constexpr (wide) {
+        if (ev0 || ev1)
+            hipExtLaunchKernelGGL((backup_a_wide_kernel<VT, KAHAN, RMAX, EXTRACT, RC>),
+                                  dim3(p.ngroups), dim3(64), (uint32_t)bytes, s, ev0, ev1, 0, p);
+        else
+            hipLaunchKernelGGL((backup_a_wide_kernel<VT, KAHAN, RMAX, EXTRACT, RC>),
+                               dim3(p.ngroups), dim3(64), bytes, s, p);
+    } else {
+        if (ev0 || ev1)
+            hipExtLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT, RC>), dim3(p.ngroups),
+                                  dim3(64), (uint32_t)bytes, s, ev0, ev1, 0, p);
+        else
+            hipLaunchKernelGGL((backup_a_kernel<VT, KAHAN, RMAX, EXTRACT, RC>), dim3(p.ngroups),
+                               dim3(64), bytes, s, p);
+    }
     return hipGetLastError();
 }
 
 template <typename VT, bool KAHAN, bool EXTRACT>
-static hipError_t launch_a_t(const ADev& p, hipStream_t s) {
+static hipError_t launch_a_t(const ADev& p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     // exact action counts of the paper's scenario A (order cap 10) and of the
     // order cap 20 instances; at R = 11 the FP64 variant fits three wavefronts per SIMD
-    if (p.R == 11) return launch_a_r<VT, KAHAN, EXTRACT, 16, 11>(p, s);
-    if (p.R == 21) return launch_a_r<VT, KAHAN, EXTRACT, 24, 21>(p, s);
-    if (p.R <= 8) return launch_a_r<VT, KAHAN, EXTRACT, 8>(p, s);
-    if (p.R <= 16) return launch_a_r<VT, KAHAN, EXTRACT, 16>(p, s);
-    if (p.R <= 24) return launch_a_r<VT, KAHAN, EXTRACT, 24>(p, s);
-    if (p.R <= 32) return launch_a_r<VT, KAHAN, EXTRACT, 32>(p, s);
+    if (p.R == 11) return launch_a_r<VT, KAHAN, EXTRACT, 16, 11>(p, s, ev0, ev1);
+    if (p.R == 21) return launch_a_r<VT, KAHAN, EXTRACT, 24, 21>(p, s, ev0, ev1);
+    if (p.R <= 8) return launch_a_r<VT, KAHAN, EXTRACT, 8>(p, s, ev0, ev1);
+    if (p.R <= 16) return launch_a_r<VT, KAHAN, EXTRACT, 16>(p, s, ev0, ev1);
+    if (p.R <= 24) return launch_a_r<VT, KAHAN, EXTRACT, 24>(p, s, ev0, ev1);
+    if (p.R <= 32) return launch_a_r<VT, KAHAN, EXTRACT, 32>(p, s, ev0, ev1);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_backup_a(const ADev& p, int storage_fp32, int acc_kahan, int extract,
-                           hipStream_t s) {
-    if (extract) return launch_a_t<double, false, true>(p, s);
+                           hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (extract) return launch_a_t<double, false, true>(p, s, ev0, ev1);
     if (storage_fp32) {
-        if (acc_kahan) return launch_a_t<float, true, false>(p, s);
-        return launch_a_t<float, false, false>(p, s);
+        if (acc_kahan) return launch_a_t<float, true, false>(p, s, ev0, ev1);
+        return launch_a_t<float, false, false>(p, s, ev0, ev1);
     }
-    return launch_a_t<double, false, false>(p, s);
+    return launch_a_t<double, false, false>(p, s, ev0, ev1);
 }
 
 hipError_t launch_span(Ctl* ctl, const double* partials, int tiles, int storage_fp32,

@@ -214,7 +214,7 @@ int slot_capacity(int threads, size_t lds_bytes);
 // LIFO issuing (p.lifo = 1, m >= 2): tiles (O, X_{m-1}..X_2), FP64 accumulation.
 hipError_t launch_backup_a_lifo(const ADev& p, int storage_fp32, int extract, hipStream_t s);
 hipError_t launch_backup_a(const ADev& p, int storage_fp32, int acc_kahan, int extract,
-                           hipStream_t s);
+                           hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Periodic stopping test after sweep i: v[j] = V_{i-j} for j = 0..P (P <= 7);
 // partials holds 2 doubles per block of the first kernel.
 struct PeriodicArgs {

@@ -287,9 +287,9 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
                                           : v64_slot(p, ring_slot(launched, 0, ph.ring));
                 void* vout = ph.fp32 ? (void*)d.v32[(launched + 1) & 1]
                                      : v64_slot(p, ring_slot(launched + 1, 0, ph.ring));
-                if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i], s));
-                PVI_HIP(family_backup(p, ph.fp32, ph.kahan, 0, ph.fixed > 0, vin, vout, s));
-                if (ph.time) PVI_HIP(hipEventRecord(d.ev[2 * i + 1], s));
+                PVI_HIP(family_backup(p, ph.fp32, ph.kahan, 0, ph.fixed > 0, vin, vout, s,
+                                      ph.time ? d.ev[2 * i] : nullptr,
+                                      ph.time ? d.ev[2 * i + 1] : nullptr));
                 if (!family_fused_span(p))
                     PVI_HIP(launch_span(d.ctl, d.partials, d.tiles, ph.fp32 ? 1 : 0,
                                         ph.fixed > 0, p->d.gamma, s));
