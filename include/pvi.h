@@ -62,6 +62,9 @@
  *    would leave fewer wavefronts than the device has SIMDs; results do not depend
  *    on the choice.  PVI_A_GROUP=<G>, 1 <= G <= floor(64 / R), read by mdp_create,
  *    fixes it (for tests).
+ *  - Scenario B as the paper runs it (lead time 1) with 16 orders of each product
+ *    sweeps with a final kernel over lanes of b's orders; PVI_B1_LANES=0 keeps the
+ *    kernel over lanes of a's stock (for tests: both give the same values).
  */
 #ifndef PVI_H
 #define PVI_H

@@ -385,16 +385,6 @@ __global__ __launch_bounds__(256) void c_final_kernel(CDev p, const void* tin) {
     }
 }
 
-// Merges of life classes 2 and 3 in one kernel (m >= 5): T_3 straight from U, so T_2 is
-// never stored.  One workgroup per (y_m, tau, digits above 3), longest rows (small y_m)
-// first; it stages the whole cube U(tau, y_m, .., z_3, z_2, z_1) (R^3 values) in LDS once
-// and walks the blocks of LB consecutive values lo = (x_2, x_1).  Per block, lane
-// (z_3, lo) first forms its slab column
-//   T_2(z_3, lo; r') = sum_{y<=r'} Bin(y; r', q_2) U(z_3, c(x_2 + y), c(x_1 + r' - y))
-// for every r' (the first merge kernel's terms and order, rounded to the table type),
-// then, as lane (x_3, lo), the level-3 merge of the merge kernel from that slab, written
-// to T_3.  The cube is read from HBM once per sweep; the work per workgroup is
-// LDS-bound (one LDS read per term).
 // One row of the first merge from a U plane: terms y = 0, 1, .., r in order.
 template <typename VT, int RC, int r>
 __device__ __forceinline__ double c23_first_row(const VT* plane, const int (&o2)[RC],
@@ -438,6 +428,15 @@ __device__ __forceinline__ void c23_first_rows(const VT* plane, const int (&o2)[
     }
 }
 
+// Merges of life classes 2 and 3 in one kernel (m >= 5): T_3 straight from U, so T_2 is
+// never stored.  One workgroup per (y_m, tau, digits above 3), longest rows (small y_m)
+// first; it stages the whole cube U(tau, y_m, .., z_3, z_2, z_1) (R^3 values) in LDS once
+// and walks the blocks of LB consecutive values lo = (x_2, x_1).  Per block, lane
+// (z_3, lo) first forms its slab column
+//   T_2(z_3, lo; r') = sum_{y<=r'} Bin(y; r', q_2) U(z_3, c(x_2 + y), c(x_1 + r' - y))
+// for every r' (the first merge kernel's terms and order, rounded to the table type),
+// then, as lane (x_3, lo), the level-3 merge of the merge kernel from that slab, written
+// to T_3.  The cube is read from HBM once per sweep; each term is one LDS read.
 template <typename VT, int LB, int RC>
 __global__ __launch_bounds__(kCFusedThreads) void c_merge23_kernel(CDev p, const void* u_,
                                                                    void* out_) {
