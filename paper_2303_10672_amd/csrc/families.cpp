@@ -76,6 +76,11 @@ static BDev make_bdev(const pvi_mdp* p) {
     b.e_cdf = p->dev.ecdf;
     b.e_tail = p->dev.etail;
     b.rexp1 = p->dev.rexp1;
+    b.tiled = p->b_tiled ? 1 : 0;
+    b.nw = (int)ipow(p->rad[0], p->m - 2);
+    b.ewp = p->b_ewp;
+    b.ppad = p->dev.bppad;
+    b.gpad = p->dev.bgpad;
     b.ctl = p->dev.ctl;
     b.partials = p->dev.partials;
     b.pi = p->dev.pi;
@@ -219,7 +224,8 @@ int family_tiles(const pvi_mdp* p) {
             return (int)(ipow(R, p->L - 1) * ipow(R, p->m - 2));
         return p->a_G > 0 ? (int)(p->a_groups.size() / p->a_G) : 1;  // one per tile group
     }
-    if (p->family == PVI_FAMILY_SUBST2) return (int)ipow(p->rad[1], p->m - 1);
+    if (p->family == PVI_FAMILY_SUBST2)  // one per (product-1 stock, middle product-0 digits)
+        return (int)(ipow(p->rad[1], p->m - 1) * (p->b_tiled ? ipow(p->rad[0], p->m - 2) : 1));
     if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
         if (p->m >= 4 && p->c_exogenous)  // top merge fused with the final sum
             return (int)c_partial_slots(p->P, ipow(p->rad[0], p->m - 2));
@@ -246,7 +252,8 @@ size_t family_extra_bytes(const pvi_mdp* p) {
                sizeof(int32_t) * p->a_groups.size();
     if (p->family == PVI_FAMILY_SUBST2)
         return sizeof(double) * ((size_t)p->b_rows * ipow(p->rad[1], p->m) + p->b_rexp0.size() +
-                                 3 * p->b_epmf.size() + p->b_rexp1.size() + p->pmf[0].size());
+                                 3 * p->b_epmf.size() + p->b_rexp1.size() + p->pmf[0].size() +
+                                 p->b_ppad.size() + p->b_gpad.size());
     if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
         const size_t ut = (size_t)p->ns * p->rad[0];
         const size_t tt = p->m >= 3 ? c_table_entries(p) : 0;
@@ -472,7 +479,9 @@ pvi_status family_init(pvi_mdp* p) {
             upload_vec(&d.epmf, p->b_epmf) != hipSuccess ||
             upload_vec(&d.ecdf, p->b_ecdf) != hipSuccess ||
             upload_vec(&d.etail, p->b_etail) != hipSuccess ||
-            upload_vec(&d.rexp1, p->b_rexp1) != hipSuccess)
+            upload_vec(&d.rexp1, p->b_rexp1) != hipSuccess ||
+            (p->b_tiled && (upload_vec(&d.bppad, p->b_ppad) != hipSuccess ||
+                            upload_vec(&d.bgpad, p->b_gpad) != hipSuccess)))
             return fail(PVI_E_NOMEM, "scenario B table allocation failed");
     }
     if (p->family == PVI_FAMILY_RUL_WEEKDAY) {
@@ -517,13 +526,13 @@ void family_free(pvi_mdp* p) {
     void* bufs[] = {d.z,    d.rexp0, d.epmf,  d.ecdf,  d.etail, d.rexp1, d.cu,  d.ct0,
                     d.ct1,  d.cpmf,  d.ccdf,  d.ctail, d.cr0,   d.cbinq,  d.cbinm, d.cpy,
                     d.cpr,  d.cpb, d.agroups, d.ctf, d.b1w, d.b1y, d.b1pa, d.b1fa, d.b1ga,
-                    d.b1pb, d.b1fb, d.b1j, d.b1jc, d.b1rev, d.b1xb};
+                    d.b1pb, d.b1fb, d.b1j, d.b1jc, d.b1rev, d.b1xb, d.bppad, d.bgpad};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     d.b1w = d.b1y = d.b1pa = d.b1fa = d.b1ga = d.b1pb = d.b1fb = d.b1j = d.b1jc = d.b1rev =
         nullptr;
     d.b1xb = nullptr;
-    d.z = d.rexp0 = d.epmf = d.ecdf = d.etail = d.rexp1 = nullptr;
+    d.z = d.rexp0 = d.epmf = d.ecdf = d.etail = d.rexp1 = d.bppad = d.bgpad = nullptr;
     d.cu = d.ct0 = d.ct1 = d.ctf = nullptr;
     d.cpmf = d.ccdf = d.ctail = d.cr0 = d.cbinq = d.cbinm = nullptr;
     d.cpy = d.cpr = d.cpb = nullptr;

@@ -159,11 +159,13 @@ __global__ __launch_bounds__(1024) void subst_stage2_kernel(BDev p) {
                         acc[2 * i + 1] = fma(pr, z.y, acc[2 * i + 1]);
                     }
                 }
-                const double base = -p.cvar0 * a0 + p.rexp0[stock0];
+                // the order costs as explicit fused multiply-adds, so that no kernel
+                // depends on how the compiler contracts them
+                const double base = fma(-p.cvar0, (double)a0, p.rexp0[stock0]);
 #pragma unroll
                 for (int a1 = 0; a1 < PVI_B_R1MAX; ++a1) {
                     if (a1 < R1) {
-                        const double q = base - p.cvar1 * a1 + acc[a1];
+                        const double q = fma(-p.cvar1, (double)a1, base) + acc[a1];
                         if (q > best) {
                             second = best;
                             best = q;
@@ -208,13 +210,296 @@ __global__ __launch_bounds__(1024) void subst_stage2_kernel(BDev p) {
     }
 }
 
+// Pointer into the constant address space: loads through it whose address is the
+// same for every lane go through the scalar cache.
+typedef const __attribute__((address_space(4))) double* ConstF64B;
+
+constexpr int kBX = 16;  // oldest-digit sums per lane in the tiled kernels (R0, R1 <= 16)
+
+// Depletes k units from the younger digits v[1..m-1] oldest first and returns the
+// offset of what is left (digit j weighs radix^(j-1)).
+__device__ __forceinline__ int b_path_offset(const int (&v)[8], int m, int radix, int k) {
+    int r = k, off = 0, pw = 1;
+#pragma unroll
+    for (int j = 1; j < 8; ++j) {
+        if (j <= m - 1) {
+            const int take = min(r, v[j]);
+            r -= take;
+            off += (v[j] - take) * pw;
+            pw *= radix;
+        }
+    }
+    return off;
+}
+
+// Stage 1, tiled: one wavefront per (row, four middle-digit indices bi of product
+// 1), lane (slot, a1).  A lane walks the FIFO path of its younger digits
+// (B_2..B_{m-1}, a1) once and keeps one sum per oldest digit x1, so every value read
+// from V serves all x1; the weights P_u(x1 + k) of the points before the path's end
+// do not depend on the lane and come through the scalar cache.  Per cell the terms
+// and their order are those of subst_stage1_kernel; the terms that kernel skips
+// (total demand beyond emax) enter here with weight zero, which leaves every sum
+// unchanged.
+template <typename VT, int KB>
+__global__ __launch_bounds__(64) void subst_stage1_tiled_kernel(BDev p) {
+    if (p.ctl->stop && !p.extract) return;
+    const int R1 = p.r1, m = p.m;
+    const int nbi = p.nb / R1;  // middle digits B_2..B_{m-1}
+    const int nq = (nbi + 3) >> 2;
+    const int row = blockIdx.x / nq, q = blockIdx.x - row * nq;
+    const int lane = threadIdx.x, a1l = lane & 15, bil = q * 4 + (lane >> 4);
+    // lanes past the orders or the digit range repeat a real cell and store nothing
+    const bool live = a1l < R1 && bil < nbi;
+    const int a1 = min(a1l, R1 - 1), bi = min(bil, nbi - 1);
+    const int i0n = row < p.na ? row : 0;
+    const int u = row < p.na ? 0 : row - p.na + 1;
+    int v[8];
+    int K = 0;
+    {
+        int rest = bi;
+#pragma unroll
+        for (int j = 1; j < 8; ++j) {
+            if (j <= m - 2) {
+                v[j] = rest % R1;
+                rest /= R1;
+            } else {
+                v[j] = j == m - 1 ? a1 : 0;
+            }
+            K += v[j];
+        }
+    }
+    const VT* Vr = reinterpret_cast<const VT*>(p.v_in) + (int64_t)i0n * p.nb;
+    const ConstF64B Fu = (ConstF64B)(p.e_cdf + (size_t)u * p.ew);
+    const ConstF64B Pu = (ConstF64B)(p.ppad + (size_t)u * p.ewp);
+    const double* Gu = p.gpad + (size_t)u * p.ewp;
+    auto load = [&](int k) { return (double)Vr[b_path_offset(v, m, R1, k)]; };
+
+    double acc[kBX];
+    {
+        const double v0 = load(0);
+#pragma unroll
+        for (int x1 = 0; x1 < kBX; ++x1) {
+            acc[x1] = 0.0;
+            const double w = K == 0 ? 1.0 : Fu[min(x1, p.emax)];
+            acc[x1] = fma(w, v0, acc[x1]);
+        }
+    }
+    auto step = [&](int k, double vk) {
+        if (k < K) {
+#pragma unroll
+            for (int x1 = 0; x1 < kBX; ++x1) acc[x1] = fma(Pu[x1 + k], vk, acc[x1]);
+        }
+    };
+    if constexpr (KB > 0) {
+        // points 1 .. K - 1 with K < KB: every value of the path is loaded before the
+        // first is used (any k gives an offset inside the row), so a wavefront waits
+        // for memory once
+        double pv[KB];
+#pragma unroll
+        for (int k = 1; k < KB; ++k) pv[k] = load(k);
+#pragma unroll
+        for (int k = 1; k < KB; ++k) step(k, pv[k]);
+    } else {
+        // longer paths: up to the wavefront's longest, values loaded four points ahead
+        const int kw = (int)wave_max((double)K);
+        double va = load(1), vb = load(2), vc = load(3), vd = load(4);
+        for (int k = 1; k < kw; k += 4) {
+            step(k, va);
+            va = load(k + 4);
+            if (k + 1 >= kw) break;
+            step(k + 1, vb);
+            vb = load(k + 5);
+            if (k + 2 >= kw) break;
+            step(k + 2, vc);
+            vc = load(k + 6);
+            if (k + 3 >= kw) break;
+            step(k + 3, vd);
+            vd = load(k + 7);
+        }
+    }
+    // the path's end: every younger unit gone, weight P_u(e >= x1 + K)
+    if (K > 0) {
+        const double vK = (double)Vr[0];
+#pragma unroll
+        for (int x1 = 0; x1 < kBX; ++x1) acc[x1] = fma(Gu[x1 + K], vK, acc[x1]);
+    }
+    if (!live) return;
+    double* zr = p.z + (int64_t)row * p.nb * R1 + (int64_t)bi * R1 * R1 + a1;
+    const double* rx = p.rexp1 + (size_t)u * p.sw + K;
+#pragma unroll
+    for (int x1 = 0; x1 < kBX; ++x1)
+        if (x1 < R1) zr[x1 * R1] = rx[x1] + p.gamma * acc[x1];
+}
+
+// Stage 2, tiled: one workgroup per (product-1 stock index ib, middle product-0 digits
+// w); lane (a0, a1) of a 16 x 16 grid.  With the younger product-0 digits (w, a0)
+// fixed, product-0 demand x0 + j lands on point j of one list of Z rows for every
+// oldest digit x0 (j <= K depletes the younger units, beyond it j - K units are
+// unmet), so a lane loads the Z entries of its column a1 at those points once and
+// forms the sums of all x0 from them.  Each sum takes its terms in the order of
+// subst_stage2_kernel (d0 ascending), so the values are the same; the maximum over
+// a1 is a 16-lane transpose-reduction, over a0 one over four lane groups and the
+// four wavefronts.
+template <typename VT, int J>
+__global__ __launch_bounds__(256) void subst_stage2_tiled_kernel(BDev p) {
+    constexpr int TS = kBX + 2;  // row stride of the Q tile (16-byte rows, spread banks)
+    __shared__ int32_t roff[kBX * J];
+    __shared__ __align__(16) double qt[kBX * kBX * TS];  // [a0][a1][x0]
+    __shared__ double red[4 * kBX];
+    if (p.ctl->stop) return;
+    const int grp = xcd_remap(blockIdx.x, gridDim.x);
+    const int ib = grp / p.nw, wi = grp - ib * p.nw;
+    const int R0 = p.r0, R1 = p.r1, m = p.m, tid = threadIdx.x;
+    // middle product-0 digits w[1..m-2] = A_2..A_{m-1}
+    int w[8];
+    int held = 0;
+    {
+        int rest = wi;
+#pragma unroll
+        for (int j = 1; j < 8; ++j) {
+            w[j] = 0;
+            if (j <= m - 2) {
+                w[j] = rest % R0;
+                rest /= R0;
+            }
+            held += w[j];
+        }
+    }
+    // element offset of the Z row at point j of tile a0 (rows of nb * R1 entries)
+    const int zrow = p.nb * R1;
+    for (int e = tid; e < kBX * J; e += blockDim.x) {
+        const int t = e / J, j = e - t * J;
+        int row = 0;
+        if (t < R0 && j <= p.d0max) {
+            const int K = held + t;
+            if (j <= K) {
+                int v[8];
+#pragma unroll
+                for (int d = 1; d < 8; ++d) v[d] = d == m - 1 ? t : w[d];
+                row = b_path_offset(v, m, R0, j);
+            } else {
+                row = p.na + (j - K) - 1;
+            }
+        }
+        roff[e] = row * zrow;
+    }
+    __syncthreads();
+
+    const int wv = tid >> 6, l16 = tid & 15;
+    const int a0 = min(wv * 4 + ((tid >> 4) & 3), R0 - 1), a1 = min(l16, R1 - 1);
+    const double* zc = p.z + (int64_t)ib * R1 + a1;
+    double zr[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) zr[j] = zc[roff[a0 * J + j]];
+
+    // demand values past d0max (up to J) add terms of weight zero, which leave the
+    // sums unchanged
+    const ConstF64B P0 = (ConstF64B)p.pmf0;
+    const int d0max = p.d0max;
+    double acc[kBX];
+#pragma unroll
+    for (int x0 = 0; x0 < kBX; ++x0) acc[x0] = 0.0;
+#pragma unroll
+    for (int d0 = 0; d0 < J; ++d0) {
+        const double pr = d0 <= d0max ? P0[min(d0, d0max)] : 0.0;
+#pragma unroll
+        for (int x0 = 0; x0 < kBX; ++x0) acc[x0] = fma(pr, zr[d0 > x0 ? d0 - x0 : 0], acc[x0]);
+    }
+    // lanes past the orders repeat the Q values of a real action, which leaves every
+    // maximum unchanged; entries x0 >= R0 are not states and are never stored.  The
+    // Q values go to LDS as [a0][a1][x0]; thread (a0, x0) then takes the maximum over
+    // a1, and over a0 two lane exchanges and the four wavefronts follow.
+    {
+        double2* row = reinterpret_cast<double2*>(qt + (size_t)(tid >> 4) * kBX * TS + l16 * TS);
+#pragma unroll
+        for (int x0 = 0; x0 < kBX; x0 += 2) {
+            const double q0 = fma(-p.cvar1, (double)a1,
+                                  fma(-p.cvar0, (double)a0, p.rexp0[min(x0, R0 - 1) + held + a0])) +
+                              acc[x0];
+            const double q1 = fma(-p.cvar1, (double)a1,
+                                  fma(-p.cvar0, (double)a0,
+                                      p.rexp0[min(x0 + 1, R0 - 1) + held + a0])) +
+                              acc[x0 + 1];
+            row[x0 / 2] = make_double2(q0, q1);
+        }
+    }
+    __syncthreads();
+    double best;
+    {
+        const double* col = qt + (size_t)(tid >> 4) * kBX * TS + l16;
+        best = col[0];
+#pragma unroll
+        for (int i = 1; i < kBX; ++i) best = fmax(best, col[i * TS]);
+    }
+    best = fmax(best, __shfl_xor(best, 16, 64));
+    best = fmax(best, __shfl_xor(best, 32, 64));
+    if ((tid & 63) < kBX) red[wv * kBX + l16] = best;
+    __syncthreads();
+    if (tid >= 64) return;
+    const double mu = sizeof(VT) == 4 ? p.ctl->mu : 0.0;
+    double dmx = -DBL_MAX, dmn = DBL_MAX, vmx = -DBL_MAX, vmn = DBL_MAX;
+    if (tid < R0) {
+        const double b = fmax(fmax(red[tid], red[kBX + tid]), fmax(red[2 * kBX + tid], red[3 * kBX + tid]));
+        const int64_t s = (int64_t)(tid + R0 * wi) * p.nb + ib;
+        const VT o = (VT)(b - mu);
+        reinterpret_cast<VT*>(p.v_out)[s] = o;
+        const double out = (double)o;
+        const double dv = out - (double)reinterpret_cast<const VT*>(p.v_in)[s];
+        dmx = dv;
+        dmn = dv;
+        vmx = out;
+        vmn = out;
+    }
+    dmx = wave_max(dmx);
+    dmn = wave_min(dmn);
+    vmx = wave_max(vmx);
+    vmn = wave_min(vmn);
+    if (tid == 0) {
+        double* pp = p.partials + 4 * (size_t)grp;
+        pp[0] = dmx;
+        pp[1] = dmn;
+        pp[2] = vmx;
+        pp[3] = vmn;
+    }
+}
+
 template <typename VT, bool EXTRACT>
 static hipError_t launch_b_t(const BDev& p, hipStream_t s) {
-    const int64_t n1 = (int64_t)p.rows * p.nb * p.r1;
-    hipLaunchKernelGGL((subst_stage1_kernel<VT>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0,
-                       s, p);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (p.tiled) {
+        const dim3 grid1((unsigned)(p.rows * ((p.nb / p.r1 + 3) / 4)));
+        // paths of at most (m - 1)(R1 - 1) younger units: loaded whole when that fits
+        const int kmax = (p.m - 1) * (p.r1 - 1);
+        if (kmax < 16)
+            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 16>), grid1, dim3(64), 0, s, p);
+        else if (kmax < 32)
+            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 32>), grid1, dim3(64), 0, s, p);
+        else
+            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 0>), grid1, dim3(64), 0, s, p);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (!EXTRACT) {  // policy extraction keeps the per-state kernel (best, second, arg)
+            const dim3 grid((unsigned)(p.nb * p.nw));
+            // the fewest demand values J >= d0max + 1 of the compiled widths
+            if (p.d0max < 8)
+                hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 8>), grid, dim3(256), 0, s, p);
+            else if (p.d0max < 16)
+                hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 16>), grid, dim3(256), 0, s, p);
+            else if (p.d0max == 20)  // demand folded at 20, the paper's truncation
+                hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 21>), grid, dim3(256), 0, s, p);
+            else if (p.d0max < 24)
+                hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 24>), grid, dim3(256), 0, s, p);
+            else
+                hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, PVI_B_JMAX>), grid, dim3(256), 0,
+                                   s, p);
+            return hipGetLastError();
+        }
+    } else {
+        const int64_t n1 = (int64_t)p.rows * p.nb * p.r1;
+        hipLaunchKernelGGL((subst_stage1_kernel<VT>), dim3((unsigned)((n1 + 255) / 256)), dim3(256),
+                           0, s, p);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const size_t bytes = sizeof(double) * ((size_t)p.rows * p.r1pad + p.d0max + 1 + 64);
     if (bytes > 65536) return hipErrorInvalidConfiguration;
     // four lanes per product-0 state; at most 1024 lanes

@@ -243,6 +243,24 @@ static void build_b_tables(pvi_mdp* p) {
             p->b_rexp1[(size_t)u * p->b_sw + s1] = p->d.c_rev[1] * r;
         }
     }
+    // the tiled sweep kernels keep one accumulator per oldest digit (at most 16 per
+    // product) and every product-0 demand value in registers (at most PVI_B_JMAX)
+    const char* tiled = std::getenv("PVI_B_TILED");
+    p->b_tiled = !(tiled && std::strcmp(tiled, "0") == 0) && m >= 2 && R0 <= 16 &&
+                 R1 <= PVI_B_R1MAX && d0 + 1 <= PVI_B_JMAX &&
+                 (double)p->b_rows * std::pow((double)R1, m) < 2147483647.0;
+    if (p->b_tiled) {
+        // x1 + k for x1 < 16 and k up to the (m - 1)(R1 - 1) younger units, or up to
+        // the 32 points the stage-1 kernel unrolls
+        p->b_ewp = (int)ew + 16 + std::max((m - 1) * (R1 - 1), 32);
+        p->b_ppad.assign((size_t)(d0 + 1) * p->b_ewp, 0.0);
+        p->b_gpad.assign((size_t)(d0 + 1) * p->b_ewp, 0.0);
+        for (int u = 0; u <= d0; ++u)
+            for (size_t e = 0; e < ew; ++e) {
+                p->b_ppad[(size_t)u * p->b_ewp + e] = p->b_epmf[u * ew + e];
+                p->b_gpad[(size_t)u * p->b_ewp + e] = p->b_etail[u * ew + e];
+            }
+    }
     // stage 1: sum over the FIFO path of each (row, product-1 part); stage 2: d0 terms
     int64_t ex1 = 0;
     for (int ib = 0; ib < nb; ++ib)

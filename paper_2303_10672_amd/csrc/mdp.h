@@ -33,6 +33,11 @@ struct pvi_mdp {
     // Scenario B kernel tables
     int b_rows = 0, b_emax = 0, b_ew = 0, b_sw = 0;
     std::vector<double> b_rexp0, b_epmf, b_ecdf, b_etail, b_rexp1;
+    // tiled sweep kernels (shape within their compile-time bounds): rows of the
+    // product-1 demand PMF and tail, zero-padded to b_ewp entries
+    bool b_tiled = false;
+    int b_ewp = 0;
+    std::vector<double> b_ppad, b_gpad;
 
     // Scenario C kernel tables
     bool c_exogenous = true;
@@ -68,7 +73,7 @@ struct pvi_mdp {
         double *pmf = nullptr, *cdf = nullptr, *tail = nullptr, *r0 = nullptr;
         int32_t* agroups = nullptr;
         double *z = nullptr, *rexp0 = nullptr, *epmf = nullptr, *ecdf = nullptr,
-               *etail = nullptr, *rexp1 = nullptr;
+               *etail = nullptr, *rexp1 = nullptr, *bppad = nullptr, *bgpad = nullptr;
         void *cu = nullptr, *ct0 = nullptr, *ct1 = nullptr, *ctf = nullptr;
         double *cpmf = nullptr, *ccdf = nullptr, *ctail = nullptr, *cr0 = nullptr,
                *cbinq = nullptr, *cbinm = nullptr;

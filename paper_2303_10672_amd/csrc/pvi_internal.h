@@ -75,6 +75,7 @@ struct ADev {
 
 // ------------------------------------------------------------------ family B
 #define PVI_B_R1MAX 16  // product-1 order choices per kernel row (a_max[1] <= 15)
+#define PVI_B_JMAX 32   // tiled scenario-B kernels: product-0 demand values (d_max[0] <= 31)
 struct BDev {
     const void* v_in;
     void* v_out;
@@ -88,8 +89,13 @@ struct BDev {
     const double* e_cdf;
     const double* e_tail;
     const double* rexp1;  // [d0max+1][sw]: c_rev1 E[min(e, stock1) | u0]
+    const double* ppad;   // [d0max+1][ewp]: e_pmf rows, zero past emax (tiled kernels)
+    const double* gpad;   // [d0max+1][ewp]: e_tail rows, zero past emax
     Ctl* ctl;
     int32_t m, r0, r1, r1pad, na, nb, rows, d0max, emax, ew, sw, extract;
+    int32_t tiled;  // sweeps use the tiled kernels (one partial per (ib, middle digits))
+    int32_t nw;     // r0^(m-2): middle product-0 digit combinations
+    int32_t ewp;
     double gamma, cvar0, cvar1;
 };
 

@@ -66,3 +66,43 @@ def test_converged(sc):
         assert relerr(vhat(pvi.value_get(m), res, g), vhat(ref["V"], ref, g)) < 1e-5
         pol, _ = pvi.policy_get(m)
         assert np.array_equal(pol[clear], tight["pi"][clear])
+
+
+WIDE = SMALL + [
+    W.scenario_b(m=3, a_max=(14, 14), d_max=(20, 20), means=(5.0, 4.0), rho=0.5),
+    W.scenario_b(m=2, a_max=(15, 9), d_max=(26, 11), means=(9.0, 3.0), rho=0.8),
+]
+
+
+@pytest.mark.parametrize("sc", WIDE, ids=IDS + ["R15-d20", "R16-d26"])
+def test_tiled_kernels_match_per_cell_kernels(sc, monkeypatch):
+    """The tiled stage kernels (one pass over each FIFO path for every oldest digit)
+    and the per-cell kernels (PVI_B_TILED=0) take the same terms in the same order:
+    one FP64 and one FP32 backup, three fixed sweeps and a converged solve give
+    bit-identical values and policies."""
+    o = Oracle(sc)
+    V = W.random_values(o.n_states, seed=12, scale=5.0, offset=40.0)
+    runs = []
+    for tiled in ("0", None):
+        if tiled is None:
+            monkeypatch.delenv("PVI_B_TILED", raising=False)
+        else:
+            monkeypatch.setenv("PVI_B_TILED", tiled)
+        m = pvi.mdp_create(sc)
+        monkeypatch.delenv("PVI_B_TILED", raising=False)
+        out = [pvi.vi_backup(m, V, "fp64"), pvi.vi_backup(m, V, "fp32")]
+        pvi.vi_solve(m, precision="fp64", fixed_sweeps=3)
+        out.append(pvi.value_get(m))
+        res = pvi.vi_solve(m, precision="fp64")
+        out.append((res["sweeps_fp64"], pvi.value_get(m), pvi.policy_get(m)))
+        res = pvi.vi_solve(m, precision="fp32")
+        out.append((res["sweeps_fp32"], res["sweeps_fp64"], pvi.value_get(m)))
+        runs.append(out)
+    (a64, a32, a3, (an, aV, ap), (af, ad, aW)), (b64, b32, b3, (bn, bV, bp), (bf, bd, bW)) = runs
+    for x, y in zip(a64 + a32, b64 + b32):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a3, b3)
+    assert an == bn and np.array_equal(aV, bV)
+    assert np.array_equal(ap[0], bp[0]) and np.array_equal(ap[1], bp[1])
+    assert (af, ad) == (bf, bd) and np.array_equal(aW, bW)
+    assert relerr(a64[0], o.sweep(V)[0]) < 1e-12
