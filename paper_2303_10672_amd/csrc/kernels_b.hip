@@ -218,11 +218,13 @@ constexpr int kBX = 16;  // oldest-digit sums per lane in the tiled kernels (R0,
 
 // Depletes k units from the younger digits v[1..m-1] oldest first and returns the
 // offset of what is left (digit j weighs radix^(j-1)).
+// M > 0: m known at compile time (no per-digit branches).
+template <int M = 0>
 __device__ __forceinline__ int b_path_offset(const int (&v)[8], int m, int radix, int k) {
     int r = k, off = 0, pw = 1;
 #pragma unroll
-    for (int j = 1; j < 8; ++j) {
-        if (j <= m - 1) {
+    for (int j = 1; j < (M > 0 ? M : 8); ++j) {
+        if (M > 0 || j <= m - 1) {
             const int take = min(r, v[j]);
             r -= take;
             off += (v[j] - take) * pw;
@@ -240,10 +242,10 @@ __device__ __forceinline__ int b_path_offset(const int (&v)[8], int m, int radix
 // and their order are those of subst_stage1_kernel; the terms that kernel skips
 // (total demand beyond emax) enter here with weight zero, which leaves every sum
 // unchanged.
-template <typename VT, int KB>
+template <typename VT, int KB, int M>
 __global__ __launch_bounds__(64) void subst_stage1_tiled_kernel(BDev p) {
     if (p.ctl->stop && !p.extract) return;
-    const int R1 = p.r1, m = p.m;
+    const int R1 = p.r1, m = M > 0 ? M : p.m;
     const int nbi = p.nb / R1;  // middle digits B_2..B_{m-1}
     const int nq = (nbi + 3) >> 2;
     const int row = blockIdx.x / nq, q = blockIdx.x - row * nq;
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(64) void subst_stage1_tiled_kernel(BDev p) {
     const ConstF64B Fu = (ConstF64B)(p.e_cdf + (size_t)u * p.ew);
     const ConstF64B Pu = (ConstF64B)(p.ppad + (size_t)u * p.ewp);
     const double* Gu = p.gpad + (size_t)u * p.ewp;
-    auto load = [&](int k) { return (double)Vr[b_path_offset(v, m, R1, k)]; };
+    auto load = [&](int k) { return (double)Vr[b_path_offset<M>(v, m, R1, k)]; };
 
     double acc[kBX];
     {
@@ -469,12 +471,17 @@ static hipError_t launch_b_t(const BDev& p, hipStream_t s) {
         const dim3 grid1((unsigned)(p.rows * ((p.nb / p.r1 + 3) / 4)));
         // paths of at most (m - 1)(R1 - 1) younger units: loaded whole when that fits
         const int kmax = (p.m - 1) * (p.r1 - 1);
-        if (kmax < 16)
-            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 16>), grid1, dim3(64), 0, s, p);
+        // the two- and three-digit shapes (m = 2, 3) have their own instances
+        if (kmax < 16 && p.m == 2)
+            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 16, 2>), grid1, dim3(64), 0, s, p);
+        else if (kmax < 32 && p.m == 3)
+            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 32, 3>), grid1, dim3(64), 0, s, p);
+        else if (kmax < 16)
+            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 16, 0>), grid1, dim3(64), 0, s, p);
         else if (kmax < 32)
-            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 32>), grid1, dim3(64), 0, s, p);
+            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 32, 0>), grid1, dim3(64), 0, s, p);
         else
-            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 0>), grid1, dim3(64), 0, s, p);
+            hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 0, 0>), grid1, dim3(64), 0, s, p);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (!EXTRACT) {  // policy extraction keeps the per-state kernel (best, second, arg)
