@@ -50,48 +50,49 @@ __device__ inline void block_reduce4(double& a, double& b, double& c, double& d,
     }
 }
 
-// Stopping rule applied to the reduced (max dv, min dv, max v', min v') of one sweep.
+// Stopping rule applied to the reduced (max dv, min dv, max v', min v') of one sweep,
+// on a copy of the control block that the caller writes back.
 // With FP32 storage (V = c + v) it also moves the centring: c <- gamma c + mu and
 // mu <- mu + mid(v').  Called by one thread after the whole sweep is reduced.
-__device__ inline void span_update(Ctl* ctl, double a0, double a1, double a2, double a3,
+__device__ inline void span_update(Ctl& ctl, double a0, double a1, double a2, double a3,
                                    int fp32, int fixed, double gamma) {
     double dmax = a0, dmin = a1;
     if (fp32) {
-        const double shift = (gamma - 1.0) * ctl->c + ctl->mu;
+        const double shift = (gamma - 1.0) * ctl.c + ctl.mu;
         dmax += shift;
         dmin += shift;
-        ctl->c = gamma * ctl->c + ctl->mu;
-        ctl->mu += 0.5 * (a2 + a3);
+        ctl.c = gamma * ctl.c + ctl.mu;
+        ctl.mu += 0.5 * (a2 + a3);
     }
     const double span = dmax - dmin;
     // stopping criterion: the span (rule 0) or max |V_new - V| (rule 1)
     // (the periodic rule, 2, is decided by its own kernels after this one)
-    const double crit = ctl->rule == 1   ? fmax(fabs(dmax), fabs(dmin))
-                        : ctl->rule == 2 ? INFINITY
+    const double crit = ctl.rule == 1   ? fmax(fabs(dmax), fabs(dmin))
+                        : ctl.rule == 2 ? INFINITY
                                          : span;
-    ctl->dmax = dmax;
-    ctl->dmin = dmin;
-    ctl->span = span;
-    ctl->sweeps += 1;
+    ctl.dmax = dmax;
+    ctl.dmin = dmin;
+    ctl.span = span;
+    ctl.sweeps += 1;
     if (fixed) return;
     if (fp32) {
         const double vabs = fmax(fabs(a2), fabs(a3));
-        ctl->vabs = vabs;
-        if (span < ctl->best_span * 0.999) {
-            ctl->best_span = span;
-            ctl->stall = 0;
+        ctl.vabs = vabs;
+        if (span < ctl.best_span * 0.999) {
+            ctl.best_span = span;
+            ctl.stall = 0;
         } else {
-            ctl->stall += 1;
+            ctl.stall += 1;
         }
         // the FP32 phase hands over to FP64 at the FP32 floor (span based for
         // either rule) or when the rule itself is met
-        if (crit < ctl->thr || span <= ctl->floor32 * vabs || ctl->stall >= 3) {
-            ctl->stop = 1;
-            ctl->stop_sweep = ctl->sweeps;
+        if (crit < ctl.thr || span <= ctl.floor32 * vabs || ctl.stall >= 3) {
+            ctl.stop = 1;
+            ctl.stop_sweep = ctl.sweeps;
         }
-    } else if (crit < ctl->thr) {
-        ctl->stop = 1;
-        ctl->stop_sweep = ctl->sweeps;
+    } else if (crit < ctl.thr) {
+        ctl.stop = 1;
+        ctl.stop_sweep = ctl.sweeps;
     }
 }
 

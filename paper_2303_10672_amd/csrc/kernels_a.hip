@@ -532,17 +532,39 @@ __global__ __launch_bounds__(1024) void span_kernel(Ctl* ctl, const double* part
                                                     int tiles, int fp32, int fixed,
                                                     double gamma) {
     __shared__ double red[4 * 16];
-    if (ctl->stop) return;
+    // the control block and up to four partials per thread are requested together,
+    // so the reduction waits for one memory round trip (partials are always
+    // readable; after the stop flag they are simply not used)
+    const Ctl cur = *ctl;
     double a0 = -DBL_MAX, a1 = DBL_MAX, a2 = -DBL_MAX, a3 = DBL_MAX;
-    for (int i = threadIdx.x; i < tiles; i += blockDim.x) {
-        a0 = fmax(a0, partials[4 * i + 0]);
-        a1 = fmin(a1, partials[4 * i + 1]);
-        a2 = fmax(a2, partials[4 * i + 2]);
-        a3 = fmin(a3, partials[4 * i + 3]);
+    const double2* pp = reinterpret_cast<const double2*>(partials);
+    const int bd = blockDim.x;
+    int i = threadIdx.x;
+    auto take = [&](double2 x, double2 y) {
+        a0 = fmax(a0, x.x);
+        a1 = fmin(a1, x.y);
+        a2 = fmax(a2, y.x);
+        a3 = fmin(a3, y.y);
+    };
+    // four loads per round, past the end repeating the last partial (max and min
+    // are unchanged by a repeat)
+    for (; i < tiles; i += 4 * bd) {
+        double2 x[4], y[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int t = min(i + k * bd, tiles - 1);
+            x[k] = pp[2 * t];
+            y[k] = pp[2 * t + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) take(x[k], y[k]);
     }
+    if (cur.stop) return;
     block_reduce4(a0, a1, a2, a3, red);
     if (threadIdx.x != 0) return;
-    span_update(ctl, a0, a1, a2, a3, fp32, fixed, gamma);
+    Ctl next = cur;
+    span_update(next, a0, a1, a2, a3, fp32, fixed, gamma);
+    *ctl = next;
 }
 
 __global__ void to_f64_kernel(const float* v32, double* v64, const Ctl* ctl, int64_t n) {
