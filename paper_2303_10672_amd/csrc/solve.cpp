@@ -262,9 +262,11 @@ pvi_status run_phase(pvi_mdp* p, const Phase& ph, hipStream_t s, PhaseOut& out) 
     int prev_sweeps = 0, last_ckpt = 0;
     const int limit = ph.fixed > 0 ? ph.fixed : ph.max_sweeps;
     if (ph.time && (int)d.ev.size() < 2 * ph.kmax) {
+        // timing only: no system-scope fence when they complete (the control block
+        // reaches the host through its own copy and stream synchronisation)
         for (int i = (int)d.ev.size(); i < 2 * ph.kmax; ++i) {
             hipEvent_t e;
-            PVI_HIP(hipEventCreate(&e));
+            PVI_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
             d.ev.push_back(e);
         }
     }
@@ -446,7 +448,7 @@ pvi_status pvi::solve_impl(pvi_mdp* p, const pvi_solve_opts* opts_in, pvi_result
     auto& d = p->dev;
     hipStream_t s = o->stream ? (hipStream_t)o->stream : d.own;
     for (auto& e : d.span_ev)
-        if (!e) PVI_HIP(hipEventCreate(&e));
+        if (!e) PVI_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     PVI_HIP(hipEventRecord(d.span_ev[0], s));
     const double g = p->d.gamma;
     // span rule: eps (1 - gamma)/gamma; undiscounted (gamma = 1), span < eps as in
