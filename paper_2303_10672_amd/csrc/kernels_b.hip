@@ -342,13 +342,15 @@ __global__ __launch_bounds__(64) void subst_stage1_tiled_kernel(BDev p) {
 // subst_stage2_kernel (d0 ascending), so the values are the same; the maximum over
 // a1 is a 16-lane transpose-reduction, over a0 one over four lane groups and the
 // four wavefronts.
-template <typename VT, int J>
+template <typename VT, int J, bool EXTRACT>
 __global__ __launch_bounds__(256) void subst_stage2_tiled_kernel(BDev p) {
     constexpr int TS = kBX + 2;  // row stride of the Q tile (16-byte rows, spread banks)
     __shared__ int32_t roff[kBX * J];
     __shared__ __align__(16) double qt[kBX * kBX * TS];  // [a0][a1][x0]
     __shared__ double red[4 * kBX];
-    if (p.ctl->stop) return;
+    __shared__ double red2[EXTRACT ? 4 * kBX : 1];
+    __shared__ int32_t reda[EXTRACT ? 4 * kBX : 1];
+    if (!EXTRACT && p.ctl->stop) return;
     const int grp = xcd_remap(blockIdx.x, gridDim.x);
     const int ib = grp / p.nw, wi = grp - ib * p.nw;
     const int R0 = p.r0, R1 = p.r1, m = p.m, tid = threadIdx.x;
@@ -408,9 +410,11 @@ __global__ __launch_bounds__(256) void subst_stage2_tiled_kernel(BDev p) {
         for (int x0 = 0; x0 < kBX; ++x0) acc[x0] = fma(pr, zr[d0 > x0 ? d0 - x0 : 0], acc[x0]);
     }
     // lanes past the orders repeat the Q values of a real action, which leaves every
-    // maximum unchanged; entries x0 >= R0 are not states and are never stored.  The
-    // Q values go to LDS as [a0][a1][x0]; thread (a0, x0) then takes the maximum over
+    // maximum unchanged (policy extraction, which also needs the second best, gives
+    // them -DBL_MAX); entries x0 >= R0 are not states and are never stored.  The Q
+    // values go to LDS as [a0][a1][x0]; thread (a0, x0) then takes the maximum over
     // a1, and over a0 two lane exchanges and the four wavefronts follow.
+    const bool real = wv * 4 + ((tid >> 4) & 3) < R0 && l16 < R1;
     {
         double2* row = reinterpret_cast<double2*>(qt + (size_t)(tid >> 4) * kBX * TS + l16 * TS);
 #pragma unroll
@@ -422,10 +426,51 @@ __global__ __launch_bounds__(256) void subst_stage2_tiled_kernel(BDev p) {
                                   fma(-p.cvar0, (double)a0,
                                       p.rexp0[min(x0 + 1, R0 - 1) + held + a0])) +
                               acc[x0 + 1];
-            row[x0 / 2] = make_double2(q0, q1);
+            row[x0 / 2] = EXTRACT && !real ? make_double2(-DBL_MAX, -DBL_MAX) : make_double2(q0, q1);
         }
     }
     __syncthreads();
+    if constexpr (EXTRACT) {
+        // (best, second, argmax) with ties to the lowest action a0 R1 + a1, as the
+        // per-state kernel takes them
+        const int a0s = tid >> 4;
+        const double* col = qt + (size_t)a0s * kBX * TS + l16;
+        double best = -DBL_MAX, second = -DBL_MAX;
+        int arg = 0x7fffffff;
+#pragma unroll
+        for (int i = 0; i < kBX; ++i) {
+            const double q = col[i * TS];
+            if (q > best) {
+                second = best;
+                best = q;
+                arg = a0s * R1 + i;
+            } else if (q > second) {
+                second = q;
+            }
+        }
+        for (int o = 16; o <= 32; o <<= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const double os = __shfl_xor(second, o, 64);
+            const int oa = __shfl_xor(arg, o, 64);
+            merge_best(best, second, arg, ob, os, oa);
+        }
+        if ((tid & 63) < kBX) {
+            red[wv * kBX + l16] = best;
+            red2[wv * kBX + l16] = second;
+            reda[wv * kBX + l16] = arg;
+        }
+        __syncthreads();
+        if (tid < R0) {
+            double b = red[tid], s2 = red2[tid];
+            int a = reda[tid];
+            for (int w2 = 1; w2 < 4; ++w2)
+                merge_best(b, s2, a, red[w2 * kBX + tid], red2[w2 * kBX + tid], reda[w2 * kBX + tid]);
+            const int64_t st = (int64_t)(tid + R0 * wi) * p.nb + ib;
+            p.pi[st] = a;
+            p.gap[st] = b - s2;
+        }
+        return;
+    }
     double best;
     {
         const double* col = qt + (size_t)(tid >> 4) * kBX * TS + l16;
@@ -484,22 +529,23 @@ static hipError_t launch_b_t(const BDev& p, hipStream_t s) {
             hipLaunchKernelGGL((subst_stage1_tiled_kernel<VT, 0, 0>), grid1, dim3(64), 0, s, p);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (!EXTRACT) {  // policy extraction keeps the per-state kernel (best, second, arg)
-            const dim3 grid((unsigned)(p.nb * p.nw));
-            // the fewest demand values J >= d0max + 1 of the compiled widths
-            if (p.d0max < 8)
-                hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 8>), grid, dim3(256), 0, s, p);
-            else if (p.d0max < 16)
-                hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 16>), grid, dim3(256), 0, s, p);
-            else if (p.d0max == 20)  // demand folded at 20, the paper's truncation
-                hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 21>), grid, dim3(256), 0, s, p);
-            else if (p.d0max < 24)
-                hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 24>), grid, dim3(256), 0, s, p);
-            else
-                hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, PVI_B_JMAX>), grid, dim3(256), 0,
-                                   s, p);
-            return hipGetLastError();
-        }
+        const dim3 grid((unsigned)(p.nb * p.nw));
+        // the fewest demand values J >= d0max + 1 of the compiled widths
+        if (p.d0max < 8)
+            hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 8, EXTRACT>), grid, dim3(256), 0, s, p);
+        else if (p.d0max < 16)
+            hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 16, EXTRACT>), grid, dim3(256), 0, s,
+                               p);
+        else if (p.d0max == 20)  // demand folded at 20, the paper's truncation
+            hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 21, EXTRACT>), grid, dim3(256), 0, s,
+                               p);
+        else if (p.d0max < 24)
+            hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, 24, EXTRACT>), grid, dim3(256), 0, s,
+                               p);
+        else
+            hipLaunchKernelGGL((subst_stage2_tiled_kernel<VT, PVI_B_JMAX, EXTRACT>), grid, dim3(256),
+                               0, s, p);
+        return hipGetLastError();
     } else {
         const int64_t n1 = (int64_t)p.rows * p.nb * p.r1;
         hipLaunchKernelGGL((subst_stage1_kernel<VT>), dim3((unsigned)((n1 + 255) / 256)), dim3(256),
