@@ -65,9 +65,9 @@
  *  - Scenario B as the paper runs it (lead time 1) with 16 orders of each product
  *    sweeps with a final kernel over lanes of b's orders; PVI_B1_LANES=0 keeps the
  *    kernel over lanes of a's stock (for tests: both give the same values).
- *  - Scenario B (two products, L = 0) sweeps with tiled stage kernels when a_max[0]
- *    <= 15 and d_max[0] <= 31; PVI_B_TILED=0, read by mdp_create, keeps the per-cell
- *    kernels (for tests: both give the same values).
+ *  - Scenario B (two products, L = 0) runs tiled stage kernels (sweeps and policy
+ *    extraction) when a_max[0] <= 15 and d_max[0] <= 31; PVI_B_TILED=0, read by
+ *    mdp_create, keeps the per-cell kernels (for tests: both give the same values).
  */
 #ifndef PVI_H
 #define PVI_H
